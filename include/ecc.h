@@ -1,0 +1,137 @@
+/*
+ * ecc.h -- C ABI of the MI355X (gfx950) library that computes the Euler
+ * characteristic curve (ECC) of 2D and 3D grayscale images.
+ *
+ * Method (Wang, Wagner, Chen, "GPU Computation of the Euler Characteristic Curve
+ * for Imaging Data", SoCG 2022):
+ *   - Sec. 2.1: the image is a d-dimensional array of values; thresholding at t
+ *     keeps the part of a cubical complex with filtration value <= t.
+ *   - Eq. (1):  ECC_i = chi(K_{<=t_i}) = sum_j (-1)^j c_j(K_{<=t_i}).
+ *   - Sec. 2.3: VCEC_i = ECC_i - ECC_{i-1}; every cell is credited, with sign
+ *     (-1)^dim, to the voxel that completes it (Algorithm 1), and the ECC is the
+ *     prefix sum of the VCEC.
+ * The curve is indexed by integer bins: out[i] = chi of the cells whose value
+ * falls in bins 0..i (empty bins included, so out has exactly nbins entries).
+ *
+ * Two filtrations (ecc_construction):
+ *   ECC_VERTEX (default) - voxels are the vertices of the complex; a cell (a block
+ *                          of 2^k voxels) takes the maximum value of its vertices;
+ *   ECC_TOP              - voxels are the top-dimensional cells, as in the paper's
+ *                          Sec. 2.1; a lower cell takes the minimum value of the
+ *                          voxels that contain it.
+ *
+ * Binning of values into [0, nbins):
+ *   integer data (ECC_U8, ECC_U16), integer range [lo, hi]:
+ *       bin = ((clamp(v, lo, hi) - lo) * nbins) / (hi - lo + 1)       (exact)
+ *   float data (ECC_F32), range [lo, hi]:
+ *       NaN -> nbins-1;  hi == lo -> (x > hi ? nbins-1 : 0);  otherwise
+ *       bin = clamp(floor(((double)x - lo) * s), 0, nbins-1) with
+ *       s = (double)nbins / (hi - lo); every operation is one IEEE double
+ *       rounding, no fused multiply-add.
+ *   Range modes: ECC_RANGE_DEFAULT = [0,255] for u8 and AUTO otherwise;
+ *   ECC_RANGE_AUTO = [min, max] of the image, computed on the device (finite
+ *   values only for f32; [0,0] when there are none); ECC_RANGE_EXPLICIT = [lo, hi]
+ *   from the caller (integers inside the type's range for u8/u16, finite for f32).
+ *
+ * Conventions shared by every entry point:
+ *   - Images are DEVICE pointers, contiguous, row-major, dims[0] slowest.  Any
+ *     alignment is accepted.  ndim is 2 or 3; every dim is >= 1.
+ *   - `out` is a DEVICE pointer to nbins int64 values, overwritten (not
+ *     accumulated) with the ECC.  1 <= nbins <= 65535.
+ *   - Every call validates all of its arguments on the host before anything is
+ *     enqueued; a call that returns an error has enqueued nothing.  Successful
+ *     calls are asynchronous on `hip_stream` (a hipStream_t; NULL = the null
+ *     stream); results are valid once that stream has completed the work.
+ *   - The caller owns images and outputs and keeps them alive until the stream
+ *     has finished.  The context owns its device scratch memory, which it grows
+ *     with hipMalloc when a call needs more than it holds.
+ *   - A context is used by one host thread at a time.  Calls on one context that
+ *     are enqueued on different streams must not overlap in time (they share the
+ *     context's scratch memory).
+ *   - No C++ exception crosses this interface; ecc_last_error() gives the text of
+ *     the last error of a context.
+ */
+#ifndef ECC_H
+#define ECC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ecc_ctx ecc_ctx;
+
+typedef enum {
+    ECC_OK = 0,
+    ECC_ERR_INVALID_ARG = 1,   /* a null pointer, a bad size, range or enum value */
+    ECC_ERR_UNSUPPORTED = 2,   /* a valid request this build cannot serve */
+    ECC_ERR_OUT_OF_MEMORY = 3, /* device scratch memory could not be allocated */
+    ECC_ERR_DEVICE = 4         /* a HIP runtime call failed */
+} ecc_status;
+
+typedef enum { ECC_U8 = 0, ECC_U16 = 1, ECC_F32 = 2 } ecc_dtype;
+
+typedef enum { ECC_VERTEX = 0, ECC_TOP = 1 } ecc_construction;
+
+typedef enum {
+    ECC_RANGE_DEFAULT = 0,
+    ECC_RANGE_EXPLICIT = 1,
+    ECC_RANGE_AUTO = 2
+} ecc_range_mode;
+
+/* One image of a call.  Enum-valued fields are int32_t for a fixed layout. */
+typedef struct {
+    const void* data;    /* device pointer to the voxels */
+    int32_t ndim;        /* 2 or 3 */
+    int32_t dtype;       /* ecc_dtype */
+    int64_t dims[3];     /* dims[0] slowest; entries beyond ndim are ignored */
+    int32_t range_mode;  /* ecc_range_mode */
+    int32_t reserved;    /* must be 0 */
+    double lo, hi;       /* used with ECC_RANGE_EXPLICIT only */
+    int64_t* out;        /* device pointer, nbins int64, overwritten with the ECC */
+} ecc_image;
+
+/* Creates a context on HIP device `device` for filtration `construction`
+ * (ecc_construction).  Sec. 2.1 defines the filtration; the vertex variant is the
+ * library's default reading.  On success *ctx owns no device memory yet.
+ * Errors: ECC_ERR_INVALID_ARG (ctx null, bad enum), ECC_ERR_DEVICE (no such
+ * device), ECC_ERR_OUT_OF_MEMORY (host allocation failed). */
+ecc_status ecc_create(ecc_ctx** ctx, int32_t device, int32_t construction);
+
+/* Releases the context and its device memory.  Waits for nothing: the caller
+ * must have synchronized every stream the context enqueued work on.  A null
+ * ctx is accepted and ignored. */
+ecc_status ecc_destroy(ecc_ctx* ctx);
+
+/* Text of the last error recorded on `ctx` ("" if none); valid until the next
+ * call on the same context.  A null ctx returns the last ecc_create error. */
+const char* ecc_last_error(const ecc_ctx* ctx);
+
+/* ECC of one image with the default range (Eq. (1), Sec. 2.3).
+ * image: device pointer; ndim 2|3; dims: HOST pointer to ndim int64;
+ * dtype: ecc_dtype; out: device pointer to nbins int64 (overwritten).
+ * Errors: ECC_ERR_INVALID_ARG for any bad argument (nothing enqueued),
+ * ECC_ERR_OUT_OF_MEMORY, ECC_ERR_DEVICE. */
+ecc_status ecc_compute(ecc_ctx* ctx, const void* image, int32_t ndim, const int64_t* dims,
+                       int32_t dtype, int32_t nbins, int64_t* out, void* hip_stream);
+
+/* ECC of one image described by `img` (HOST pointer to the descriptor; its data
+ * and out fields are device pointers).  Same semantics and errors as ecc_compute,
+ * plus the range selection of the descriptor. */
+ecc_status ecc_compute_ex(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, void* hip_stream);
+
+/* ECC of `count` images in one persistent launch.  imgs: HOST array of `count`
+ * descriptors; images may differ in ndim, dtype, size and range mode but share
+ * nbins and the context's filtration; each writes its own `out`.  The result of
+ * every image is identical to what ecc_compute_ex returns for it alone.
+ * count == 0 is a no-op.  Errors as above; the index of the first bad descriptor
+ * is named in ecc_last_error. */
+ecc_status ecc_compute_batch(ecc_ctx* ctx, const ecc_image* imgs, int32_t count, int32_t nbins,
+                             void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ECC_H */

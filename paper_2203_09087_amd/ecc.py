@@ -1,0 +1,206 @@
+"""Python binding of the C ABI in ``include/ecc.h`` (argument marshalling only).
+
+Every step of the computation runs in the HIP library ``libecc_hip.so``; this
+module only converts Python/torch arguments to the plain pointers and sizes of
+the C entry points, which it exposes under the same names (``ecc_create``,
+``ecc_compute``, ``ecc_compute_ex``, ``ecc_compute_batch``, ``ecc_destroy``,
+``ecc_last_error``).  There is no fallback: if the library is missing, loading
+fails with an error.
+
+``Context`` is a convenience wrapper taking torch tensors that live on the GPU:
+the image tensor's memory is passed as the device pointer, the output is an
+int64 tensor of ``nbins`` values, and work is enqueued on the current torch
+stream unless another is given.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libecc_hip.so")
+
+ECC_OK, ECC_ERR_INVALID_ARG, ECC_ERR_UNSUPPORTED, ECC_ERR_OUT_OF_MEMORY, ECC_ERR_DEVICE = range(5)
+ECC_U8, ECC_U16, ECC_F32 = 0, 1, 2
+ECC_VERTEX, ECC_TOP = 0, 1
+ECC_RANGE_DEFAULT, ECC_RANGE_EXPLICIT, ECC_RANGE_AUTO = 0, 1, 2
+
+STATUS_NAMES = {0: "ECC_OK", 1: "ECC_ERR_INVALID_ARG", 2: "ECC_ERR_UNSUPPORTED",
+                3: "ECC_ERR_OUT_OF_MEMORY", 4: "ECC_ERR_DEVICE"}
+CONSTRUCTIONS = {"vertex": ECC_VERTEX, "top": ECC_TOP}
+
+# Symbols declared in include/ecc.h.
+EXPORTED = ("ecc_create", "ecc_destroy", "ecc_last_error", "ecc_compute", "ecc_compute_ex",
+            "ecc_compute_batch")
+
+
+class ecc_image(ctypes.Structure):
+    """Mirror of ``ecc_image`` in include/ecc.h."""
+    _fields_ = [
+        ("data", ctypes.c_void_p),
+        ("ndim", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("dims", ctypes.c_int64 * 3),
+        ("range_mode", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("lo", ctypes.c_double),
+        ("hi", ctypes.c_double),
+        ("out", ctypes.c_void_p),
+    ]
+
+
+class EccError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libecc_hip.so and declares the C signatures.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            f"{path} is not built; run __graft_entry__.build() (hipcc --offload-arch=gfx950)")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
+    lib.ecc_create.argtypes = [ctypes.POINTER(vp), i32, i32]
+    lib.ecc_create.restype = ctypes.c_int
+    lib.ecc_destroy.argtypes = [vp]
+    lib.ecc_destroy.restype = ctypes.c_int
+    lib.ecc_last_error.argtypes = [vp]
+    lib.ecc_last_error.restype = ctypes.c_char_p
+    lib.ecc_compute.argtypes = [vp, vp, i32, i64p, i32, i32, vp, vp]
+    lib.ecc_compute.restype = ctypes.c_int
+    lib.ecc_compute_ex.argtypes = [vp, ctypes.POINTER(ecc_image), i32, vp]
+    lib.ecc_compute_ex.restype = ctypes.c_int
+    lib.ecc_compute_batch.argtypes = [vp, ctypes.POINTER(ecc_image), i32, i32, vp]
+    lib.ecc_compute_batch.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+# ----------------------------------------------------------- C entry points
+
+def ecc_create(device: int = 0, construction: int = ECC_VERTEX) -> int:
+    lib = load_library()
+    h = ctypes.c_void_p()
+    st = lib.ecc_create(ctypes.byref(h), int(device), int(construction))
+    if st != ECC_OK:
+        raise EccError(st, lib.ecc_last_error(None).decode())
+    return h.value
+
+
+def ecc_destroy(ctx: int) -> int:
+    return load_library().ecc_destroy(ctx)
+
+
+def ecc_last_error(ctx) -> str:
+    return load_library().ecc_last_error(ctx).decode()
+
+
+def ecc_compute(ctx: int, image_ptr: int, ndim: int, dims, dtype: int, nbins: int, out_ptr: int,
+                stream: int = 0) -> int:
+    dims_arr = (ctypes.c_int64 * max(1, len(dims)))(*[int(d) for d in dims])
+    return load_library().ecc_compute(ctx, image_ptr, int(ndim), dims_arr, int(dtype), int(nbins),
+                                      out_ptr, stream)
+
+
+def ecc_compute_ex(ctx: int, img: ecc_image, nbins: int, stream: int = 0) -> int:
+    return load_library().ecc_compute_ex(ctx, ctypes.byref(img), int(nbins), stream)
+
+
+def ecc_compute_batch(ctx: int, imgs, nbins: int, stream: int = 0) -> int:
+    arr = (ecc_image * max(1, len(imgs)))(*imgs)
+    return load_library().ecc_compute_batch(ctx, arr, len(imgs), int(nbins), stream)
+
+
+# ------------------------------------------------------ torch convenience
+
+def _dtype_code(t) -> int:
+    import torch
+    codes = {torch.uint8: ECC_U8, torch.uint16: ECC_U16, torch.int16: ECC_U16,
+             torch.float32: ECC_F32}
+    if t.dtype not in codes:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return codes[t.dtype]
+
+
+def make_image(t, out, value_range=None) -> ecc_image:
+    """Descriptor for a contiguous device tensor ``t`` and int64 output ``out``.
+
+    t: uint8, uint16 (or int16 holding the bits of uint16 data) or float32.
+    value_range: None (default range), "auto", or (lo, hi) (explicit)."""
+    if not t.is_contiguous():
+        raise ValueError("image tensor must be contiguous")
+    im = ecc_image()
+    im.data = t.data_ptr()
+    im.ndim = t.dim()
+    im.dtype = _dtype_code(t)
+    for i, s in enumerate(t.shape[:3]):
+        im.dims[i] = int(s)
+    if value_range is None:
+        im.range_mode = ECC_RANGE_DEFAULT
+    elif isinstance(value_range, str):
+        if value_range != "auto":
+            raise ValueError(f"unknown range {value_range!r}")
+        im.range_mode = ECC_RANGE_AUTO
+    else:
+        im.range_mode = ECC_RANGE_EXPLICIT
+        im.lo, im.hi = float(value_range[0]), float(value_range[1])
+    im.out = out.data_ptr()
+    return im
+
+
+class Context:
+    """Owns an ``ecc_ctx`` on one device for one filtration ("vertex" or "top")."""
+
+    def __init__(self, device: int = 0, construction: str = "vertex"):
+        self.device = int(device)
+        self.construction = construction
+        self.handle = ecc_create(self.device, CONSTRUCTIONS[construction])
+
+    def close(self):
+        if self.handle:
+            ecc_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self, stream):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+    def _check(self, st):
+        if st != ECC_OK:
+            raise EccError(st, ecc_last_error(self.handle))
+
+    def compute(self, image, nbins: int, value_range=None, out=None, stream=None):
+        """ECC (int64 tensor of nbins) of a device tensor, enqueued on `stream`."""
+        import torch
+        if out is None:
+            out = torch.empty(int(nbins), dtype=torch.int64, device=image.device)
+        im = make_image(image, out, value_range)
+        self._check(ecc_compute_ex(self.handle, im, nbins, self._stream(stream)))
+        return out
+
+    def compute_batch(self, images, nbins: int, value_ranges=None, outs=None, stream=None):
+        """ECCs of a list of device tensors in one call; returns the list of outputs."""
+        import torch
+        if outs is None:
+            outs = [torch.empty(int(nbins), dtype=torch.int64, device=t.device) for t in images]
+        if value_ranges is None:
+            value_ranges = [None] * len(images)
+        descs = [make_image(t, o, r) for t, o, r in zip(images, outs, value_ranges)]
+        self._check(ecc_compute_batch(self.handle, descs, nbins, self._stream(stream)))
+        return outs

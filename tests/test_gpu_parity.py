@@ -1,0 +1,240 @@
+"""GPU parity: the HIP library against the oracle, bit for bit.
+
+Everything here is exact integer work (bins are decided in the same IEEE double
+arithmetic on both sides), so the bar is equality of every output value.  The
+cases span several tiles with ragged tails, size-1 axes, images with few
+distinct values (many ties, which exercise the tie-break), every dtype, both
+filtrations, AUTO and explicit ranges, bin counts from 1 to 65535 (several LDS
+bin windows), float specials, and the full-size workloads.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CONS = ("vertex", "top")
+
+
+@pytest.fixture(scope="module")
+def ctxs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_09087_amd import ecc
+    c = {k: ecc.Context(0, k) for k in CONS}
+    yield c
+    for v in c.values():
+        v.close()
+
+
+def to_dev(a):
+    if a.dtype == np.uint16:
+        return torch.from_numpy(np.ascontiguousarray(a).view(np.int16)).cuda()
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def say(*args):
+    print(*args, flush=True, file=sys.stderr)
+
+
+def check(ctx, oracle_mod, img, nbins, cons, rng=None, threads=8):
+    say(f"case: {cons} shape={img.shape} dtype={img.dtype} nbins={nbins} range={rng}")
+    got = ctx.compute(to_dev(img), nbins, value_range=rng)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    want = oracle_mod.ecc(img, nbins, cons, value_range=rng, threads=threads)
+    if not np.array_equal(got, want):
+        bad = np.nonzero(got != want)[0]
+        raise AssertionError(f"{cons} {img.shape} {img.dtype} nbins={nbins} range={rng}: "
+                             f"{bad.size} bins differ, first {bad[0]}: {got[bad[0]]} != {want[bad[0]]}")
+
+
+SHAPES = [(1, 1), (1, 7), (7, 1), (5, 5), (33, 65), (64, 64), (65, 63), (97, 130),
+          (1, 1, 1), (1, 1, 5), (3, 1, 4), (9, 8, 33), (10, 9, 31), (17, 17, 17), (8, 8, 64),
+          (2, 40, 70)]
+
+
+def _image(rng, shape, dtype, levels):
+    if dtype == np.float32:
+        return (rng.integers(0, levels, size=shape) * 0.37 - 3.0).astype(np.float32)
+    top = 256 if dtype == np.uint8 else 65536
+    return rng.integers(0, min(levels, top), size=shape).astype(dtype)
+
+
+@pytest.mark.parametrize("cons", CONS)
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16, np.float32])
+def test_shapes_dtypes(ctxs, oracle_mod, cons, dtype):
+    rng = np.random.default_rng(100 + int(np.dtype(dtype).itemsize) + (7 if cons == "top" else 0))
+    for shape in SHAPES:
+        for levels in (3, 1000):
+            img = _image(rng, shape, dtype, levels)
+            if dtype == np.uint8:
+                check(ctxs[cons], oracle_mod, img, 256, cons)
+                check(ctxs[cons], oracle_mod, img, 7, cons, rng=(0, 255))
+            elif dtype == np.uint16:
+                check(ctxs[cons], oracle_mod, img, 4096, cons, rng="auto")
+                check(ctxs[cons], oracle_mod, img, 100, cons, rng=(5, 700))
+            else:
+                check(ctxs[cons], oracle_mod, img, 4096, cons, rng="auto")
+                check(ctxs[cons], oracle_mod, img, 100, cons, rng=(-2.0, 30.0))
+
+
+@pytest.mark.parametrize("cons", CONS)
+def test_bin_counts(ctxs, oracle_mod, cons):
+    rng = np.random.default_rng(200)
+    img2 = rng.integers(0, 65536, size=(70, 90)).astype(np.uint16)
+    img3 = rng.integers(0, 65536, size=(12, 20, 40)).astype(np.uint16)
+    for nbins in (1, 2, 255, 256, 4096, 8192, 8193, 20000, 65535):
+        check(ctxs[cons], oracle_mod, img2, nbins, cons, rng="auto")
+        check(ctxs[cons], oracle_mod, img3, nbins, cons, rng=(0, 65535))
+
+
+@pytest.mark.parametrize("cons", CONS)
+def test_float_specials(ctxs, oracle_mod, cons):
+    rng = np.random.default_rng(300)
+    img = rng.standard_normal((30, 41)).astype(np.float32)
+    img.flat[rng.choice(img.size, 40, replace=False)] = np.nan
+    img.flat[rng.choice(img.size, 10, replace=False)] = np.inf
+    img.flat[rng.choice(img.size, 10, replace=False)] = -np.inf
+    img.flat[rng.choice(img.size, 10, replace=False)] = -0.0
+    img.flat[rng.choice(img.size, 10, replace=False)] = 0.0
+    for r in ("auto", (-1.0, 1.0), (0.5, 0.5)):
+        check(ctxs[cons], oracle_mod, img, 64, cons, rng=r)
+    allnan = np.full((5, 6, 7), np.nan, dtype=np.float32)
+    check(ctxs[cons], oracle_mod, allnan, 16, cons, rng="auto")
+    flat = np.full((9, 3), 2.5, dtype=np.float32)
+    check(ctxs[cons], oracle_mod, flat, 16, cons, rng="auto")
+
+
+@pytest.mark.parametrize("cons", CONS)
+def test_workload_small_2d(ctxs, oracle_mod, cons):
+    """256 x 256 uint8 uniform noise, 256 bins (one per gray level)."""
+    from paper_2203_09087_amd import synth
+    check(ctxs[cons], oracle_mod, synth.uniform_u8((256, 256), seed=1), 256, cons)
+
+
+@pytest.mark.parametrize("cons", CONS)
+def test_workload_smoothed_3d(ctxs, oracle_mod, cons):
+    """256^3 uint8 smoothed noise (sigma 2), 256 bins."""
+    from paper_2203_09087_amd import synth
+    img = synth.smoothed_noise_u8((256, 256, 256), sigma=2.0, seed=2)
+    check(ctxs[cons], oracle_mod, img, 256, cons, threads=16)
+
+
+@pytest.fixture(scope="module")
+def grf3d():
+    from paper_2203_09087_amd import synth
+    return synth.grf((512, 512, 512), seed=3)
+
+
+@pytest.mark.parametrize("cons", CONS)
+def test_workload_grf_512_cubed(ctxs, oracle_mod, grf3d, cons):
+    """512^3 float32 GRF (k^-3), 4096 bins over [min, max], explicit and AUTO."""
+    lo, hi = float(grf3d.min()), float(grf3d.max())
+    check(ctxs[cons], oracle_mod, grf3d, 4096, cons, rng=(lo, hi), threads=16)
+    if cons == "vertex":
+        check(ctxs[cons], oracle_mod, grf3d, 4096, cons, rng="auto", threads=16)
+
+
+def test_workload_grf_16384_squared(ctxs, oracle_mod):
+    """16384^2 uint16 GRF quantized to 4096 levels, 4096 bins over [min, max]."""
+    from paper_2203_09087_amd import synth
+    img = synth.quantize_u16(synth.grf((16384, 16384), seed=4), 4096)
+    check(ctxs["vertex"], oracle_mod, img, 4096, "vertex", rng="auto", threads=16)
+
+
+@pytest.mark.parametrize("cons", CONS)
+def test_batch_matches_single_and_oracle(ctxs, oracle_mod, cons):
+    rng = np.random.default_rng(400)
+    imgs, ranges = [], []
+    for i in range(24):
+        d = 2 if i % 3 else 3
+        shape = tuple(int(s) for s in rng.integers(1, 90 if d == 2 else 24, size=d))
+        kind = i % 4
+        if kind == 0:
+            imgs.append(rng.integers(0, 256, size=shape).astype(np.uint8)); ranges.append(None)
+        elif kind == 1:
+            imgs.append(rng.integers(0, 300, size=shape).astype(np.uint16)); ranges.append("auto")
+        elif kind == 2:
+            imgs.append(rng.standard_normal(shape).astype(np.float32)); ranges.append((-1.5, 1.5))
+        else:
+            imgs.append(rng.standard_normal(shape).astype(np.float32)); ranges.append("auto")
+    say(f"case: batch of {len(imgs)} ({cons})")
+    dev = [to_dev(a) for a in imgs]
+    outs = ctxs[cons].compute_batch(dev, 512, value_ranges=ranges)
+    torch.cuda.synchronize()
+    for a, d, r, o in zip(imgs, dev, ranges, outs):
+        single = ctxs[cons].compute(d, 512, value_range=r)
+        torch.cuda.synchronize()
+        want = oracle_mod.ecc(a, 512, cons, value_range=r)
+        assert np.array_equal(o.cpu().numpy(), want), (a.shape, a.dtype, r)
+        assert np.array_equal(single.cpu().numpy(), want), (a.shape, a.dtype, r)
+    assert ctxs[cons].compute_batch([], 512) == []
+
+
+def test_repeat_runs_are_identical(ctxs):
+    from paper_2203_09087_amd import synth
+    img = to_dev(synth.grf((64, 80, 96), seed=9))
+    say("case: determinism 64x80x96 f32")
+    ref = ctxs["vertex"].compute(img, 4096, value_range="auto").cpu().numpy()
+    for _ in range(20):
+        got = ctxs["vertex"].compute(img, 4096, value_range="auto").cpu().numpy()
+        assert np.array_equal(got, ref)
+
+
+def test_non_default_stream(ctxs, oracle_mod):
+    from paper_2203_09087_amd import synth
+    a = synth.uniform_u8((300, 200), seed=12)
+    say("case: side stream")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        d = to_dev(a)
+        out = ctxs["top"].compute(d, 256)
+    s.synchronize()
+    assert np.array_equal(out.cpu().numpy(), oracle_mod.ecc(a, 256, "top"))
+
+
+def test_invalid_arguments_enqueue_nothing(ctxs):
+    """Every bad argument returns ECC_ERR_INVALID_ARG and leaves the output untouched."""
+    from paper_2203_09087_amd import ecc
+    h = ctxs["vertex"].handle
+    img = torch.zeros((8, 8), dtype=torch.uint8, device="cuda")
+    out = torch.full((16,), -7, dtype=torch.int64, device="cuda")
+    good = ecc.make_image(img, out)
+
+    def variant(**kw):
+        im = ecc.make_image(img, out)
+        for k, v in kw.items():
+            if k == "dims":
+                for i, x in enumerate(v):
+                    im.dims[i] = x
+            else:
+                setattr(im, k, v)
+        return im
+
+    bad = [variant(data=None), variant(out=None), variant(ndim=1), variant(ndim=4),
+           variant(dtype=7), variant(range_mode=9), variant(reserved=1), variant(dims=(0, 8)),
+           variant(dims=(8, -1)), variant(range_mode=ecc.ECC_RANGE_EXPLICIT, lo=3.0, hi=2.0),
+           variant(range_mode=ecc.ECC_RANGE_EXPLICIT, lo=0.5, hi=2.0),
+           variant(range_mode=ecc.ECC_RANGE_EXPLICIT, lo=0.0, hi=256.0)]
+    for im in bad:
+        assert ecc.ecc_compute_ex(h, im, 16) == ecc.ECC_ERR_INVALID_ARG
+        assert ecc.ecc_last_error(h)
+    for nb in (0, -1, 65536):
+        assert ecc.ecc_compute_ex(h, good, nb) == ecc.ECC_ERR_INVALID_ARG
+    assert ecc.ecc_compute(h, img.data_ptr(), 2, (8, 8), 0, 16, 0) == ecc.ECC_ERR_INVALID_ARG
+    assert ecc.ecc_compute(h, img.data_ptr(), 5, (8, 8), 0, 16, out.data_ptr()) == ecc.ECC_ERR_INVALID_ARG
+    f = torch.zeros((4, 4), dtype=torch.float32, device="cuda")
+    fim = ecc.make_image(f, out, (0.0, float("inf")))
+    assert ecc.ecc_compute_ex(h, fim, 16) == ecc.ECC_ERR_INVALID_ARG
+    # batch: the bad descriptor is named and nothing runs for the good ones either
+    st = ecc.ecc_compute_batch(h, [good, variant(ndim=5)], 16)
+    assert st == ecc.ECC_ERR_INVALID_ARG and "image 1" in ecc.ecc_last_error(h)
+    torch.cuda.synchronize()
+    assert (out.cpu() == -7).all()
+    assert ecc.ecc_compute_ex(h, good, 16) == ecc.ECC_OK
+    torch.cuda.synchronize()
+    assert out.cpu().tolist() == [1] * 16
