@@ -12,7 +12,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libecc_hip.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("ecc_api.hip", "ecc_kernels.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("ecc_api.hip", "ecc_kernels.hip", "ecc_batch.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -30,15 +30,17 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    """Compiles every HIP source into LIB (always recompiles)."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, *SOURCES, "-o", tmp]
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compiles every HIP source into `out` (always recompiles).
+
+    defines: extra preprocessor definitions ("NAME=VALUE"), used for tuning builds."""
+    tmp = out + ".tmp"
+    cmd = [hipcc(), *HIPCC_FLAGS, *[f"-D{d}" for d in defines], *SOURCES, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/ecc.h"
 #include "ecc_internal.h"
@@ -20,8 +21,12 @@ struct ecc_ctx {
     int device = 0;
     int construction = 0;
     int cu_count = 256;
-    void* ws = nullptr;     // device scratch
+    void* ws = nullptr;          // device scratch
     size_t ws_bytes = 0;
+    void* staging = nullptr;     // pinned host memory for the batch tables
+    size_t staging_bytes = 0;
+    hipEvent_t staging_done = nullptr;   // recorded after the last copy out of `staging`
+    bool staging_pending = false;
     std::string err;
 };
 
@@ -30,6 +35,10 @@ namespace {
 thread_local std::string g_create_err;
 
 constexpr int kMinmaxBlocks = 1024;
+// The first bytes of the scratch hold the counters of the single-image merge,
+// which the kernels re-arm after every call; no other use may overwrite them.
+constexpr size_t kCounterBytes = 1024;
+static_assert(kCounterBytes >= ecc::kCounterWords * sizeof(uint32_t), "counter region too small");
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -77,6 +86,13 @@ ecc_status ensure_ws(ecc_ctx* ctx, size_t bytes)
         ctx->ws = nullptr;
         return hip_fail(ctx, e, "hipMalloc(scratch)");
     }
+    // The brick and merge counters live in the scratch and must start at zero;
+    // the kernels re-arm them after every call.
+    if ((e = hipMemset(ctx->ws, 0, want)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
+        (void)hipFree(ctx->ws);
+        ctx->ws = nullptr;
+        return hip_fail(ctx, e, "hipMemset(scratch)");
+    }
     ctx->ws_bytes = want;
     return ECC_OK;
 }
@@ -120,11 +136,19 @@ ecc_status validate(ecc_ctx* ctx, const ecc_image& im, int32_t nbins, const char
             snprintf(buf, sizeof buf, "%s: dims[%d] = %lld out of [1, 2^31]", where, i, (long long)im.dims[i]);
             return fail(ctx, ECC_ERR_INVALID_ARG, buf);
         }
-        if (nvox > (int64_t(1) << 46) / im.dims[i]) {
-            snprintf(buf, sizeof buf, "%s: image has more than 2^46 voxels", where);
+        if (nvox > (int64_t(1) << 40) / im.dims[i]) {
+            snprintf(buf, sizeof buf, "%s: image has more than 2^40 voxels", where);
             return fail(ctx, ECC_ERR_INVALID_ARG, buf);
         }
         nvox *= im.dims[i];
+    }
+    {
+        // the kernels address a brick with 32-bit byte offsets from its first row
+        const int64_t esize = im.dtype == ECC_U8 ? 1 : (im.dtype == ECC_U16 ? 2 : 4);
+        if (im.dims[im.ndim - 1] * esize > (int64_t(1) << 27)) {
+            snprintf(buf, sizeof buf, "%s: rows longer than 2^27 bytes are not supported", where);
+            return fail(ctx, ECC_ERR_UNSUPPORTED, buf);
+        }
     }
     if (im.range_mode == ECC_RANGE_EXPLICIT) {
         if (im.dtype == ECC_F32) {
@@ -166,7 +190,8 @@ ecc::BinParams host_params(const Job& j, int32_t nbins)
     p.hi = j.hi;
     if (j.dtype == ECC_F32) {
         p.flat = (j.hi == j.lo) ? 1 : 0;
-        p.scale = p.flat ? 0.0 : (double)nbins / (j.hi - j.lo);
+        // a flat range bins through scale = +inf (see key_of in the kernels)
+        p.scale = p.flat ? HUGE_VAL : (double)nbins / (j.hi - j.lo);
     } else {
         const uint32_t ilo = (uint32_t)j.lo, ihi = (uint32_t)j.hi;
         const uint64_t D = (uint64_t)(ihi - ilo) + 1u;
@@ -175,25 +200,56 @@ ecc::BinParams host_params(const Job& j, int32_t nbins)
         p.q0 = (uint32_t)((uint64_t)nbins / D);
         const uint64_t r = (uint64_t)nbins % D;
         p.magic = (uint32_t)(((r << 32) / D) + 1u);
+        p.ident = ((uint64_t)nbins == D) ? 1 : 0;
     }
     return p;
 }
 
 struct Sizes {
     int grid;
+    int waves;
+    int64_t depth;
     int32_t window;
-    size_t off_params, off_mm, off_partials, total;
+    size_t off_params, off_counters, off_mm, off_level2, off_partials, total;
 };
 
+// Launch shape of the main kernel for one image:
+//  - waves: a workgroup's waves cover a contiguous x-chunk of 62 * waves columns,
+//    the whole row when it is at most 9 * 62 wide, else chunks of 8 * 62;
+//  - depth: planes (3D) or rows (2D) per workgroup brick, chosen so that there are
+//    about two bricks per CU;
+//  - grid: at most two resident workgroups per CU (more concurrent bricks cost
+//    DRAM locality), at least enough that no workgroup histogram can reach 2^31
+//    (every voxel adds at most 6 in absolute value).
 Sizes plan_sizes(const ecc_ctx* ctx, const Job& j, int32_t nbins)
 {
     Sizes s;
-    const int64_t tiles = ecc::hist_tiles(j.ndim, j.g);
-    s.grid = (int)std::min<int64_t>(tiles, (int64_t)ctx->cu_count * 4);
+    const int64_t cols = (j.g.n2 + 61) / 62;
+    s.waves = (int)(cols <= ecc::kMaxWaves ? cols : 8);
+    const int64_t chunk = 62 * (int64_t)s.waves;
+    const int64_t nxc = (j.g.n2 + chunk - 1) / chunk;
+    const int64_t target = 2 * (int64_t)ctx->cu_count;
+    if (j.ndim == 3) {
+        const int64_t nyb = (j.g.n1 + ecc::kRows3 - 1) / ecc::kRows3;
+        int64_t d = (j.g.n0 * nxc * nyb + target - 1) / target;
+        s.depth = std::min<int64_t>(std::max<int64_t>(d, 4), 32);
+    } else {
+        int64_t d = (j.g.n1 * nxc + target - 1) / target;
+        d = std::min<int64_t>(std::max<int64_t>(d, ecc::kChunk2), 512);
+        s.depth = (d + ecc::kChunk2 - 1) / ecc::kChunk2 * ecc::kChunk2;
+    }
+    const int64_t bricks = ecc::wg_bricks(j.ndim, j.g, s.waves, s.depth);
+    const bool windowed = nbins > ecc::kMaxLdsBins;
+    const int per_cu = std::min(2, ecc::resident_wgs_per_cu(j.ndim, j.dtype, ctx->construction, windowed, s.waves));
+    int64_t grid = std::min<int64_t>(bricks, (int64_t)ctx->cu_count * per_cu);
+    grid = std::max<int64_t>(grid, std::min<int64_t>(bricks, (j.nvox >> 27) + 1));
+    s.grid = (int)std::max<int64_t>(grid, 1);
     s.window = std::min<int32_t>(nbins, ecc::kMaxLdsBins);
-    s.off_params = 0;
-    s.off_mm = align_up(sizeof(ecc::BinParams));
-    s.off_partials = s.off_mm + align_up((size_t)kMinmaxBlocks * 2 * sizeof(uint32_t));
+    s.off_counters = 0;   // fixed place, shared with the batch layout (never overwritten)
+    s.off_params = kCounterBytes;
+    s.off_mm = s.off_params + align_up(sizeof(ecc::BinParams));
+    s.off_level2 = s.off_mm + align_up((size_t)kMinmaxBlocks * 2 * sizeof(uint32_t));
+    s.off_partials = s.off_level2 + align_up((size_t)ecc::kMergeGroups * (size_t)s.window * sizeof(int64_t));
     s.total = s.off_partials + align_up((size_t)s.grid * (size_t)s.window * sizeof(int32_t));
     return s;
 }
@@ -205,17 +261,18 @@ ecc_status enqueue_one(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t st
     if (st != ECC_OK) return st;
     char* base = (char*)ctx->ws;
     ecc::BinParams* pdev = nullptr;
+    uint32_t* counters = (uint32_t*)(base + sz.off_counters);
     hipError_t e;
     if (j.range_mode == ECC_RANGE_AUTO) {
         uint32_t* mm = (uint32_t*)(base + sz.off_mm);
         pdev = (ecc::BinParams*)(base + sz.off_params);
-        const int blocks = (int)std::min<int64_t>(kMinmaxBlocks, (j.nvox + 255) / 256);
+        const int blocks = (int)std::min<int64_t>(kMinmaxBlocks, (j.nvox + 4095) / 4096);
         if ((e = ecc::launch_minmax(j.data, j.dtype, j.nvox, mm, blocks, stream)) != hipSuccess)
             return hip_fail(ctx, e, "minmax launch");
         if ((e = ecc::launch_params_from_minmax(mm, blocks, j.dtype, nbins, pdev, stream)) != hipSuccess)
             return hip_fail(ctx, e, "params launch");
     }
-    ecc::HistLaunch L;
+    ecc::EccLaunch L;
     L.data = j.data;
     L.ndim = j.ndim;
     L.dtype = j.dtype;
@@ -223,16 +280,201 @@ ecc_status enqueue_one(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t st
     L.g = j.g;
     L.params_dev = pdev;
     L.params = host_params(j, nbins);
-    L.partials = (int32_t*)(base + sz.off_partials);
+    L.windowed = sz.window < nbins ? 1 : 0;
     L.grid = sz.grid;
+    L.waves = sz.waves;
+    L.depth = sz.depth;
+    L.partials = (int32_t*)(base + sz.off_partials);
+    L.out = j.out;
+    L.counter = counters;
     for (int32_t b0 = 0; b0 < nbins; b0 += sz.window) {
         L.bin_lo = b0;
         L.width = std::min<int32_t>(sz.window, nbins - b0);
-        if ((e = ecc::launch_hist(L, stream)) != hipSuccess) return hip_fail(ctx, e, "hist launch");
-        if ((e = ecc::launch_reduce(L.partials, L.grid, L.width, j.out + b0, stream)) != hipSuccess)
-            return hip_fail(ctx, e, "reduce launch");
+        const bool last = b0 + L.width >= nbins;
+        if ((e = ecc::launch_ecc(L, stream)) != hipSuccess) return hip_fail(ctx, e, "ecc launch");
+        if ((e = ecc::launch_merge(L.partials, L.grid, L.width, L.bin_lo, (int64_t*)(base + sz.off_level2),
+                                   j.out, nbins, counters, last, stream)) != hipSuccess)
+            return hip_fail(ctx, e, "merge launch");
     }
-    if ((e = ecc::launch_scan(j.out, nbins, stream)) != hipSuccess) return hip_fail(ctx, e, "scan launch");
+    return ECC_OK;
+}
+
+// ------------------------------------------------------------------ batches
+
+ecc_status ensure_staging(ecc_ctx* ctx, size_t bytes)
+{
+    hipError_t e;
+    if (!ctx->staging_done) {
+        if ((e = hipEventCreateWithFlags(&ctx->staging_done, hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(ctx, e, "hipEventCreate");
+    }
+    // the previous batch's table copy must have left the pinned buffer
+    if (ctx->staging_pending) {
+        if ((e = hipEventSynchronize(ctx->staging_done)) != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize");
+        ctx->staging_pending = false;
+    }
+    if (bytes <= ctx->staging_bytes) return ECC_OK;
+    if (ctx->staging) (void)hipHostFree(ctx->staging);
+    ctx->staging = nullptr;
+    ctx->staging_bytes = 0;
+    const size_t want = std::max(bytes, (size_t)64 << 10);
+    if ((e = hipHostMalloc(&ctx->staging, want, hipHostMallocDefault)) != hipSuccess) {
+        ctx->staging = nullptr;
+        return hip_fail(ctx, e, "hipHostMalloc(staging)");
+    }
+    ctx->staging_bytes = want;
+    return ECC_OK;
+}
+
+// Byte layout of the batch tables (identical in the pinned staging buffer and in
+// the device scratch) followed by the partial histogram rows on the device.
+struct BatchLayout {
+    size_t images, segs, wg_seg, slot_off, slots, mm, pieces, tables_end, partials, total;
+};
+
+ecc_status enqueue_batch(ecc_ctx* ctx, const std::vector<Job>& jobs, int32_t nbins, hipStream_t stream)
+{
+    const int count = (int)jobs.size();
+    const int waves = ecc::kBatchWaves;
+    std::vector<ecc::BatchImage> images((size_t)count);
+    std::vector<int64_t> bricks((size_t)count);
+    std::vector<double> brick_cost((size_t)count);
+    for (int i = 0; i < count; ++i) {
+        const Job& j = jobs[(size_t)i];
+        ecc::BatchImage& im = images[(size_t)i];
+        memset(&im, 0, sizeof im);
+        im.data = j.data;
+        im.g = j.g;
+        im.ndim = j.ndim;
+        im.dtype = j.dtype;
+        im.auto_range = j.range_mode == ECC_RANGE_AUTO ? 1 : 0;
+        im.nvox = j.nvox;
+        im.params = host_params(j, nbins);
+        im.out = j.out;
+        bricks[(size_t)i] = ecc::batch_bricks(im, waves);
+        // work of one brick: voxels visited times the 2D problems per voxel
+        const double cols = std::min<double>((double)j.g.n2, 62.0 * waves);
+        brick_cost[(size_t)i] = j.ndim == 3 ? 2.0 * cols * ecc::kRows3 * (double)im.depth
+                                            : 1.0 * cols * (double)im.depth;
+    }
+    // One launch per dtype present; the bricks of its images, in order, are cut
+    // into one contiguous run per workgroup with about equal work.
+    std::vector<ecc::BatchSeg> segs;
+    std::vector<int32_t> wg_seg;
+    struct Group { int dtype; int grid; size_t wg_seg_first; };
+    std::vector<Group> groups;
+    for (int dt = 0; dt < 3; ++dt) {
+        double total = 0;
+        int64_t nbr = 0;
+        for (int i = 0; i < count; ++i)
+            if (images[(size_t)i].dtype == dt) { total += bricks[(size_t)i] * brick_cost[(size_t)i]; nbr += bricks[(size_t)i]; }
+        if (nbr == 0) continue;
+        const int G = (int)std::max<int64_t>(1, std::min<int64_t>(nbr, 2 * (int64_t)ctx->cu_count));
+        Group gr{dt, G, wg_seg.size()};
+        const double per = total / G;
+        int wg = 0;
+        double acc = 0;   // work assigned to workgroups 0..wg-1 plus the current one
+        wg_seg.push_back((int32_t)segs.size());
+        for (int i = 0; i < count; ++i) {
+            if (images[(size_t)i].dtype != dt) continue;
+            int64_t b = 0;
+            while (b < bricks[(size_t)i]) {
+                // bricks of image i that still fit in workgroup wg's share
+                const double room = per * (wg + 1) - acc;
+                int64_t take = (int64_t)std::ceil(room / brick_cost[(size_t)i] - 1e-9);
+                if (wg == G - 1) take = bricks[(size_t)i] - b;
+                take = std::max<int64_t>(1, std::min<int64_t>(take, bricks[(size_t)i] - b));
+                segs.push_back(ecc::BatchSeg{i, (int32_t)segs.size(), b, b + take});
+                acc += take * brick_cost[(size_t)i];
+                b += take;
+                if (acc >= per * (wg + 1) - 1e-9 && wg < G - 1) {
+                    ++wg;
+                    wg_seg.push_back((int32_t)segs.size());
+                }
+            }
+        }
+        while ((int)(wg_seg.size() - gr.wg_seg_first) < G + 1) wg_seg.push_back((int32_t)segs.size());
+        groups.push_back(gr);
+    }
+    const int nseg = (int)segs.size();
+    // partial rows of every image
+    std::vector<int32_t> slot_off((size_t)count + 1, 0), slots((size_t)nseg);
+    for (const auto& sg : segs) slot_off[(size_t)sg.image + 1]++;
+    for (int i = 0; i < count; ++i) slot_off[(size_t)i + 1] += slot_off[(size_t)i];
+    {
+        std::vector<int32_t> fill(slot_off.begin(), slot_off.end() - 1);
+        for (const auto& sg : segs) slots[(size_t)fill[(size_t)sg.image]++] = sg.slot;
+    }
+    // pieces of the AUTO images for the min/max pass
+    std::vector<ecc::BatchPiece> pieces;
+    const int64_t piece = int64_t(1) << 20;
+    for (int i = 0; i < count; ++i)
+        if (images[(size_t)i].auto_range)
+            for (int64_t b = 0; b < images[(size_t)i].nvox; b += piece)
+                pieces.push_back(ecc::BatchPiece{i, 0, b, std::min(images[(size_t)i].nvox, b + piece)});
+    std::vector<uint32_t> mm((size_t)count * 2);
+    for (int i = 0; i < count; ++i) { mm[2 * (size_t)i] = 0xFFFFFFFFu; mm[2 * (size_t)i + 1] = 0u; }
+
+    const int32_t window = std::min<int32_t>(nbins, ecc::kMaxLdsBins);
+    BatchLayout lay;
+    lay.images = kCounterBytes;   // the single-image counters stay untouched
+    lay.segs = align_up(lay.images + images.size() * sizeof(ecc::BatchImage));
+    lay.wg_seg = align_up(lay.segs + segs.size() * sizeof(ecc::BatchSeg));
+    lay.slot_off = align_up(lay.wg_seg + wg_seg.size() * sizeof(int32_t));
+    lay.slots = align_up(lay.slot_off + slot_off.size() * sizeof(int32_t));
+    lay.mm = align_up(lay.slots + slots.size() * sizeof(int32_t));
+    lay.pieces = align_up(lay.mm + mm.size() * sizeof(uint32_t));
+    lay.tables_end = align_up(lay.pieces + pieces.size() * sizeof(ecc::BatchPiece));
+    lay.partials = lay.tables_end;
+    lay.total = lay.partials + align_up((size_t)nseg * (size_t)window * sizeof(int32_t));
+
+    ecc_status st = ensure_ws(ctx, lay.total);
+    if (st != ECC_OK) return st;
+    if ((st = ensure_staging(ctx, lay.tables_end - lay.images)) != ECC_OK) return st;
+    char* h = (char*)ctx->staging - lay.images;   // staging holds bytes [lay.images, lay.tables_end)
+    memcpy(h + lay.images, images.data(), images.size() * sizeof(ecc::BatchImage));
+    memcpy(h + lay.segs, segs.data(), segs.size() * sizeof(ecc::BatchSeg));
+    memcpy(h + lay.wg_seg, wg_seg.data(), wg_seg.size() * sizeof(int32_t));
+    memcpy(h + lay.slot_off, slot_off.data(), slot_off.size() * sizeof(int32_t));
+    memcpy(h + lay.slots, slots.data(), slots.size() * sizeof(int32_t));
+    memcpy(h + lay.mm, mm.data(), mm.size() * sizeof(uint32_t));
+    if (!pieces.empty()) memcpy(h + lay.pieces, pieces.data(), pieces.size() * sizeof(ecc::BatchPiece));
+    char* d = (char*)ctx->ws;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(d + lay.images, h + lay.images, lay.tables_end - lay.images, hipMemcpyHostToDevice,
+                            stream)) != hipSuccess)
+        return hip_fail(ctx, e, "hipMemcpyAsync(batch tables)");
+    if ((e = hipEventRecord(ctx->staging_done, stream)) != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
+    ctx->staging_pending = true;
+
+    ecc::BatchLaunch B;
+    memset(&B, 0, sizeof B);
+    B.images = (const ecc::BatchImage*)(d + lay.images);
+    B.count = count;
+    B.segs = (const ecc::BatchSeg*)(d + lay.segs);
+    B.slot_off = (const int32_t*)(d + lay.slot_off);
+    B.slots = (const int32_t*)(d + lay.slots);
+    B.mm = (uint32_t*)(d + lay.mm);
+    B.partials = (int32_t*)(d + lay.partials);
+    B.nbins = nbins;
+    B.waves = waves;
+    B.windowed = window < nbins ? 1 : 0;
+    if ((e = ecc::launch_minmax_batch(B.images, (const ecc::BatchPiece*)(d + lay.pieces), (int)pieces.size(), B.mm,
+                                      stream)) != hipSuccess)
+        return hip_fail(ctx, e, "batch minmax launch");
+    for (int32_t b0 = 0; b0 < nbins; b0 += window) {
+        B.bin_lo = b0;
+        B.width = std::min<int32_t>(window, nbins - b0);
+        for (const Group& gr : groups) {
+            B.dtype = gr.dtype;
+            B.grid = gr.grid;
+            B.wg_seg = (const int32_t*)(d + lay.wg_seg) + gr.wg_seg_first;
+            if ((e = ecc::launch_ecc_batch(B, ctx->construction, stream)) != hipSuccess)
+                return hip_fail(ctx, e, "batch launch");
+        }
+        if ((e = ecc::launch_merge_batch(B, b0 + B.width >= nbins, stream)) != hipSuccess)
+            return hip_fail(ctx, e, "batch merge launch");
+    }
     return ECC_OK;
 }
 
@@ -268,9 +510,11 @@ ecc_status ecc_create(ecc_ctx** ctx, int32_t device, int32_t construction)
 ecc_status ecc_destroy(ecc_ctx* ctx)
 {
     if (!ctx) return ECC_OK;
-    if (ctx->ws) {
+    {
         DeviceGuard g(ctx->device);
-        (void)hipFree(ctx->ws);
+        if (ctx->ws) (void)hipFree(ctx->ws);
+        if (ctx->staging) (void)hipHostFree(ctx->staging);
+        if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
     }
     delete ctx;
     return ECC_OK;
@@ -325,23 +569,16 @@ ecc_status ecc_compute_batch(ecc_ctx* ctx, const ecc_image* imgs, int32_t count,
     if (count < 0) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_compute_batch: negative count");
     if (count == 0) return ECC_OK;
     if (!imgs) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_compute_batch: null descriptor array");
-    Job* jobs = new (std::nothrow) Job[(size_t)count];
-    if (!jobs) return fail(ctx, ECC_ERR_OUT_OF_MEMORY, "ecc_compute_batch: out of host memory");
+    std::vector<Job> jobs((size_t)count);
     for (int32_t i = 0; i < count; ++i) {
         char where[64];
         snprintf(where, sizeof where, "ecc_compute_batch: image %d", i);
         ecc_status st = validate(ctx, imgs[i], nbins, where, &jobs[i]);
-        if (st != ECC_OK) { delete[] jobs; return st; }
+        if (st != ECC_OK) return st;
     }
     DeviceGuard g(ctx->device);
-    if (!g.ok) { delete[] jobs; return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed"); }
-    size_t need = 0;
-    for (int32_t i = 0; i < count; ++i) need = std::max(need, plan_sizes(ctx, jobs[i], nbins).total);
-    ecc_status st = ensure_ws(ctx, need);
-    for (int32_t i = 0; i < count && st == ECC_OK; ++i)
-        st = enqueue_one(ctx, jobs[i], nbins, (hipStream_t)hip_stream);
-    delete[] jobs;
-    return st;
+    if (!g.ok) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed");
+    return enqueue_batch(ctx, jobs, nbins, (hipStream_t)hip_stream);
 }
 
 }  // extern "C"

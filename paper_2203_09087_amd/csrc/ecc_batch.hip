@@ -1,0 +1,153 @@
+// ecc_batch.hip -- the batched form: the ECCs of many images of uneven sizes and
+// dimensions in one persistent launch.
+//
+// The host cuts the bricks of all images (in order) into one contiguous run per
+// workgroup, balanced by work, and lists each run as segments of single images.
+// A workgroup processes its segments in order with the same brick bodies as the
+// single-image kernels, and writes one partial histogram row per segment.  The
+// merge kernel then gives every image the sum of its rows (and its prefix scan)
+// without any atomic operation on the histogram bins, so the result of an image
+// does not depend on the batch it is in.
+#include "ecc_device.h"
+
+namespace ecc {
+
+namespace {
+
+using namespace dev;
+
+// Min/max keys of AUTO-range images: one block per piece, folded into the
+// image's keys with atomics (the host uploads lo = ~0, hi = 0 first).
+template <int DT>
+__device__ void minmax_piece(const BatchImage& I, const BatchPiece& pc, uint32_t* mm)
+{
+    using T = typename ValT<DT>::T;
+    const T* __restrict__ img = (const T*)I.data;
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    for (int64_t i = pc.begin + threadIdx.x; i < pc.end; i += kThreads) mm_take<DT>(img[i], lo, hi);
+    block_minmax(lo, hi);
+    if (threadIdx.x == 0) {
+        atomicMin(&mm[2 * pc.image], lo);
+        atomicMax(&mm[2 * pc.image + 1], hi);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_minmax_batch(const BatchImage* images, const BatchPiece* pieces,
+                                                           uint32_t* mm)
+{
+    const BatchPiece pc = pieces[blockIdx.x];
+    const BatchImage& I = images[pc.image];
+    switch (I.dtype) {
+    case DT_U8: minmax_piece<DT_U8>(I, pc, mm); break;
+    case DT_U16: minmax_piece<DT_U16>(I, pc, mm); break;
+    default: minmax_piece<DT_F32>(I, pc, mm); break;
+    }
+}
+
+template <int DT, int CONS, bool WIN>
+__global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU)))
+void k_ecc_batch(BatchLaunch B)
+{
+    __shared__ int32_t hist[kMaxLdsBins];
+    const HistRef H{hist, (uint32_t)B.bin_lo << 2, (uint32_t)B.width << 2};
+    const int64_t chunk = (int64_t)(blockDim.x >> 6) * 62;
+    const int s_end = B.wg_seg[blockIdx.x + 1];
+    for (int si = B.wg_seg[blockIdx.x]; si < s_end; ++si) {
+        const BatchSeg S = B.segs[si];
+        const BatchImage& I = B.images[S.image];
+        const BinParams P = I.auto_range
+                                ? params_from_keys(B.mm[2 * S.image], B.mm[2 * S.image + 1], DT, B.nbins)
+                                : I.params;
+        EccLaunch L;   // the fields the brick bodies read
+        L.data = I.data;
+        L.g = I.g;
+        L.depth = I.depth;
+        zero_hist(hist, B.width);
+        const uint32_t nxc = (uint32_t)I.nxc, nyb = (uint32_t)I.nyb;
+        for (int64_t b = S.b0; b < S.b1; ++b) {
+            const uint32_t bb = (uint32_t)b;
+            if (I.ndim == 3)
+                run_brick_3d<DT, CONS, WIN>(L, P, H, chunk, bb % nxc, (bb / nxc) % nyb, bb / (nxc * nyb));
+            else
+                run_brick_2d<DT, CONS, WIN>(L, P, H, chunk, bb % nxc, bb / nxc);
+        }
+        __syncthreads();
+        int32_t* dst = B.partials + (size_t)S.slot * (size_t)B.width;
+        for (int j = threadIdx.x; j < B.width; j += blockDim.x) dst[j] = hist[j];
+    }
+}
+
+// One block per image: out[bin_lo + j] = sum of the image's partial rows; with
+// `scan`, the image's out[0 .. nbins) is then prefix-summed in place.
+__global__ __launch_bounds__(kThreads) void k_merge_batch(BatchLaunch B, int scan)
+{
+    const int i = blockIdx.x;
+    const BatchImage& I = B.images[i];
+    const int r0 = B.slot_off[i], r1 = B.slot_off[i + 1];
+    for (int j = threadIdx.x; j < B.width; j += kThreads) {
+        int64_t s = 0;
+        for (int r = r0; r < r1; ++r) s += B.partials[(size_t)B.slots[r] * (size_t)B.width + j];
+        I.out[B.bin_lo + j] = s;
+    }
+    if (!scan) return;
+    __syncthreads();
+    block_scan_inplace(I.out, B.nbins);
+}
+
+template <int DT, int CONS>
+hipError_t launch_batch_w(const BatchLaunch& B, hipStream_t s)
+{
+    if (B.windowed)
+        hipLaunchKernelGGL((k_ecc_batch<DT, CONS, true>), dim3(B.grid), dim3(B.waves * 64), 0, s, B);
+    else
+        hipLaunchKernelGGL((k_ecc_batch<DT, CONS, false>), dim3(B.grid), dim3(B.waves * 64), 0, s, B);
+    return hipGetLastError();
+}
+
+template <int CONS>
+hipError_t launch_batch_d(const BatchLaunch& B, hipStream_t s)
+{
+    switch (B.dtype) {
+    case DT_U8: return launch_batch_w<DT_U8, CONS>(B, s);
+    case DT_U16: return launch_batch_w<DT_U16, CONS>(B, s);
+    default: return launch_batch_w<DT_F32, CONS>(B, s);
+    }
+}
+
+}  // namespace
+
+int64_t batch_bricks(BatchImage& im, int waves)
+{
+    const int64_t chunk = 62 * (int64_t)waves;
+    im.nxc = (int32_t)((im.g.n2 + chunk - 1) / chunk);
+    if (im.ndim == 3) {
+        im.depth = 8;
+        im.nyb = (int32_t)((im.g.n1 + kRows3 - 1) / kRows3);
+        return (int64_t)im.nxc * im.nyb * ((im.g.n0 + im.depth - 1) / im.depth);
+    }
+    im.depth = 64;
+    im.nyb = (int32_t)((im.g.n1 + im.depth - 1) / im.depth);
+    return (int64_t)im.nxc * im.nyb;
+}
+
+hipError_t launch_minmax_batch(const BatchImage* images, const BatchPiece* pieces, int npieces, uint32_t* mm,
+                               hipStream_t s)
+{
+    if (npieces <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_minmax_batch, dim3(npieces), dim3(kThreads), 0, s, images, pieces, mm);
+    return hipGetLastError();
+}
+
+hipError_t launch_ecc_batch(const BatchLaunch& B, int construction, hipStream_t s)
+{
+    return construction == CONS_TOP ? launch_batch_d<CONS_TOP>(B, s) : launch_batch_d<CONS_VERTEX>(B, s);
+}
+
+hipError_t launch_merge_batch(const BatchLaunch& B, bool scan, hipStream_t s)
+{
+    if (B.count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_merge_batch, dim3(B.count), dim3(kThreads), 0, s, B, scan ? 1 : 0);
+    return hipGetLastError();
+}
+
+}  // namespace ecc

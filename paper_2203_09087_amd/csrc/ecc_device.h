@@ -1,0 +1,563 @@
+// ecc_device.h -- device-side building blocks shared by the single-image and
+// the batched kernels (binning, wave helpers, the 2D row step, brick bodies).
+//
+// What is computed (Wang, Wagner, Chen, SoCG 2022):
+//   VCEC[j] = sum over cells of the cubical complex whose value has bin j of
+//             (-1)^dim  (Sec. 2.3), and the ECC is its prefix sum (Eq. (1)).
+// Each cell is credited to the voxel that completes it (Sec. 2.3, "Faces
+// introduced by a voxel"; Algorithm 1), so every voxel adds one signed count to
+// the histogram at its own bin.
+//
+// Who completes a cell.  In the vertex filtration a cell's value is the largest
+// bin among its vertices; voxel v completes it if v beats every other vertex,
+// "beats" = larger bin, ties won by the later raster position.  In the top
+// filtration (the paper's) a face takes the smallest bin among the voxels that
+// contain it; v introduces it if v beats them all with "beats" = smaller bin,
+// ties won by the earlier position (the paper's tie-break).  Between two voxels
+// inside the image exactly one of "v beats u (vertex)" and "v beats u (top)"
+// holds, and a voxel outside the image loses every top comparison and wins
+// every vertex one (it belongs to no vertex cell).  So one bit per neighbour,
+//     w(u) = [v wins the vertex comparison against u]   (0 for u outside),
+// serves both filtrations: x = w (vertex) or x = ~w (top).
+//
+// 2D: around a pixel, the 9 cells that contain it are summed as
+//     P(x) = 1 - sum_{i in (t, r, b, l)} x(e_i) & ~(x(e_{i-1}) & x(d_{i-1,i}))
+// (e = edge neighbours in cyclic order, d = the diagonal between two of them).
+// The vertex VCEC of an image is sum_v P(w)(v) at bin(v); the top VCEC is
+// sum_v P(~w)(v).
+//
+// 3D: a cell is (2D cell) x (z-vertex or z-edge).  Its value is the max (vertex)
+// or min (top) over its voxels, so the cells over the z-edge [z, z+1] behave like
+// the 2D complex of the plane max(P_z, P_{z+1}) (vertex) and the faces at the
+// lattice point z like the 2D complex of min(P_{z-1}, P_z) (top):
+//   vertex:  VCEC = sum_z V2(P_z) - sum_{z<n-1} V2(max(P_z, P_{z+1}))
+//   top:     VCEC = sum_z c_z T2(P_z) + sum_{z<n-1} T2(min(P_z, P_{z+1})),
+//            c_z = -1 + [z == 0] + [z == n-1]
+// so the 3D kernel solves two 2D problems per plane.
+//
+// Mapping to the hardware.  One wave handles a brick of 64 consecutive x
+// positions; lanes 0 and 63 are halo (read, never credited), lanes 1..62 own their
+// voxel.  Neighbours along x come from the adjacent lane through DPP; every
+// comparison is one v_cmp whose result is a 64-bit lane mask in SGPRs, and all of
+// the cell logic runs on the scalar unit, 64 voxels per instruction.  Only the
+// comparisons a voxel makes with its right and lower neighbours are evaluated;
+// the ones with its left and upper neighbours are the complements of the
+// neighbours' results, shifted by one lane.  The per-voxel signed count is
+// assembled with carry-in adds (v_addc/v_subb with the mask as carry) and added
+// to a workgroup histogram in LDS only where it is non-zero.  Workgroup
+// histograms are merged and prefix-scanned by a second kernel.
+#pragma once
+
+#include "ecc_internal.h"
+
+namespace ecc {
+namespace dev {
+
+
+constexpr uint32_t kSentinel = 0xFFFFFFFFu;   // above every key
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr uint64_t kOwnLanes = 0x7FFFFFFFFFFFFFFEull;   // lanes 1..62
+
+// ------------------------------------------------------------------ binning
+//
+// The kernels compare and store KEYS = 4 * bin: the order is that of the bins,
+// and a key is directly the byte offset of its counter in the LDS histogram.
+
+template <int DT> struct ValT;
+template <> struct ValT<DT_U8> { using T = uint8_t; };
+template <> struct ValT<DT_U16> { using T = uint16_t; };
+template <> struct ValT<DT_F32> { using T = float; };
+
+template <int DT>
+__device__ __forceinline__ uint32_t key_of(typename ValT<DT>::T v, const BinParams& p)
+{
+    if constexpr (DT == DT_F32) {
+        // clamp(floor(((double)x - lo) * scale), 0, nbins-1) without branches.  A
+        // flat range (hi == lo) carries scale = +inf: x > lo -> +inf -> nbins-1,
+        // x < lo -> -inf -> 0, x == lo -> 0*inf = NaN, which fmax turns into 0.
+        const float x = v;
+        double t = __dmul_rn(__dsub_rn((double)x, p.lo), p.scale);
+        t = __builtin_fmax(t, 0.0);
+        t = __builtin_fmin(t, (double)(p.nbins - 1));
+        uint32_t b = (uint32_t)t;
+        b = (x != x) ? (uint32_t)(p.nbins - 1) : b;
+        return b << 2;
+    } else {
+        uint32_t a = (uint32_t)v;
+        a = min(max(a, p.ilo), p.ihi) - p.ilo;
+        if (p.ident) return a << 2;   // nbins == hi - lo + 1
+        return (a * p.q0 + __umulhi(a, p.magic)) << 2;
+    }
+}
+
+// Binning parameters from the min/max keys of an image (AUTO range).  Keys are
+// order-preserving: integers as themselves, finite floats through the sign-flip
+// map; lo_key > hi_key means no (finite) value was seen, which gives [0, 0].
+__device__ __forceinline__ double key_to_double(uint32_t k, int dtype)
+{
+    if (dtype != DT_F32) return (double)k;
+    const uint32_t u = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+    return (double)__uint_as_float(u);
+}
+
+__device__ __forceinline__ BinParams params_from_keys(uint32_t lo_key, uint32_t hi_key, int dtype, int32_t nbins)
+{
+    BinParams p = {};
+    p.dtype = dtype;
+    p.nbins = nbins;
+    const bool empty = lo_key > hi_key;
+    const double dlo = empty ? 0.0 : key_to_double(lo_key, dtype);
+    const double dhi = empty ? 0.0 : key_to_double(hi_key, dtype);
+    p.lo = dlo;
+    p.hi = dhi;
+    if (dtype == DT_F32) {
+        p.flat = (dhi == dlo) ? 1 : 0;
+        p.scale = p.flat ? __builtin_inf() : __ddiv_rn((double)nbins, __dsub_rn(dhi, dlo));
+    } else {
+        const uint32_t ilo = (uint32_t)dlo, ihi = (uint32_t)dhi;
+        const uint64_t D = (uint64_t)(ihi - ilo) + 1u;
+        p.ilo = ilo;
+        p.ihi = ihi;
+        p.q0 = (uint32_t)((uint64_t)nbins / D);
+        const uint64_t r = (uint64_t)nbins % D;
+        p.magic = (uint32_t)(((r << 32) / D) + 1u);
+        p.ident = ((uint64_t)nbins == D) ? 1 : 0;
+    }
+    return p;
+}
+
+// Folds one value into running min/max keys (non-finite floats are skipped).
+template <int DT>
+__device__ __forceinline__ void mm_take(typename ValT<DT>::T v, uint32_t& lo, uint32_t& hi)
+{
+    if constexpr (DT == DT_F32) {
+        const uint32_t u = __float_as_uint(v);
+        const uint32_t k = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+        const bool fin = (u & 0x7F800000u) != 0x7F800000u;
+        lo = fin ? min(lo, k) : lo;
+        hi = fin ? max(hi, k) : hi;
+    } else {
+        const uint32_t k = (uint32_t)v;
+        lo = min(lo, k);
+        hi = max(hi, k);
+    }
+}
+
+// Block-wide min/max of (lo, hi); the result is valid in thread 0.
+__device__ __forceinline__ void block_minmax(uint32_t& lo, uint32_t& hi)
+{
+    __shared__ uint32_t slo[kThreads], shi[kThreads];
+    slo[threadIdx.x] = lo;
+    shi[threadIdx.x] = hi;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            slo[threadIdx.x] = min(slo[threadIdx.x], slo[threadIdx.x + s]);
+            shi[threadIdx.x] = max(shi[threadIdx.x], shi[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    lo = slo[0];
+    hi = shi[0];
+}
+
+// Inclusive prefix sum of v[0..n) by one block of kThreads threads.
+__device__ __forceinline__ void block_scan_inplace(int64_t* v, int32_t n)
+{
+    __shared__ int64_t part[kThreads];
+    const int per = (n + kThreads - 1) / kThreads;
+    const int b = threadIdx.x * per;
+    const int e = min(n, b + per);
+    int64_t s = 0;
+    for (int i = b; i < e; ++i) s += v[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < kThreads; off <<= 1) {
+        const int64_t add = (threadIdx.x >= (unsigned)off) ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int64_t acc = part[threadIdx.x] - s;
+    for (int i = b; i < e; ++i) {
+        acc += v[i];
+        v[i] = acc;
+    }
+}
+
+// ------------------------------------------------------------ wave helpers
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// lane i <- lane i+1 (lane 63 gets 0; it is never owned)
+__device__ __forceinline__ uint32_t from_right(uint32_t v)
+{
+    return __builtin_amdgcn_mov_dpp(v, 0x130 /* wave_shl:1 */, 0xF, 0xF, true);
+}
+
+// lane i <- lane i-1 (lane 0 gets 0; it is never owned)
+__device__ __forceinline__ uint32_t from_left(uint32_t v)
+{
+    return __builtin_amdgcn_mov_dpp(v, 0x138 /* wave_shr:1 */, 0xF, 0xF, true);
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+__device__ __forceinline__ bool lane_bit(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
+// acc - [lane bit of m]
+__device__ __forceinline__ int32_t sub_bit(int32_t acc, uint64_t m)
+{
+    int32_t r;
+    uint64_t carry;
+    asm("v_subb_co_u32_e64 %0, %1, %2, 0, %3" : "=v"(r), "=s"(carry) : "v"(acc), "s"(m));
+    return r;
+}
+
+// acc + [lane bit of m]
+__device__ __forceinline__ int32_t add_bit(int32_t acc, uint64_t m)
+{
+    int32_t r;
+    uint64_t carry;
+    asm("v_addc_co_u32_e64 %0, %1, %2, 0, %3" : "=v"(r), "=s"(carry) : "v"(acc), "s"(m));
+    return r;
+}
+
+// ------------------------------------------------- one row of a 2D problem
+
+// State carried from row to row of one 2D problem (one wave, 64 columns).
+struct RowState {
+    uint32_t c;        // keys of the current row
+    uint32_t c_right;  // keys of the current row, one lane to the right
+    uint64_t fb;       // previous row: [above > current] per column
+    uint64_t fbr;      // previous row: [above(x) > current(x+1)]
+    uint64_t fbl;      // previous row: [above(x) > current(x-1)]
+};
+
+__device__ __forceinline__ void row_start(RowState& s, uint32_t above, uint32_t cur)
+{
+    s.c = cur;
+    s.c_right = from_right(cur);
+    const uint32_t c_left = from_left(cur);
+    s.fb = ballot(above > cur);
+    s.fbr = ballot(above > s.c_right);
+    s.fbl = ballot(above > c_left);
+}
+
+struct HistRef {
+    int32_t* hist;     // LDS
+    uint32_t key_lo;   // 4 * first bin of the window
+    uint32_t key_span; // 4 * window width
+};
+
+__device__ __forceinline__ void hist_add(const HistRef& H, uint32_t key, int32_t v)
+{
+    atomicAdd((int32_t*)((char*)H.hist + key), v);
+}
+
+// Credits the current row (owned lanes `own`) with sign SIGN and advances the
+// state to `below`.
+template <int CONS, int SIGN, bool WIN, bool CHECK = true>
+__device__ __forceinline__ void row_step(RowState& s, uint32_t below, uint64_t own, const HistRef& H)
+{
+    const uint32_t c = s.c;
+    const uint32_t b_right = from_right(below);
+    const uint32_t b_left = from_left(below);
+    const uint64_t fr = ballot(c > s.c_right);
+    const uint64_t fb = ballot(c > below);
+    const uint64_t fbr = ballot(c > b_right);
+    const uint64_t fbl = ballot(c > b_left);
+    if (!CHECK || own) {
+        // vertex-comparison bits of the 8 neighbours
+        uint64_t er = fr, eb = fb, dbr = fbr, dbl = fbl;
+        uint64_t el = ~(fr << 1), et = ~s.fb, dtl = ~(s.fbr << 1), dtr = ~(s.fbl >> 1);
+        if constexpr (CONS == CONS_TOP) {
+            er = ~er; eb = ~eb; dbr = ~dbr; dbl = ~dbl;
+            el = ~el; et = ~et; dtl = ~dtl; dtr = ~dtr;
+        }
+        const uint64_t tt = et & ~(el & dtl);
+        const uint64_t tr = er & ~(et & dtr);
+        const uint64_t tb = eb & ~(er & dbr);
+        const uint64_t tl = el & ~(eb & dbl);
+        int32_t v;
+        if constexpr (SIGN > 0) v = sub_bit(sub_bit(sub_bit(sub_bit(1, tt), tr), tb), tl);
+        else v = add_bit(add_bit(add_bit(add_bit(-1, tt), tr), tb), tl);
+        uint32_t key = c;
+        bool hit = lane_bit(own) && v != 0;
+        if constexpr (WIN) {
+            key -= H.key_lo;
+            hit = hit && key < H.key_span;
+        }
+        if (hit) hist_add(H, key, v);
+    }
+    s.fb = fb;
+    s.fbr = fbr;
+    s.fbl = fbl;
+    s.c = below;
+    s.c_right = b_right;
+}
+
+// ------------------------------------------------------------ main kernels
+
+__device__ __forceinline__ void zero_hist(int32_t* hist, int width)
+{
+    for (int j = threadIdx.x; j < width; j += blockDim.x) hist[j] = 0;
+    __syncthreads();
+}
+
+__device__ __forceinline__ void flush_hist(const int32_t* hist, const EccLaunch& L)
+{
+    __syncthreads();
+    int32_t* dst = L.partials + (size_t)blockIdx.x * (size_t)L.width;
+    for (int j = threadIdx.x; j < L.width; j += blockDim.x) dst[j] = hist[j];
+}
+
+// Key of one loaded value; lanes outside the image (x_ok clear) get the sentinel.
+template <int DT>
+__device__ __forceinline__ uint32_t key_or_sentinel(typename ValT<DT>::T v, const BinParams& P, bool all_x,
+                                                    bool x_ok)
+{
+    const uint32_t k = key_of<DT>(v, P);
+    return (all_x || x_ok) ? k : kSentinel;
+}
+
+// Raw buffer loads: one 32-bit per-lane byte offset (the column) plus one scalar
+// byte offset (the row) against a resource whose base is the brick's first row.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_at(const void* base)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, -1, 0x00020000);
+}
+
+template <typename T> __device__ __forceinline__ T buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <> __device__ __forceinline__ uint8_t buffer_load<uint8_t>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_amdgcn_raw_buffer_load_b8(r, (int)voff, (int)soff, 0);
+}
+template <> __device__ __forceinline__ uint16_t buffer_load<uint16_t>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0);
+}
+template <> __device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+
+// Advances a scalar offset by `step`; the empty asm keeps the compiler from
+// precomputing every row's offset into its own register.
+__device__ __forceinline__ uint32_t advance(uint32_t off, uint32_t step)
+{
+    off += step;
+    asm volatile("" : "+s"(off));
+    return off;
+}
+
+// One plane step of a 3D brick: problem A on plane z with sign SA (0: skipped)
+// and, with HASB, problem B on the combined plane of z and z+1 with sign SB.
+// The two problems are independent and are advanced row by row together.
+template <int CONS, bool WIN, bool FULL, int SA, bool HASB, int NR>
+__device__ __forceinline__ void plane_step(const uint32_t (&Bc)[NR + 2], const uint32_t (&Bn)[NR + 2],
+                                           uint64_t own_x, int rows_owned, const HistRef& H)
+{
+    constexpr int SB = (CONS == CONS_TOP) ? +1 : -1;
+    auto comb = [&](int r) -> uint32_t {
+        return (CONS == CONS_TOP) ? min(Bc[r], Bn[r]) : max(Bc[r], Bn[r]);
+    };
+    RowState sa, sb;
+    if constexpr (ECC_INTERLEAVE) {
+        if constexpr (SA != 0) row_start(sa, Bc[0], Bc[1]);
+        if constexpr (HASB) row_start(sb, comb(0), comb(1));
+#pragma unroll
+        for (int r = 1; r <= NR; ++r) {
+            const uint64_t own = (FULL || r <= rows_owned) ? own_x : 0ull;
+            if constexpr (SA != 0) row_step<CONS, SA, WIN, !FULL>(sa, Bc[r + 1], own, H);
+            if constexpr (HASB) row_step<CONS, SB, WIN, !FULL>(sb, comb(r + 1), own, H);
+        }
+    } else {
+        if constexpr (SA != 0) {
+            row_start(sa, Bc[0], Bc[1]);
+#pragma unroll
+            for (int r = 1; r <= NR; ++r)
+                row_step<CONS, SA, WIN, !FULL>(sa, Bc[r + 1], (FULL || r <= rows_owned) ? own_x : 0ull, H);
+        }
+        if constexpr (HASB) {
+            row_start(sb, comb(0), comb(1));
+#pragma unroll
+            for (int r = 1; r <= NR; ++r)
+                row_step<CONS, SB, WIN, !FULL>(sb, comb(r + 1), (FULL || r <= rows_owned) ? own_x : 0ull, H);
+        }
+    }
+}
+
+// The planes of one 3D brick.  FULL: every row of the brick and its halo lies
+// inside the image (no per-row checks).  Plane z+2 is being loaded while plane z
+// is processed.
+template <int DT, int CONS, bool WIN, bool FULL>
+__device__ __forceinline__ void brick_3d(const EccLaunch& L, const BinParams& P, const HistRef& H, int64_t y0,
+                                         int64_t z0, int64_t zend, uint32_t xob, bool x_ok, bool all_x,
+                                         uint64_t own_x, int rows_owned, int r_lo, int r_hi)
+{
+    constexpr int NR = kRows3;
+    using T = typename ValT<DT>::T;
+    const int64_t n0 = L.g.n0, n1 = L.g.n1, n2 = L.g.n2;
+    const int64_t row_bytes = n2 * (int64_t)sizeof(T);
+    const char* img = (const char*)L.data;
+
+    auto row_ok = [&](int r) -> bool { return FULL || (r >= r_lo && r < r_hi); };
+    auto load_plane = [&](int64_t z, T (&raw)[NR + 2]) {
+        const __amdgpu_buffer_rsrc_t rs = rsrc_at(img + (z * n1 + (y0 - 1)) * row_bytes);
+        uint32_t soff = 0;
+#pragma unroll
+        for (int r = 0; r < NR + 2; ++r) {
+            raw[r] = row_ok(r) ? buffer_load<T>(rs, xob, soff) : T(0);
+            soff = advance(soff, (uint32_t)row_bytes);
+        }
+    };
+    auto keys = [&](const T (&raw)[NR + 2], uint32_t (&B)[NR + 2]) {
+#pragma unroll
+        for (int r = 0; r < NR + 2; ++r)
+            B[r] = row_ok(r) ? key_or_sentinel<DT>(raw[r], P, all_x, x_ok) : kSentinel;
+    };
+
+    uint32_t Bc[NR + 2], Bn[NR + 2];
+    T raw[NR + 2];
+    load_plane(z0, raw);
+    keys(raw, Bc);
+    if (ECC_PREFETCH2 && z0 + 1 < n0) load_plane(z0 + 1, raw);
+    for (int64_t z = z0; z < zend; ++z) {
+        const bool has1 = z + 1 < n0;
+        if constexpr (ECC_PREFETCH2) {
+            if (has1) keys(raw, Bn);
+            if (z + 1 < zend && z + 2 < n0) load_plane(z + 2, raw);
+        } else {
+            if (has1) {
+                load_plane(z + 1, raw);
+                keys(raw, Bn);
+            }
+        }
+        if constexpr (CONS == CONS_VERTEX) {
+            if (has1) plane_step<CONS, WIN, FULL, +1, true, NR>(Bc, Bn, own_x, rows_owned, H);
+            else plane_step<CONS, WIN, FULL, +1, false, NR>(Bc, Bn, own_x, rows_owned, H);
+        } else {
+            // top filtration: plane z enters with -1 + [z == 0] + [z == n0-1]
+            const int ca = -1 + (z == 0) + (z == n0 - 1);
+            if (has1) {
+                if (ca < 0) plane_step<CONS, WIN, FULL, -1, true, NR>(Bc, Bn, own_x, rows_owned, H);
+                else plane_step<CONS, WIN, FULL, 0, true, NR>(Bc, Bn, own_x, rows_owned, H);
+            } else {
+                if (ca > 0) plane_step<CONS, WIN, FULL, +1, false, NR>(Bc, Bn, own_x, rows_owned, H);
+                else if (ca < 0) plane_step<CONS, WIN, FULL, -1, false, NR>(Bc, Bn, own_x, rows_owned, H);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NR + 2; ++r) Bc[r] = Bn[r];
+    }
+}
+
+// The rows [y0, yend) of one 2D brick for one wave: rows are streamed in chunks
+// of kChunk2, the next chunk loading while the current one is processed.
+template <int DT, int CONS, bool WIN>
+__device__ __forceinline__ void brick_2d(const void* data, int64_t n1, int64_t n2, const BinParams& P,
+                                         const HistRef& H, int64_t y0, int64_t yend, uint32_t xo, bool x_ok,
+                                         bool all_x, uint64_t own_x)
+{
+    constexpr int CH = kChunk2;
+    using T = typename ValT<DT>::T;
+    const T* __restrict__ img = (const T*)data;
+    auto key_at = [&](int64_t y) -> uint32_t {
+        if (y < 0 || y >= n1) return kSentinel;
+        return key_or_sentinel<DT>(img[y * n2 + xo], P, all_x, x_ok);
+    };
+    const uint32_t row_bytes = (uint32_t)(n2 * (int64_t)sizeof(T));
+    const uint32_t xob = xo * (uint32_t)sizeof(T);
+    // rows ys .. ys+CH-1 (those inside the image)
+    auto load_chunk = [&](int64_t ys, T (&raw)[CH]) {
+        const __amdgpu_buffer_rsrc_t rs = rsrc_at(img + ys * n2);
+        uint32_t soff = 0;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            raw[k] = (ys + k < n1) ? buffer_load<T>(rs, xob, soff) : T(0);
+            soff = advance(soff, row_bytes);
+        }
+    };
+    RowState s;
+    row_start(s, key_at(y0 - 1), key_at(y0));
+    T raw[CH];
+    load_chunk(y0 + 1, raw);
+    for (int64_t y = y0; y < yend; y += CH) {
+        uint32_t b[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k)
+            b[k] = (y + 1 + k < n1) ? key_or_sentinel<DT>(raw[k], P, all_x, x_ok) : kSentinel;
+        if (y + CH < yend) load_chunk(y + CH + 1, raw);
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const uint64_t own = (y + k < yend) ? own_x : 0ull;
+            row_step<CONS, +1, WIN>(s, b[k], own, H);
+        }
+    }
+}
+
+// Column placement of one wave inside a workgroup brick: lane 0 and lane 63 are
+// halo, lanes 1..62 own columns x0 + 62 * wave + lane - 1.
+struct WaveCols {
+    bool active;       // the wave owns at least one column of the image
+    bool x_ok;         // this lane's column lies inside the image
+    bool all_x;        // every lane's column does
+    uint64_t own_x;    // owned lanes
+    uint32_t xo;       // this lane's column, clamped into the image
+};
+
+__device__ __forceinline__ WaveCols wave_cols(int64_t x0, int wave, int64_t n2)
+{
+    WaveCols w;
+    const int64_t first = x0 + (int64_t)wave * 62;
+    w.active = first < n2;
+    const int64_t x = first - 1 + (int64_t)lane_id();
+    w.x_ok = x >= 0 && x < n2;
+    const uint64_t xmask = ballot(w.x_ok);
+    w.all_x = xmask == ~0ull;
+    w.own_x = xmask & kOwnLanes;
+    w.xo = (uint32_t)(x < 0 ? 0 : (x >= n2 ? n2 - 1 : x));
+    return w;
+}
+
+// One 3D workgroup brick (x-chunk xc, row block yb, plane block zb) for this wave.
+template <int DT, int CONS, bool WIN>
+__device__ __forceinline__ void run_brick_3d(const EccLaunch& L, const BinParams& P, const HistRef& H,
+                                             int64_t chunk, uint32_t xc, uint32_t yb, uint32_t zb)
+{
+    constexpr int NR = kRows3;
+    using T = typename ValT<DT>::T;
+    const int64_t n0 = L.g.n0, n1 = L.g.n1, n2 = L.g.n2;
+    const WaveCols w = wave_cols((int64_t)xc * chunk, (int)(threadIdx.x >> 6), n2);
+    if (!w.active) return;
+    const uint32_t xob = w.xo * (uint32_t)sizeof(T);
+    const int64_t y0 = (int64_t)yb * NR;
+    const int rows_owned = (int)((n1 - y0) < NR ? (n1 - y0) : NR);
+    const int64_t z0 = (int64_t)zb * L.depth;
+    const int64_t zend = (z0 + L.depth < n0) ? z0 + L.depth : n0;
+    // rows r in [r_lo, r_hi) of the brick (row r is y0 - 1 + r) lie inside the image
+    const int r_lo = (y0 == 0) ? 1 : 0;
+    const int r_hi = (int)((n1 - (y0 - 1)) < NR + 2 ? (n1 - (y0 - 1)) : NR + 2);
+    if (r_lo == 0 && r_hi == NR + 2)
+        brick_3d<DT, CONS, WIN, true>(L, P, H, y0, z0, zend, xob, w.x_ok, w.all_x, w.own_x, rows_owned, r_lo, r_hi);
+    else
+        brick_3d<DT, CONS, WIN, false>(L, P, H, y0, z0, zend, xob, w.x_ok, w.all_x, w.own_x, rows_owned, r_lo, r_hi);
+}
+
+// One 2D workgroup brick (x-chunk xc, row block yb) for this wave.
+template <int DT, int CONS, bool WIN>
+__device__ __forceinline__ void run_brick_2d(const EccLaunch& L, const BinParams& P, const HistRef& H,
+                                             int64_t chunk, uint32_t xc, uint32_t yb)
+{
+    const int64_t n1 = L.g.n1, n2 = L.g.n2;
+    const WaveCols w = wave_cols((int64_t)xc * chunk, (int)(threadIdx.x >> 6), n2);
+    if (!w.active) return;
+    const int64_t y0 = (int64_t)yb * L.depth;
+    const int64_t yend = (y0 + L.depth < n1) ? y0 + L.depth : n1;
+    brick_2d<DT, CONS, WIN>(L.data, n1, n2, P, H, y0, yend, w.xo, w.x_ok, w.all_x, w.own_x);
+}
+
+}  // namespace dev
+}  // namespace ecc

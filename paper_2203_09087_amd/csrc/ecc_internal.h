@@ -17,45 +17,143 @@ enum : int32_t { CONS_VERTEX = 0, CONS_TOP = 1 };
 //                 exactly as umulhi(a, magic), magic = floor(r*2^32/D) + 1
 //                 (exact because a*D < 2^32);
 //   float data:   NaN -> nbins-1; flat range -> (x > hi ? nbins-1 : 0);
-//                 otherwise clamp(floor(((double)x - lo) * scale), 0, nbins-1).
+//                 otherwise clamp(floor(((double)x - lo) * scale), 0, nbins-1),
+//                 scale = nbins / (hi - lo) (+inf for a flat range, which gives
+//                 the flat rule through the same formula).
 struct BinParams {
     int32_t dtype;
     int32_t nbins;
     uint32_t ilo, ihi, q0, magic;
-    int32_t flat;
-    int32_t pad;
+    int32_t flat;     // float data, hi == lo
+    int32_t ident;    // integer data, nbins == D: bin = a
     double lo, hi, scale;
 };
 
-// Geometry of one image: n[0] slowest.  For 2D images n[0] is 1.
+// Geometry of one image: n0 slowest.  For 2D images n0 is 1.
 struct Geom {
     int64_t n0, n1, n2;
 };
 
 // Histogram window: bins [bin_lo, bin_lo + width) are accumulated in LDS.
-constexpr int kMaxLdsBins = 8192;
+constexpr int kMaxLdsBins = 4096;
 
-struct HistLaunch {
+// Brick shapes of the wave kernels (64 x-lanes, 62 of them owned).  The
+// ECC_* macros exist for tuning builds; the defaults are the shipped shapes.
+#ifndef ECC_ROWS3
+#define ECC_ROWS3 16
+#endif
+#ifndef ECC_PLANES3
+#define ECC_PLANES3 32
+#endif
+#ifndef ECC_CHUNK2
+#define ECC_CHUNK2 16
+#endif
+#ifndef ECC_PREFETCH2
+#define ECC_PREFETCH2 1   // 3D: plane z+2 in flight while plane z is processed
+#endif
+#ifndef ECC_WAVES_PER_EU
+#define ECC_WAVES_PER_EU 5   // resident waves per SIMD the main kernels are compiled for
+#endif
+#ifndef ECC_INTERLEAVE
+#define ECC_INTERLEAVE 1  // 3D: advance the two 2D problems of a plane row by row together
+#endif
+constexpr int kRows3 = ECC_ROWS3;      // rows per 3D brick
+constexpr int kPlanes3 = ECC_PLANES3;  // planes per 3D brick
+constexpr int kChunk2 = ECC_CHUNK2;    // rows loaded together in the 2D kernel
+// Waves per workgroup of the main kernels (x-chunk = waves * 62 columns).
+constexpr int kMaxWaves = 9;
+
+struct EccLaunch {
     const void* data;
     int ndim, dtype, construction;
     Geom g;
     const BinParams* params_dev;   // non-null: read the parameters from device memory
     BinParams params;              // used when params_dev is null
     int32_t bin_lo, width;
-    int32_t* partials;             // [grid][width]
-    int grid;                      // number of workgroups
+    int32_t windowed;              // nbins > width: skip bins outside the window
+    int32_t grid;                  // number of workgroups
+    int32_t waves;                 // waves per workgroup (x-chunk = 62 * waves columns)
+    int64_t depth;                 // planes (3D) or rows (2D) per workgroup brick
+    int32_t* partials;             // [grid][width] workgroup histograms
+    int64_t* out;                  // the caller's output (VCEC window, zeroed by block 0)
+    uint32_t* counter;             // unused by the main kernels (kept 0 for the merge)
 };
+
+// ---------------------------------------------------------------- batches
+
+// One image of a batch, as the batched kernels see it.
+struct BatchImage {
+    const void* data;
+    Geom g;
+    int32_t ndim, dtype;
+    int32_t auto_range;   // parameters come from the min/max keys mm[2*i], mm[2*i+1]
+    int32_t nxc;          // x-chunks of 62 * waves columns
+    int32_t nyb;          // row blocks (3D: kRows3 rows; 2D: `depth` rows)
+    int32_t pad;
+    int64_t depth;        // planes (3D) or rows (2D) per brick
+    int64_t nvox;
+    BinParams params;     // explicit or default range
+    int64_t* out;         // the caller's output, nbins int64
+};
+
+// A run of consecutive bricks [b0, b1) of one image handled by one workgroup; its
+// histogram lands in partial row `slot`.
+struct BatchSeg {
+    int32_t image;
+    int32_t slot;
+    int64_t b0, b1;
+};
+
+// A contiguous piece of one AUTO-range image for the batched min/max pass.
+struct BatchPiece {
+    int32_t image;
+    int32_t pad;
+    int64_t begin, end;   // element range
+};
+
+struct BatchLaunch {
+    const BatchImage* images;
+    int32_t count;
+    int32_t dtype;              // the launch serves the images of this dtype
+    const BatchSeg* segs;
+    const int32_t* wg_seg;      // workgroup g runs segs[wg_seg[g] .. wg_seg[g+1])
+    const int32_t* slot_off;    // image i owns partial rows slots[slot_off[i] .. slot_off[i+1])
+    const int32_t* slots;
+    uint32_t* mm;               // [count][2] min/max keys of AUTO images
+    int32_t* partials;          // [nslots][width]
+    int32_t nbins, bin_lo, width, windowed;
+    int32_t grid, waves;
+};
+
+// Launchers (ecc_batch.hip).
+hipError_t launch_minmax_batch(const BatchImage* images, const BatchPiece* pieces, int npieces, uint32_t* mm,
+                               hipStream_t s);
+hipError_t launch_ecc_batch(const BatchLaunch& B, int construction, hipStream_t s);
+// Sums every image's partial rows into its out[bin_lo .. bin_lo+width) and, with
+// `scan`, prefix-sums its out[0 .. nbins).
+hipError_t launch_merge_batch(const BatchLaunch& B, bool scan, hipStream_t s);
+// Bricks of one batch image for the batched launch shape (sets nxc, nyb, depth).
+int64_t batch_bricks(BatchImage& im, int waves);
+constexpr int kBatchWaves = 4;   // waves per workgroup of the batched kernel
 
 // Launchers (ecc_kernels.hip).  All enqueue on `s` and return the launch status.
 hipError_t launch_minmax(const void* data, int dtype, int64_t nvox, uint32_t* mm_out, int blocks,
                          hipStream_t s);
 hipError_t launch_params_from_minmax(const uint32_t* mm, int blocks, int dtype, int32_t nbins,
                                      BinParams* out, hipStream_t s);
-hipError_t launch_hist(const HistLaunch& L, hipStream_t s);
-hipError_t launch_reduce(const int32_t* partials, int grid, int32_t width, int64_t* out_window,
-                         hipStream_t s);
-hipError_t launch_scan(int64_t* out, int32_t nbins, hipStream_t s);
+hipError_t launch_ecc(const EccLaunch& L, hipStream_t s);
+// Sums the `rows` partial histograms into out[bin_lo..bin_lo+width) (through
+// `level2`, kMergeGroups*width int64 of scratch), re-arms the counters and, with
+// `scan`, prefix-sums out[0..nbins).  counters[0] is the brick counter of the
+// main kernel, counters[1] and counters[2..] belong to the merge.
+constexpr int kMergeGroups = 16;
+constexpr int kCounterWords = 256;   // >= 2 + kMaxLdsBins / 64
+hipError_t launch_merge(const int32_t* partials, int rows, int32_t width, int32_t bin_lo, int64_t* level2,
+                        int64_t* out, int32_t nbins, uint32_t* counters, bool scan, hipStream_t s);
 
-int64_t hist_tiles(int ndim, const Geom& g);
+// Workgroup bricks of an image for a launch shape.
+int64_t wg_bricks(int ndim, const Geom& g, int waves, int64_t depth);
+// Workgroups of the main kernel variant (of `waves` waves) that fit on one CU.
+int resident_wgs_per_cu(int ndim, int dtype, int construction, bool windowed, int waves);
 
 }  // namespace ecc
