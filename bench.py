@@ -70,6 +70,43 @@ def cpu_baseline(vol, nbins, lo, hi, target_s=12.0):
                       f"({sample.size} voxels, vertex filtration, {nbins} bins), {dt:.1f} s"}
 
 
+def serving_leg(dev, rates=(100, 200, 500, 1000, 2000, 5000), seconds=2.0, max_requests=4000):
+    """Open-loop Poisson request streams over crops of two GRF pools (uint16,
+    4096 levels), 4096 bins, HBM-footprint admission; p50/p99 per rate."""
+    import torch
+    from paper_2203_09087_amd import serve, synth
+    log("generating serving pools ...")
+    p2 = torch.from_numpy(synth.quantize_u16(synth.grf((4096, 4096), seed=61), 4096).view(np.int16)).to(dev)
+    p3 = torch.from_numpy(synth.quantize_u16(synth.grf((384, 384, 384), seed=62), 4096).view(np.int16)).to(dev)
+    torch.cuda.synchronize()
+    budget = 8 << 30
+    out = {"budget_bytes": budget, "max_batch": 64, "lanes": 2, "nbins": 4096, "rates": {}}
+    srv = serve.Server(budget_bytes=budget, max_batch=64, lanes=2)
+    for rate in rates:
+        n = int(min(max_requests, max(200, rate * seconds)))
+        reqs = synth.serving_requests(float(rate), n, seed=6)
+        views = []
+        for q in reqs:
+            o, s = q["offset"], q["shape"]
+            if len(s) == 2:
+                views.append(p2[o[0]:o[0] + s[0], o[1]:o[1] + s[1]])
+            else:
+                views.append(p3[o[0]:o[0] + s[0], o[1]:o[1] + s[1], o[2]:o[2] + s[2]])
+        arrivals = [q["t"] for q in reqs]
+        log(f"serving at {rate} req/s, {n} requests ...")
+        t0 = time.perf_counter()
+        done = srv.run_open_loop(arrivals, lambda i: serve.Request(source=views[i], nbins=4096,
+                                                                   value_range=(0, 4095)))
+        wall = time.perf_counter() - t0
+        summ = serve.latency_summary(done, wall)
+        summ["gvox_s"] = round(sum(v.numel() for v in views) / wall / 1e9, 2)
+        summ["peak_held_bytes"] = srv.peak_held
+        out["rates"][str(rate)] = summ
+    out["batches"] = srv.batches
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +114,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-side", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; the histogram of a multi-GPU "
@@ -166,6 +204,9 @@ def main():
                              "per_image_calls_ms": round(mp, 3),
                              "speedup_vs_per_image": round(mp / mb, 3)}
         del dev_imgs, outs
+
+    if not args.no_side and not args.no_serve:
+        result["serving"] = serving_leg(dev)
 
     if not args.no_cpu:
         log("cpu baseline ...")

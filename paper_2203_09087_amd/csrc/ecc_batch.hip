@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kThreads) void k_minmax_batch(const BatchImage* ima
 }
 
 template <int DT, int CONS, bool WIN>
-__global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU)))
+__global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU_3D)))
 void k_ecc_batch(BatchLaunch B)
 {
     __shared__ int32_t hist[kMaxLdsBins];

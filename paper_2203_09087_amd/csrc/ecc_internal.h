@@ -49,13 +49,16 @@ constexpr int kMaxLdsBins = 4096;
 #define ECC_CHUNK2 16
 #endif
 #ifndef ECC_PREFETCH2
-#define ECC_PREFETCH2 1   // 3D: plane z+2 in flight while plane z is processed
+#define ECC_PREFETCH2 0   // 3D: plane z+2 in flight while plane z is processed
 #endif
-#ifndef ECC_WAVES_PER_EU
-#define ECC_WAVES_PER_EU 5   // resident waves per SIMD the main kernels are compiled for
+#ifndef ECC_WAVES_PER_EU_3D
+#define ECC_WAVES_PER_EU_3D 5   // resident waves per SIMD the 3D kernels are compiled for
+#endif
+#ifndef ECC_WAVES_PER_EU_2D
+#define ECC_WAVES_PER_EU_2D 5   // resident waves per SIMD the 2D kernels are compiled for
 #endif
 #ifndef ECC_INTERLEAVE
-#define ECC_INTERLEAVE 1  // 3D: advance the two 2D problems of a plane row by row together
+#define ECC_INTERLEAVE 0  // 3D: advance the two 2D problems of a plane row by row together
 #endif
 constexpr int kRows3 = ECC_ROWS3;      // rows per 3D brick
 constexpr int kPlanes3 = ECC_PLANES3;  // planes per 3D brick

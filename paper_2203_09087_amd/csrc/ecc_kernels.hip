@@ -15,7 +15,7 @@ using namespace dev;
 // All waves of a workgroup read the same rows at about the same time, so every
 // plane step of a workgroup reads whole row segments of memory.
 template <int DT, int CONS, bool WIN>
-__global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU))) void k_ecc_3d(EccLaunch L)
+__global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU_3D))) void k_ecc_3d(EccLaunch L)
 {
     __shared__ int32_t hist[kMaxLdsBins];
     const BinParams P = L.params_dev ? *L.params_dev : L.params;
@@ -33,7 +33,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
 
 // 2D images.  A workgroup brick is a contiguous x-chunk x L.depth rows.
 template <int DT, int CONS, bool WIN>
-__global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU))) void k_ecc_2d(EccLaunch L)
+__global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU_2D))) void k_ecc_2d(EccLaunch L)
 {
     __shared__ int32_t hist[kMaxLdsBins];
     const BinParams P = L.params_dev ? *L.params_dev : L.params;

@@ -1,0 +1,177 @@
+"""Serving form: a continuous-batching loop over the ECC library.
+
+Requests (one image each, already resident in device memory or given as a
+device view to copy from) arrive over time.  The loop admits arrived requests in
+arrival order as long as their device footprint (input copy + int64 output) fits
+the memory budget and a lane is free, gathers the admitted requests of a lane
+into one ``ecc_compute_batch`` call, and records one event per batch.  Several
+lanes (each its own library context and HIP stream) let batches that were
+admitted at different times run on the device at the same time, so requests that
+arrive while others are on the GPU join the next batch instead of waiting for the
+GPU to drain.  Outputs stay on the device; completion times are taken when the
+loop sees a batch's event complete.
+
+All computation is in the library; this module only schedules calls.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+from . import ecc
+
+
+@dataclass
+class Request:
+    """One ECC request.  ``source`` is a device tensor (any strides); ``value_range``
+    as in ``ecc.make_image``.  Timing fields are host ``perf_counter`` seconds."""
+    source: object
+    nbins: int = 4096
+    value_range: object = None
+    t_arrival: float = 0.0
+    t_admit: float = -1.0
+    t_done: float = -1.0
+    out: object = None
+    image: object = None
+    nbytes: int = 0
+    lane: int = -1
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrival
+
+
+@dataclass
+class _Lane:
+    ctx: object
+    stream: object
+    inflight: collections.deque = field(default_factory=collections.deque)   # (event, [requests])
+
+
+class Server:
+    """Continuous-batching ECC server on one GPU.
+
+    budget_bytes: device memory that admitted, unfinished requests may hold.
+    max_batch:    most requests per library call.
+    lanes:        independent (context, stream) pairs; at most ``max_inflight``
+                  batches are outstanding per lane.
+    """
+
+    def __init__(self, device=0, construction="vertex", budget_bytes=8 << 30, max_batch=64, lanes=2,
+                 max_inflight=2):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.budget = int(budget_bytes)
+        self.max_batch = int(max_batch)
+        self.max_inflight = int(max_inflight)
+        self.lanes = [_Lane(ecc.Context(device, construction), torch.cuda.Stream(self.device))
+                      for _ in range(lanes)]
+        self.pending = collections.deque()
+        self.held = 0             # bytes held by admitted, unfinished requests
+        self.peak_held = 0
+        self.completed = []
+        self.batches = 0
+
+    def close(self):
+        for ln in self.lanes:
+            ln.ctx.close()
+
+    # ------------------------------------------------------------ scheduling
+
+    def submit(self, req: Request):
+        """Queues a request that has arrived (its ``t_arrival`` is already set)."""
+        src = req.source
+        req.nbytes = src.numel() * src.element_size() + 8 * req.nbins
+        if req.nbytes > self.budget:
+            raise ValueError(f"request of {req.nbytes} bytes exceeds the budget of {self.budget}")
+        self.pending.append(req)
+
+    def _reap(self, now: float) -> int:
+        done = 0
+        for ln in self.lanes:
+            while ln.inflight and ln.inflight[0][0].query():
+                _, reqs = ln.inflight.popleft()
+                for r in reqs:
+                    r.t_done = now
+                    self.held -= r.nbytes
+                    r.image = None          # the input copy can be released
+                    self.completed.append(r)
+                done += len(reqs)
+        return done
+
+    def _admit(self, now: float) -> int:
+        torch = self.torch
+        started = 0
+        for li, ln in enumerate(self.lanes):
+            if not self.pending:
+                break
+            if len(ln.inflight) >= self.max_inflight:
+                continue
+            batch = []
+            nbins = self.pending[0].nbins
+            while (self.pending and len(batch) < self.max_batch and self.pending[0].nbins == nbins
+                   and self.held + self.pending[0].nbytes <= self.budget):
+                r = self.pending.popleft()
+                self.held += r.nbytes
+                batch.append(r)
+            if not batch:
+                break      # the head request waits for memory to free up
+            self.peak_held = max(self.peak_held, self.held)
+            with torch.cuda.stream(ln.stream):
+                for r in batch:
+                    r.t_admit = now
+                    r.lane = li
+                    r.image = r.source.contiguous() if not r.source.is_contiguous() else r.source
+                    r.out = torch.empty(r.nbins, dtype=torch.int64, device=self.device)
+            ln.ctx.compute_batch([r.image for r in batch], nbins,
+                                 value_ranges=[r.value_range for r in batch],
+                                 outs=[r.out for r in batch], stream=ln.stream)
+            ev = torch.cuda.Event()
+            ev.record(ln.stream)
+            ln.inflight.append((ev, batch))
+            self.batches += 1
+            started += len(batch)
+        return started
+
+    def step(self) -> None:
+        now = time.perf_counter()
+        self._reap(now)
+        self._admit(now)
+
+    def busy(self) -> bool:
+        return bool(self.pending) or any(ln.inflight for ln in self.lanes)
+
+    def drain(self) -> None:
+        while self.busy():
+            self.step()
+
+    # ------------------------------------------------------------- open loop
+
+    def run_open_loop(self, arrivals, make_request):
+        """Replays an arrival schedule (seconds from start, ascending): request i is
+        submitted once its time has come; returns the completed requests in order."""
+        t0 = time.perf_counter()
+        i, n = 0, len(arrivals)
+        while i < n or self.busy():
+            now = time.perf_counter()
+            while i < n and t0 + arrivals[i] <= now:
+                req = make_request(i)
+                req.t_arrival = t0 + arrivals[i]
+                self.submit(req)
+                i += 1
+            self.step()
+        done = sorted(self.completed, key=lambda r: r.t_arrival)
+        self.completed = []
+        return done
+
+
+def latency_summary(reqs, wall_s: float) -> dict:
+    """p50/p99 latency (ms) and completed requests per second."""
+    import numpy as np
+    lat = np.array([r.latency for r in reqs]) * 1e3
+    return {"requests": len(reqs), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "mean_ms": round(float(lat.mean()), 3),
+            "completed_per_s": round(len(reqs) / wall_s, 1)}
