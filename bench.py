@@ -49,6 +49,114 @@ def timed_calls(fn, stream, steps, warmup):
     return [s.elapsed_time(e) for s, e in zip(starts, ends)], wall
 
 
+def traffic_bytes():
+    """HBM bytes per launch of the histogram kernel on the 512^3 f32 step, from the
+    committed rocprofv3 counter summary, if it was taken from the current kernel
+    sources (else None)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    fields = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    try:
+        return int(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ecc_3d_f32_512cubed_traffic.txt")
+COPY_BYTES = 512 << 20
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2203_09087_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()
+
+
+def traffic_run():
+    """The program the counter passes profile: three plain copies of a 512 MiB
+    buffer (the calibration kernel, known bytes) and three steps of the 512^3 f32
+    ECC."""
+    import torch
+    from paper_2203_09087_amd import ecc, synth
+    dev = torch.device("cuda", 0)
+    vol = synth.grf((512, 512, 512), seed=3)
+    lo, hi = float(vol.min()), float(vol.max())
+    vol_d = torch.from_numpy(vol).to(dev)
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    ctx = ecc.Context(0, "vertex")
+    out = torch.empty(4096, dtype=torch.int64, device=dev)
+    for _ in range(3):
+        ctx.compute(vol_d, 4096, value_range=(lo, hi), out=out)
+    torch.cuda.synchronize()
+    ctx.close()
+    log("traffic run done")
+
+
+def write_traffic(fetch_csv, write_csv):
+    """Turns the FETCH_SIZE and WRITE_SIZE passes over traffic_run() into the
+    summary that traffic_bytes() reads.  Each counter is scaled by the bytes the
+    copy kernel is known to move over what the counter reads for it."""
+    import csv
+
+    def per_kernel(path, counter):
+        vals = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return vals
+
+    f, w = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    copy = [k for k in f if "copy" in k.lower()]
+    ecck = [k for k in f if "k_ecc_3d" in k]
+    if not copy or not ecck:
+        raise SystemExit(f"copy or histogram kernel not found in {sorted(f)}")
+    copy = max(copy, key=lambda k: np.mean(f[k]))
+    ecck = ecck[0]
+    cf, cw = float(np.mean(f[copy])), float(np.mean(w[copy]))
+    ef, ew = float(np.mean(f[ecck])), float(np.mean(w[ecck]))
+    fs, ws = COPY_BYTES / (cf * 1024), COPY_BYTES / (cw * 1024)
+    hf, hw = ef * 1024 * fs, ew * 1024 * ws
+    lines = [
+        "# HBM traffic per launch of the histogram kernel, 512^3 float32 GRF (seed 3),",
+        "# vertex filtration, 4096 bins over [min, max]; counters in KiB per dispatch.",
+        "command_fetch: cd /tmp && timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv "
+        "-d $REPO/gpurun_out/pmc_fetch -o run -- python3 $REPO/bench.py --traffic",
+        "command_write: cd /tmp && timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv "
+        "-d $REPO/gpurun_out/pmc_write -o run -- python3 $REPO/bench.py --traffic",
+        f"command_summary: python3 bench.py --write-traffic {fetch_csv} {write_csv}",
+        f"calibration_kernel: {copy}",
+        f"calibration_bytes: {COPY_BYTES} read and {COPY_BYTES} written per dispatch",
+        f"copy_fetch_kib: {cf:.1f} (mean of {len(f[copy])})",
+        f"copy_write_kib: {cw:.1f} (mean of {len(w[copy])})",
+        f"fetch_scale: {fs:.4f}",
+        f"write_scale: {ws:.4f}",
+        f"histogram_kernel: {ecck}",
+        f"ecc_fetch_kib: {ef:.1f} (mean of {len(f[ecck])})",
+        f"ecc_write_kib: {ew:.1f} (mean of {len(w[ecck])})",
+        f"hbm_fetch_bytes_per_launch: {int(round(hf))}",
+        f"hbm_write_bytes_per_launch: {int(round(hw))}",
+        f"hbm_bytes_per_launch: {int(round(hf + hw))}",
+        f"algorithmic_bytes_per_launch: {512 ** 3 * 4}",
+        f"kernel_sources_sha256: {kernel_sources_sha256()}",
+    ]
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def cpu_baseline(vol, nbins, lo, hi, target_s=12.0):
     """The oracle as it is, on the first planes of the volume (bounded sample)."""
     import oracle
@@ -115,12 +223,21 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-side", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--traffic", action="store_true", help="only the program the counter passes profile")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarize the two counter passes into the profiles folder")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; the histogram of a multi-GPU "
                                    "run would be one all-reduce of nbins int64 (see the design notes)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.traffic:
+        traffic_run()
+        return
 
     import torch
     from paper_2203_09087_amd import ecc, synth
@@ -140,12 +257,20 @@ def main():
         ctx.compute(vol_d, nbins, value_range=(lo, hi), out=out, stream=stream)
 
     log("timing plain 512^3 ...")
-    ms, wall = timed_calls(step, stream, args.steps, args.warmup)
+    # HIP events around every launch of the histogram kernel, on the call's stream
+    ctx.set_kernel_timing(True)
+    for _ in range(args.warmup):
+        step()
+    ctx.kernel_time()
+    ms, wall = timed_calls(step, stream, args.steps, 0)
+    k_ms, k_launches = ctx.kernel_time()
+    ctx.set_kernel_timing(False)
+    k_avg = k_ms / max(1, k_launches)
     ms_mean = float(np.mean(ms))
     nvox = vol.size
     gvox = nvox / (ms_mean * 1e-3) / 1e9
-    alg_bytes = nvox * 4
-    achieved = alg_bytes / (ms_mean * 1e-3) / 1e9
+    alg_bytes = nvox * 4            # each f32 voxel read once
+    achieved = alg_bytes / (k_avg * 1e-3) / 1e9
 
     result = {
         "metric": "Gvoxels/s (plain single-image ECC, 512^3 f32, 4096 bins)",
@@ -161,8 +286,10 @@ def main():
         "config": {"workload": "512^3 float32 Gaussian random field (P(k)~k^-3, seed 3), "
                                "4096 bins over [min,max], vertex filtration, one ECC per step",
                    "shape": [512, 512, 512], "nbins": nbins, "range": "explicit"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "roofline": {"bound": "hbm", "kernel": "k_ecc_3d (f32, vertex)", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_bytes(), "kernel_ms": round(k_avg, 4),
+                     "launches": k_launches, "algorithmic_bytes": alg_bytes},
         "p50_ms": round(float(np.percentile(ms, 50)), 4),
         "p99_ms": round(float(np.percentile(ms, 99)), 4),
         "wall_s": round(wall, 3),

@@ -130,6 +130,22 @@ ecc_status ecc_compute_ex(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, voi
 ecc_status ecc_compute_batch(ecc_ctx* ctx, const ecc_image* imgs, int32_t count, int32_t nbins,
                              void* hip_stream);
 
+/* Kernel timing, for measurement tools (the method itself does not need it).
+ * With enable != 0, every later call on `ctx` records a pair of HIP events on its
+ * stream around each launch of the histogram kernel (the voxel pass of Sec. 2.3
+ * that reads the image; AUTO min/max, merge and scan launches are not counted).
+ * enable == 0 stops recording and drops unread records.  Timing changes no result.
+ * Errors: ECC_ERR_INVALID_ARG (ctx null), ECC_ERR_DEVICE. */
+ecc_status ecc_set_kernel_timing(ecc_ctx* ctx, int32_t enable);
+
+/* Waits for the recorded events, writes the summed duration in milliseconds of
+ * the histogram-kernel launches recorded since the previous read to *total_ms and
+ * their number to *launches (both HOST pointers), and clears the tally.  Blocks
+ * until those launches have finished.  After 4096 unread launches a call folds
+ * its records into the tally, waiting for them first.
+ * Errors: ECC_ERR_INVALID_ARG (null pointer), ECC_ERR_DEVICE. */
+ecc_status ecc_kernel_time(ecc_ctx* ctx, double* total_ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

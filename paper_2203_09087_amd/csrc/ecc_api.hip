@@ -27,6 +27,12 @@ struct ecc_ctx {
     size_t staging_bytes = 0;
     hipEvent_t staging_done = nullptr;   // recorded after the last copy out of `staging`
     bool staging_pending = false;
+    // kernel timing (ecc_set_kernel_timing): event pairs around histogram launches
+    bool timing = false;
+    std::vector<hipEvent_t> tev;   // 2 * kTimingPairs events, created on enable
+    size_t tused = 0;              // pairs recorded since the last fold
+    double tms = 0.0;              // folded milliseconds
+    int64_t tcount = 0;            // folded launches
     std::string err;
 };
 
@@ -67,6 +73,39 @@ ecc_status hip_fail(ecc_ctx* ctx, hipError_t e, const char* what)
 {
     ctx->err = std::string(what) + ": " + hipGetErrorString(e);
     return e == hipErrorOutOfMemory ? ECC_ERR_OUT_OF_MEMORY : ECC_ERR_DEVICE;
+}
+
+constexpr size_t kTimingPairs = 4096;
+
+// Adds the durations of the recorded pairs to the tally (waits for them).
+ecc_status fold_timing(ecc_ctx* ctx)
+{
+    for (size_t i = 0; i < ctx->tused; ++i) {
+        hipError_t e = hipEventSynchronize(ctx->tev[2 * i + 1]);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize(timing)");
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, ctx->tev[2 * i], ctx->tev[2 * i + 1])) != hipSuccess)
+            return hip_fail(ctx, e, "hipEventElapsedTime");
+        ctx->tms += ms;
+        ctx->tcount += 1;
+    }
+    ctx->tused = 0;
+    return ECC_OK;
+}
+
+// Runs `launch` (returning hipError_t) between a pair of timing events when the
+// context records kernel timing.
+template <class F>
+hipError_t timed_launch(ecc_ctx* ctx, hipStream_t s, F&& launch)
+{
+    if (!ctx->timing) return launch();
+    if (ctx->tused == kTimingPairs && fold_timing(ctx) != ECC_OK) return hipErrorUnknown;
+    hipError_t e = hipEventRecord(ctx->tev[2 * ctx->tused], s);
+    if (e != hipSuccess) return e;
+    if ((e = launch()) != hipSuccess) return e;
+    if ((e = hipEventRecord(ctx->tev[2 * ctx->tused + 1], s)) != hipSuccess) return e;
+    ctx->tused += 1;
+    return hipSuccess;
 }
 
 ecc_status ensure_ws(ecc_ctx* ctx, size_t bytes)
@@ -192,15 +231,14 @@ ecc::BinParams host_params(const Job& j, int32_t nbins)
         p.flat = (j.hi == j.lo) ? 1 : 0;
         // a flat range bins through scale = +inf (see key_of in the kernels)
         p.scale = p.flat ? HUGE_VAL : (double)nbins / (j.hi - j.lo);
+        p.base = p.flat ? std::nextafter(j.lo, HUGE_VAL) : j.lo;
     } else {
         const uint32_t ilo = (uint32_t)j.lo, ihi = (uint32_t)j.hi;
-        const uint64_t D = (uint64_t)(ihi - ilo) + 1u;
+        const uint32_t D = ihi - ilo + 1u;
         p.ilo = ilo;
         p.ihi = ihi;
-        p.q0 = (uint32_t)((uint64_t)nbins / D);
-        const uint64_t r = (uint64_t)nbins % D;
-        p.magic = (uint32_t)(((r << 32) / D) + 1u);
-        p.ident = ((uint64_t)nbins == D) ? 1 : 0;
+        p.ident = ((uint32_t)nbins == D) ? 1 : 0;
+        p.rcp = std::nextafter(1.0 / (double)D, HUGE_VAL);
     }
     return p;
 }
@@ -291,7 +329,8 @@ ecc_status enqueue_one(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t st
         L.bin_lo = b0;
         L.width = std::min<int32_t>(sz.window, nbins - b0);
         const bool last = b0 + L.width >= nbins;
-        if ((e = ecc::launch_ecc(L, stream)) != hipSuccess) return hip_fail(ctx, e, "ecc launch");
+        if ((e = timed_launch(ctx, stream, [&] { return ecc::launch_ecc(L, stream); })) != hipSuccess)
+            return hip_fail(ctx, e, "ecc launch");
         if ((e = ecc::launch_merge(L.partials, L.grid, L.width, L.bin_lo, (int64_t*)(base + sz.off_level2),
                                    j.out, nbins, counters, last, stream)) != hipSuccess)
             return hip_fail(ctx, e, "merge launch");
@@ -469,7 +508,8 @@ ecc_status enqueue_batch(ecc_ctx* ctx, const std::vector<Job>& jobs, int32_t nbi
             B.dtype = gr.dtype;
             B.grid = gr.grid;
             B.wg_seg = (const int32_t*)(d + lay.wg_seg) + gr.wg_seg_first;
-            if ((e = ecc::launch_ecc_batch(B, ctx->construction, stream)) != hipSuccess)
+            if ((e = timed_launch(ctx, stream, [&] { return ecc::launch_ecc_batch(B, ctx->construction, stream); })) !=
+                hipSuccess)
                 return hip_fail(ctx, e, "batch launch");
         }
         if ((e = ecc::launch_merge_batch(B, b0 + B.width >= nbins, stream)) != hipSuccess)
@@ -515,6 +555,7 @@ ecc_status ecc_destroy(ecc_ctx* ctx)
         if (ctx->ws) (void)hipFree(ctx->ws);
         if (ctx->staging) (void)hipHostFree(ctx->staging);
         if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
+        for (hipEvent_t ev : ctx->tev) (void)hipEventDestroy(ev);
     }
     delete ctx;
     return ECC_OK;
@@ -579,6 +620,50 @@ ecc_status ecc_compute_batch(ecc_ctx* ctx, const ecc_image* imgs, int32_t count,
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed");
     return enqueue_batch(ctx, jobs, nbins, (hipStream_t)hip_stream);
+}
+
+ecc_status ecc_set_kernel_timing(ecc_ctx* ctx, int32_t enable)
+{
+    if (!ctx) return ECC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed");
+    if (!enable) {
+        ctx->timing = false;
+        ctx->tused = 0;
+        ctx->tms = 0.0;
+        ctx->tcount = 0;
+        return ECC_OK;
+    }
+    if (ctx->tev.empty()) {
+        std::vector<hipEvent_t> ev(2 * kTimingPairs, nullptr);
+        for (size_t i = 0; i < ev.size(); ++i) {
+            hipError_t e = hipEventCreate(&ev[i]);
+            if (e != hipSuccess) {
+                for (size_t k = 0; k < i; ++k) (void)hipEventDestroy(ev[k]);
+                return hip_fail(ctx, e, "hipEventCreate(timing)");
+            }
+        }
+        ctx->tev.swap(ev);
+    }
+    ctx->timing = true;
+    return ECC_OK;
+}
+
+ecc_status ecc_kernel_time(ecc_ctx* ctx, double* total_ms, int64_t* launches)
+{
+    if (!ctx) return ECC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (!total_ms || !launches) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_kernel_time: null output pointer");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed");
+    ecc_status st = fold_timing(ctx);
+    if (st != ECC_OK) return st;
+    *total_ms = ctx->tms;
+    *launches = ctx->tcount;
+    ctx->tms = 0.0;
+    ctx->tcount = 0;
+    return ECC_OK;
 }
 
 }  // extern "C"

@@ -69,25 +69,32 @@ template <> struct ValT<DT_U8> { using T = uint8_t; };
 template <> struct ValT<DT_U16> { using T = uint16_t; };
 template <> struct ValT<DT_F32> { using T = float; };
 
-template <int DT>
-__device__ __forceinline__ uint32_t key_of(typename ValT<DT>::T v, const BinParams& p)
+// Key (4 * bin, the bin's LDS byte address) of one value, OR-ed with `oob`
+// (0, or ~0 for lanes outside the image, which makes the key the sentinel).
+// IDENT: integer data with nbins == hi - lo + 1, where the bin is the level.
+template <int DT, bool IDENT>
+__device__ __forceinline__ uint32_t key_of(typename ValT<DT>::T v, const BinParams& p, uint32_t oob)
 {
     if constexpr (DT == DT_F32) {
-        // clamp(floor(((double)x - lo) * scale), 0, nbins-1) without branches.  A
-        // flat range (hi == lo) carries scale = +inf: x > lo -> +inf -> nbins-1,
-        // x < lo -> -inf -> 0, x == lo -> 0*inf = NaN, which fmax turns into 0.
+        // clamp(floor(((double)x - lo) * scale), 0, nbins-1) without branches:
+        // fmin maps NaN to nbins-1 before fmax clamps from below.  A flat range
+        // (hi == lo) carries scale = +inf and base = the next double above lo, so
+        // x <= lo gives -inf -> 0, x > lo gives +inf or 0*inf = NaN -> nbins-1.
         const float x = v;
-        double t = __dmul_rn(__dsub_rn((double)x, p.lo), p.scale);
-        t = __builtin_fmax(t, 0.0);
+        double t = __dmul_rn(__dsub_rn((double)x, p.base), p.scale);
         t = __builtin_fmin(t, (double)(p.nbins - 1));
-        uint32_t b = (uint32_t)t;
-        b = (x != x) ? (uint32_t)(p.nbins - 1) : b;
-        return b << 2;
+        t = __builtin_fmax(t, 0.0);
+        return ((uint32_t)t << 2) | oob;
     } else {
         uint32_t a = (uint32_t)v;
         a = min(max(a, p.ilo), p.ihi) - p.ilo;
-        if (p.ident) return a << 2;   // nbins == hi - lo + 1
-        return (a * p.q0 + __umulhi(a, p.magic)) << 2;
+        if constexpr (IDENT) return (a << 2) | oob;
+        // floor(a * nbins / D): a * nbins < 2^32 is exact in double, and rcp is
+        // 1/D rounded up, so the product never falls below an integer it should
+        // reach and stays below the next one (a < D <= 65536).
+        const uint32_t n = __umul24(a, (uint32_t)p.nbins);
+        const uint32_t b = (uint32_t)__dmul_rn((double)n, p.rcp);
+        return (b << 2) | oob;
     }
 }
 
@@ -114,15 +121,18 @@ __device__ __forceinline__ BinParams params_from_keys(uint32_t lo_key, uint32_t 
     if (dtype == DT_F32) {
         p.flat = (dhi == dlo) ? 1 : 0;
         p.scale = p.flat ? __builtin_inf() : __ddiv_rn((double)nbins, __dsub_rn(dhi, dlo));
+        // next double above lo (lo is finite): the subtrahend of a flat range
+        const double up = dlo == 0.0 ? __longlong_as_double(1ll)
+                                     : __longlong_as_double(__double_as_longlong(dlo) + (dlo > 0.0 ? 1 : -1));
+        p.base = p.flat ? up : dlo;
     } else {
         const uint32_t ilo = (uint32_t)dlo, ihi = (uint32_t)dhi;
-        const uint64_t D = (uint64_t)(ihi - ilo) + 1u;
+        const uint32_t D = ihi - ilo + 1u;
         p.ilo = ilo;
         p.ihi = ihi;
-        p.q0 = (uint32_t)((uint64_t)nbins / D);
-        const uint64_t r = (uint64_t)nbins % D;
-        p.magic = (uint32_t)(((r << 32) / D) + 1u);
-        p.ident = ((uint64_t)nbins == D) ? 1 : 0;
+        p.ident = ((uint32_t)nbins == D) ? 1 : 0;
+        // 1/D rounded up: one step above the correctly rounded quotient
+        p.rcp = __longlong_as_double(__double_as_longlong(__ddiv_rn(1.0, (double)D)) + 1);
     }
     return p;
 }
@@ -313,20 +323,23 @@ __device__ __forceinline__ void flush_hist(const int32_t* hist, const EccLaunch&
     for (int j = threadIdx.x; j < L.width; j += blockDim.x) dst[j] = hist[j];
 }
 
-// Key of one loaded value; lanes outside the image (x_ok clear) get the sentinel.
-template <int DT>
-__device__ __forceinline__ uint32_t key_or_sentinel(typename ValT<DT>::T v, const BinParams& P, bool all_x,
-                                                    bool x_ok)
-{
-    const uint32_t k = key_of<DT>(v, P);
-    return (all_x || x_ok) ? k : kSentinel;
-}
+// A flag the whole wave shares (the binning parameters may come from device
+// memory, which the compiler cannot prove uniform); branching on it must not
+// make the code behind the branch divergent.
+__device__ __forceinline__ bool uniform_flag(int32_t f) { return __builtin_amdgcn_readfirstlane(f) != 0; }
 
 // Raw buffer loads: one 32-bit per-lane byte offset (the column) plus one scalar
 // byte offset (the row) against a resource whose base is the brick's first row.
+// The base is the same for the whole wave; reading it back from the first lane
+// lets the compiler keep the resource in scalar registers (otherwise it may not
+// prove uniformity and wraps every load in a loop over distinct resources).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_at(const void* base)
 {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, -1, 0x00020000);
+    const uint64_t a = (uint64_t)base;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));
+    void* u = (void*)(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(u, (short)0, -1, 0x00020000);
 }
 
 template <typename T> __device__ __forceinline__ T buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
@@ -392,10 +405,10 @@ __device__ __forceinline__ void plane_step(const uint32_t (&Bc)[NR + 2], const u
 // The planes of one 3D brick.  FULL: every row of the brick and its halo lies
 // inside the image (no per-row checks).  Plane z+2 is being loaded while plane z
 // is processed.
-template <int DT, int CONS, bool WIN, bool FULL>
+template <int DT, int CONS, bool WIN, bool FULL, bool IDENT>
 __device__ __forceinline__ void brick_3d(const EccLaunch& L, const BinParams& P, const HistRef& H, int64_t y0,
-                                         int64_t z0, int64_t zend, uint32_t xob, bool x_ok, bool all_x,
-                                         uint64_t own_x, int rows_owned, int r_lo, int r_hi)
+                                         int64_t z0, int64_t zend, uint32_t xob, uint32_t oob, uint64_t own_x,
+                                         int rows_owned, int r_lo, int r_hi)
 {
     constexpr int NR = kRows3;
     using T = typename ValT<DT>::T;
@@ -416,7 +429,7 @@ __device__ __forceinline__ void brick_3d(const EccLaunch& L, const BinParams& P,
     auto keys = [&](const T (&raw)[NR + 2], uint32_t (&B)[NR + 2]) {
 #pragma unroll
         for (int r = 0; r < NR + 2; ++r)
-            B[r] = row_ok(r) ? key_or_sentinel<DT>(raw[r], P, all_x, x_ok) : kSentinel;
+            B[r] = row_ok(r) ? key_of<DT, IDENT>(raw[r], P, oob) : kSentinel;
     };
 
     uint32_t Bc[NR + 2], Bn[NR + 2];
@@ -456,44 +469,78 @@ __device__ __forceinline__ void brick_3d(const EccLaunch& L, const BinParams& P,
 
 // The rows [y0, yend) of one 2D brick for one wave: rows are streamed in chunks
 // of kChunk2, the next chunk loading while the current one is processed.
-template <int DT, int CONS, bool WIN>
-__device__ __forceinline__ void brick_2d(const void* data, int64_t n1, int64_t n2, const BinParams& P,
-                                         const HistRef& H, int64_t y0, int64_t yend, uint32_t xo, bool x_ok,
-                                         bool all_x, uint64_t own_x)
+// Row indices are 32-bit (the scalar unit compares 32-bit values only; 64-bit
+// loop bounds would move the loop, and every mask derived from it, to vector
+// registers).  Rows are at most 2^31, so y + 2 * kChunk2 does not wrap.
+template <int DT, int CONS, bool WIN, bool IDENT>
+__device__ __forceinline__ void brick_2d(const void* data, uint32_t n1, int64_t n2, const BinParams& P,
+                                         const HistRef& H, uint32_t y0, uint32_t yend, uint32_t xo, uint32_t oob,
+                                         uint64_t own_x)
 {
-    constexpr int CH = kChunk2;
+    constexpr uint32_t CH = kChunk2;
     using T = typename ValT<DT>::T;
     const T* __restrict__ img = (const T*)data;
-    auto key_at = [&](int64_t y) -> uint32_t {
-        if (y < 0 || y >= n1) return kSentinel;
-        return key_or_sentinel<DT>(img[y * n2 + xo], P, all_x, x_ok);
-    };
     const uint32_t row_bytes = (uint32_t)(n2 * (int64_t)sizeof(T));
     const uint32_t xob = xo * (uint32_t)sizeof(T);
     // rows ys .. ys+CH-1 (those inside the image)
-    auto load_chunk = [&](int64_t ys, T (&raw)[CH]) {
-        const __amdgpu_buffer_rsrc_t rs = rsrc_at(img + ys * n2);
+    auto load_chunk = [&](uint32_t ys, T (&raw)[CH]) {
+        const __amdgpu_buffer_rsrc_t rs = rsrc_at(img + (int64_t)ys * n2);
         uint32_t soff = 0;
 #pragma unroll
-        for (int k = 0; k < CH; ++k) {
+        for (uint32_t k = 0; k < CH; ++k) {
             raw[k] = (ys + k < n1) ? buffer_load<T>(rs, xob, soff) : T(0);
             soff = advance(soff, row_bytes);
         }
     };
+    // the same when every row lies in the image (no per-row checks)
+    auto load_chunk_full = [&](uint32_t ys, T (&raw)[CH]) {
+        const __amdgpu_buffer_rsrc_t rs = rsrc_at(img + (int64_t)ys * n2);
+        uint32_t soff = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < CH; ++k) {
+            raw[k] = buffer_load<T>(rs, xob, soff);
+            soff = advance(soff, row_bytes);
+        }
+    };
     RowState s;
-    row_start(s, key_at(y0 - 1), key_at(y0));
+    {
+        const uint32_t above = y0 == 0 ? kSentinel : key_of<DT, IDENT>(img[(int64_t)(y0 - 1) * n2 + xo], P, oob);
+        row_start(s, above, key_of<DT, IDENT>(img[(int64_t)y0 * n2 + xo], P, oob));
+    }
     T raw[CH];
-    load_chunk(y0 + 1, raw);
-    for (int64_t y = y0; y < yend; y += CH) {
+    if (uniform_flag(y0 + CH < n1)) load_chunk_full(y0 + 1, raw);
+    else load_chunk(y0 + 1, raw);
+    for (uint32_t y = y0; y < yend; y += CH) {
+        // Uniform per chunk: the rows below (y+1 .. y+CH) all lie in the image,
+        // and the rows owned (y .. y+CH-1) all lie in the brick.  (Read back
+        // through uniform_flag: otherwise the compiler lowers these branches as
+        // divergent and moves the row masks out of scalar registers.)
+        const bool keys_full = uniform_flag(y + CH < n1);
+        const bool own_full = uniform_flag(y + CH <= yend);
         uint32_t b[CH];
+        if (keys_full) {
 #pragma unroll
-        for (int k = 0; k < CH; ++k)
-            b[k] = (y + 1 + k < n1) ? key_or_sentinel<DT>(raw[k], P, all_x, x_ok) : kSentinel;
-        if (y + CH < yend) load_chunk(y + CH + 1, raw);
+            for (uint32_t k = 0; k < CH; ++k) b[k] = key_of<DT, IDENT>(raw[k], P, oob);
+        } else {
 #pragma unroll
-        for (int k = 0; k < CH; ++k) {
-            const uint64_t own = (y + k < yend) ? own_x : 0ull;
-            row_step<CONS, +1, WIN>(s, b[k], own, H);
+            for (uint32_t k = 0; k < CH; ++k)
+                b[k] = (y + 1 + k < n1) ? key_of<DT, IDENT>(raw[k], P, oob) : kSentinel;
+        }
+        if (uniform_flag(y + CH < yend)) {
+            if (uniform_flag(y + 2 * CH < n1)) load_chunk_full(y + CH + 1, raw);
+            else load_chunk(y + CH + 1, raw);
+        }
+        if (own_full) {
+#pragma unroll
+            for (uint32_t k = 0; k < CH; ++k) row_step<CONS, +1, WIN, false>(s, b[k], own_x, H);
+        } else {
+            // rows past the brick run with no owned lanes (a branch around
+            // them here would make the compiler treat the row state as divergent)
+#pragma unroll
+            for (uint32_t k = 0; k < CH; ++k) {
+                const uint64_t own = (y + k < yend) ? own_x : 0ull;
+                row_step<CONS, +1, WIN, false>(s, b[k], own, H);
+            }
         }
     }
 }
@@ -502,11 +549,13 @@ __device__ __forceinline__ void brick_2d(const void* data, int64_t n1, int64_t n
 // halo, lanes 1..62 own columns x0 + 62 * wave + lane - 1.
 struct WaveCols {
     bool active;       // the wave owns at least one column of the image
-    bool x_ok;         // this lane's column lies inside the image
-    bool all_x;        // every lane's column does
+    uint32_t oob;      // 0 if this lane's column lies inside the image, else ~0
     uint64_t own_x;    // owned lanes
     uint32_t xo;       // this lane's column, clamped into the image
 };
+
+// Index of this wave in its workgroup, known to the compiler to be wave-uniform.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
 __device__ __forceinline__ WaveCols wave_cols(int64_t x0, int wave, int64_t n2)
 {
@@ -514,9 +563,9 @@ __device__ __forceinline__ WaveCols wave_cols(int64_t x0, int wave, int64_t n2)
     const int64_t first = x0 + (int64_t)wave * 62;
     w.active = first < n2;
     const int64_t x = first - 1 + (int64_t)lane_id();
-    w.x_ok = x >= 0 && x < n2;
-    const uint64_t xmask = ballot(w.x_ok);
-    w.all_x = xmask == ~0ull;
+    const bool x_ok = x >= 0 && x < n2;
+    const uint64_t xmask = ballot(x_ok);
+    w.oob = x_ok ? 0u : ~0u;
     w.own_x = xmask & kOwnLanes;
     w.xo = (uint32_t)(x < 0 ? 0 : (x >= n2 ? n2 - 1 : x));
     return w;
@@ -530,7 +579,7 @@ __device__ __forceinline__ void run_brick_3d(const EccLaunch& L, const BinParams
     constexpr int NR = kRows3;
     using T = typename ValT<DT>::T;
     const int64_t n0 = L.g.n0, n1 = L.g.n1, n2 = L.g.n2;
-    const WaveCols w = wave_cols((int64_t)xc * chunk, (int)(threadIdx.x >> 6), n2);
+    const WaveCols w = wave_cols((int64_t)xc * chunk, wave_id(), n2);
     if (!w.active) return;
     const uint32_t xob = w.xo * (uint32_t)sizeof(T);
     const int64_t y0 = (int64_t)yb * NR;
@@ -540,10 +589,14 @@ __device__ __forceinline__ void run_brick_3d(const EccLaunch& L, const BinParams
     // rows r in [r_lo, r_hi) of the brick (row r is y0 - 1 + r) lie inside the image
     const int r_lo = (y0 == 0) ? 1 : 0;
     const int r_hi = (int)((n1 - (y0 - 1)) < NR + 2 ? (n1 - (y0 - 1)) : NR + 2);
-    if (r_lo == 0 && r_hi == NR + 2)
-        brick_3d<DT, CONS, WIN, true>(L, P, H, y0, z0, zend, xob, w.x_ok, w.all_x, w.own_x, rows_owned, r_lo, r_hi);
-    else
-        brick_3d<DT, CONS, WIN, false>(L, P, H, y0, z0, zend, xob, w.x_ok, w.all_x, w.own_x, rows_owned, r_lo, r_hi);
+    const bool full = r_lo == 0 && r_hi == NR + 2;
+    if (DT != DT_F32 && uniform_flag(P.ident)) {
+        if (full) brick_3d<DT, CONS, WIN, true, true>(L, P, H, y0, z0, zend, xob, w.oob, w.own_x, rows_owned, r_lo, r_hi);
+        else brick_3d<DT, CONS, WIN, false, true>(L, P, H, y0, z0, zend, xob, w.oob, w.own_x, rows_owned, r_lo, r_hi);
+    } else {
+        if (full) brick_3d<DT, CONS, WIN, true, false>(L, P, H, y0, z0, zend, xob, w.oob, w.own_x, rows_owned, r_lo, r_hi);
+        else brick_3d<DT, CONS, WIN, false, false>(L, P, H, y0, z0, zend, xob, w.oob, w.own_x, rows_owned, r_lo, r_hi);
+    }
 }
 
 // One 2D workgroup brick (x-chunk xc, row block yb) for this wave.
@@ -552,11 +605,14 @@ __device__ __forceinline__ void run_brick_2d(const EccLaunch& L, const BinParams
                                              int64_t chunk, uint32_t xc, uint32_t yb)
 {
     const int64_t n1 = L.g.n1, n2 = L.g.n2;
-    const WaveCols w = wave_cols((int64_t)xc * chunk, (int)(threadIdx.x >> 6), n2);
+    const WaveCols w = wave_cols((int64_t)xc * chunk, wave_id(), n2);
     if (!w.active) return;
-    const int64_t y0 = (int64_t)yb * L.depth;
-    const int64_t yend = (y0 + L.depth < n1) ? y0 + L.depth : n1;
-    brick_2d<DT, CONS, WIN>(L.data, n1, n2, P, H, y0, yend, w.xo, w.x_ok, w.all_x, w.own_x);
+    const uint32_t y0 = yb * (uint32_t)L.depth;
+    const uint32_t yend = (int64_t)y0 + L.depth < n1 ? y0 + (uint32_t)L.depth : (uint32_t)n1;
+    if (DT != DT_F32 && uniform_flag(P.ident))
+        brick_2d<DT, CONS, WIN, true>(L.data, (uint32_t)n1, n2, P, H, y0, yend, w.xo, w.oob, w.own_x);
+    else
+        brick_2d<DT, CONS, WIN, false>(L.data, (uint32_t)n1, n2, P, H, y0, yend, w.xo, w.oob, w.own_x);
 }
 
 }  // namespace dev

@@ -12,21 +12,25 @@ enum : int32_t { CONS_VERTEX = 0, CONS_TOP = 1 };
 
 // Bin of a value (the library's reading of the paper's gray-level histogram
 // index for data that is not 0..255 integers):
-//   integer data: a = clamp(v, ilo, ihi) - ilo ; bin = a*q0 + floor(a*r/D) with
-//                 D = ihi-ilo+1, nbins = q0*D + r, the second term computed
-//                 exactly as umulhi(a, magic), magic = floor(r*2^32/D) + 1
-//                 (exact because a*D < 2^32);
+//   integer data: a = clamp(v, ilo, ihi) - ilo ; bin = floor(a * nbins / D),
+//                 D = ihi-ilo+1 (bin = a when nbins == D), computed as the
+//                 double product (a * nbins) * rcp with rcp = 1/D rounded up,
+//                 which is exact because a * nbins < 2^32 and D <= 65536;
 //   float data:   NaN -> nbins-1; flat range -> (x > hi ? nbins-1 : 0);
 //                 otherwise clamp(floor(((double)x - lo) * scale), 0, nbins-1),
-//                 scale = nbins / (hi - lo) (+inf for a flat range, which gives
-//                 the flat rule through the same formula).
+//                 scale = nbins / (hi - lo) (+inf for a flat range, which with
+//                 the next double above lo as subtrahend gives the flat rule
+//                 through the same formula).
 struct BinParams {
     int32_t dtype;
     int32_t nbins;
-    uint32_t ilo, ihi, q0, magic;
-    int32_t flat;     // float data, hi == lo
-    int32_t ident;    // integer data, nbins == D: bin = a
-    double lo, hi, scale;
+    uint32_t ilo, ihi;  // integer range
+    int32_t flat;       // float data, hi == lo
+    int32_t ident;      // integer data, nbins == D = hi - lo + 1: bin = level - lo
+    double lo, hi;      // the range used
+    double base;        // float data: subtrahend (lo, or the next double above lo if flat)
+    double scale;       // float data: nbins / (hi - lo), +inf if flat
+    double rcp;         // integer data: 1 / D rounded up
 };
 
 // Geometry of one image: n0 slowest.  For 2D images n0 is 1.

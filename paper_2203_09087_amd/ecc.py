@@ -31,7 +31,7 @@ CONSTRUCTIONS = {"vertex": ECC_VERTEX, "top": ECC_TOP}
 
 # Symbols declared in include/ecc.h.
 EXPORTED = ("ecc_create", "ecc_destroy", "ecc_last_error", "ecc_compute", "ecc_compute_ex",
-            "ecc_compute_batch")
+            "ecc_compute_batch", "ecc_set_kernel_timing", "ecc_kernel_time")
 
 
 class ecc_image(ctypes.Structure):
@@ -80,6 +80,10 @@ def load_library(path: str = LIB_PATH):
     lib.ecc_compute_ex.restype = ctypes.c_int
     lib.ecc_compute_batch.argtypes = [vp, ctypes.POINTER(ecc_image), i32, i32, vp]
     lib.ecc_compute_batch.restype = ctypes.c_int
+    lib.ecc_set_kernel_timing.argtypes = [vp, i32]
+    lib.ecc_set_kernel_timing.restype = ctypes.c_int
+    lib.ecc_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64p]
+    lib.ecc_kernel_time.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -117,6 +121,17 @@ def ecc_compute_ex(ctx: int, img: ecc_image, nbins: int, stream: int = 0) -> int
 def ecc_compute_batch(ctx: int, imgs, nbins: int, stream: int = 0) -> int:
     arr = (ecc_image * max(1, len(imgs)))(*imgs)
     return load_library().ecc_compute_batch(ctx, arr, len(imgs), int(nbins), stream)
+
+
+def ecc_set_kernel_timing(ctx: int, enable: int) -> int:
+    return load_library().ecc_set_kernel_timing(ctx, int(enable))
+
+
+def ecc_kernel_time(ctx: int):
+    """(status, total_ms, launches) of the histogram-kernel launches since the last read."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    st = load_library().ecc_kernel_time(ctx, ctypes.byref(ms), ctypes.byref(n))
+    return st, ms.value, n.value
 
 
 # ------------------------------------------------------ torch convenience
@@ -204,3 +219,13 @@ class Context:
         descs = [make_image(t, o, r) for t, o, r in zip(images, outs, value_ranges)]
         self._check(ecc_compute_batch(self.handle, descs, nbins, self._stream(stream)))
         return outs
+
+    def set_kernel_timing(self, enable: bool = True):
+        """Records HIP events around every histogram-kernel launch of later calls."""
+        self._check(ecc_set_kernel_timing(self.handle, 1 if enable else 0))
+
+    def kernel_time(self):
+        """(total_ms, launches) of the histogram kernel since the last read; waits for them."""
+        st, ms, n = ecc_kernel_time(self.handle)
+        self._check(st)
+        return ms, n

@@ -110,6 +110,22 @@ def test_float_specials(ctxs, oracle_mod, cons):
 
 
 @pytest.mark.parametrize("cons", CONS)
+def test_flat_ranges(ctxs, oracle_mod, cons):
+    """hi == lo: values <= lo go to bin 0, values above it and NaN to the last bin,
+    including lo = 0 (whose next double is subnormal), negative lo, and an
+    explicit lo that no float equals."""
+    tiny = np.float32(1e-45)             # smallest positive subnormal float
+    vals = np.array([0.0, -0.0, tiny, -tiny, 1.0, -1.0, np.nan, np.inf, -np.inf,
+                     0.1, np.nextafter(np.float32(0.1), np.float32(1)), -2.5,
+                     np.nextafter(np.float32(-2.5), np.float32(0)), np.float32(3.4e38)],
+                    dtype=np.float32)
+    rng = np.random.default_rng(301)
+    img = rng.choice(vals, size=(23, 70)).astype(np.float32)
+    for lo in (0.0, -2.5, 0.1, float(np.float32(0.1)), 3.4e38):
+        check(ctxs[cons], oracle_mod, img, 8, cons, rng=(lo, lo))
+
+
+@pytest.mark.parametrize("cons", CONS)
 def test_workload_small_2d(ctxs, oracle_mod, cons):
     """256 x 256 uint8 uniform noise, 256 bins (one per gray level)."""
     from paper_2203_09087_amd import synth
@@ -238,3 +254,33 @@ def test_invalid_arguments_enqueue_nothing(ctxs):
     assert ecc.ecc_compute_ex(h, good, 16) == ecc.ECC_OK
     torch.cuda.synchronize()
     assert out.cpu().tolist() == [1] * 16
+
+
+def test_kernel_timing_counts_launches_and_changes_nothing(ctxs):
+    """The timing hook counts one histogram launch per call and bin window, one per
+    dtype group and window of a batch, and leaves results untouched."""
+    from paper_2203_09087_amd import synth
+    ctx = ctxs["vertex"]
+    say("case: kernel timing, 64^3 u8 and a 3-image batch, 256 and 9000 bins")
+    img = to_dev(synth.smoothed_noise_u8((64, 64, 64), 2.0, 12))
+    plain = ctx.compute(img, 256)
+    wide = ctx.compute(img, 9000, value_range=(0, 255))
+    torch.cuda.synchronize()
+    ctx.set_kernel_timing(True)
+    try:
+        for _ in range(3):
+            got = ctx.compute(img, 256)
+        got_wide = ctx.compute(img, 9000, value_range=(0, 255))   # 3 windows of 4096 bins
+        f = torch.rand(20, 30, device="cuda", dtype=torch.float32)
+        outs = ctx.compute_batch([img, img[:5].contiguous(), f], 256)   # u8 and f32 groups
+        ms, n = ctx.kernel_time()
+        assert n == 3 + 3 + 2 and ms > 0.0
+        assert np.array_equal(got.cpu().numpy(), plain.cpu().numpy())
+        assert np.array_equal(got_wide.cpu().numpy(), wide.cpu().numpy())
+        assert np.array_equal(outs[0].cpu().numpy(), plain.cpu().numpy())
+        assert ctx.kernel_time() == (0.0, 0)
+    finally:
+        ctx.set_kernel_timing(False)
+    ctx.compute(img, 256, out=got)
+    ms, n = ctx.kernel_time()
+    assert n == 0
