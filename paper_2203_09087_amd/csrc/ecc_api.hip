@@ -278,7 +278,8 @@ Sizes plan_sizes(const ecc_ctx* ctx, const Job& j, int32_t nbins)
     }
     const int64_t bricks = ecc::wg_bricks(j.ndim, j.g, s.waves, s.depth);
     const bool windowed = nbins > ecc::kMaxLdsBins;
-    const int per_cu = std::min(2, ecc::resident_wgs_per_cu(j.ndim, j.dtype, ctx->construction, windowed, s.waves));
+    const int per_cu = std::min(j.ndim == 3 ? ECC_MAX_WGS_PER_CU_3D : ECC_MAX_WGS_PER_CU_2D,
+                                ecc::resident_wgs_per_cu(j.ndim, j.dtype, ctx->construction, windowed, s.waves));
     int64_t grid = std::min<int64_t>(bricks, (int64_t)ctx->cu_count * per_cu);
     grid = std::max<int64_t>(grid, std::min<int64_t>(bricks, (j.nvox >> 27) + 1));
     s.grid = (int)std::max<int64_t>(grid, 1);

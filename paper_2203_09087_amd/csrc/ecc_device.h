@@ -77,14 +77,16 @@ __device__ __forceinline__ uint32_t key_of(typename ValT<DT>::T v, const BinPara
 {
     if constexpr (DT == DT_F32) {
         // clamp(floor(((double)x - lo) * scale), 0, nbins-1) without branches:
-        // fmin maps NaN to nbins-1 before fmax clamps from below.  A flat range
+        // fmin maps NaN to nbins-1, and the saturating conversion clamps below.  A flat range
         // (hi == lo) carries scale = +inf and base = the next double above lo, so
         // x <= lo gives -inf -> 0, x > lo gives +inf or 0*inf = NaN -> nbins-1.
         const float x = v;
         double t = __dmul_rn(__dsub_rn((double)x, p.base), p.scale);
         t = __builtin_fmin(t, (double)(p.nbins - 1));
-        t = __builtin_fmax(t, 0.0);
-        return ((uint32_t)t << 2) | oob;
+        // the conversion saturates: negative values and -inf give 0
+        uint32_t b;
+        asm("v_cvt_u32_f64 %0, %1" : "=v"(b) : "v"(t));
+        return (b << 2) | oob;
     } else {
         uint32_t a = (uint32_t)v;
         a = min(max(a, p.ilo), p.ihi) - p.ilo;
@@ -172,27 +174,51 @@ __device__ __forceinline__ void block_minmax(uint32_t& lo, uint32_t& hi)
     hi = shi[0];
 }
 
-// Inclusive prefix sum of v[0..n) by one block of kThreads threads.
+// Inclusive prefix sum of v[0..n) by one block of kThreads threads.  The values
+// pass through LDS in chunks of kScanChunk: coalesced loads, a sequential scan
+// of kScanPer values per thread, a scan of the thread totals, coalesced stores.
+constexpr int kScanPer = 16;
+constexpr int kScanChunk = kThreads * kScanPer;
+
 __device__ __forceinline__ void block_scan_inplace(int64_t* v, int32_t n)
 {
-    __shared__ int64_t part[kThreads];
-    const int per = (n + kThreads - 1) / kThreads;
-    const int b = threadIdx.x * per;
-    const int e = min(n, b + per);
-    int64_t s = 0;
-    for (int i = b; i < e; ++i) s += v[i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 1; off < kThreads; off <<= 1) {
-        const int64_t add = (threadIdx.x >= (unsigned)off) ? part[threadIdx.x - off] : 0;
+    __shared__ int64_t buf[kScanChunk];
+    __shared__ int64_t tot[kThreads];
+    const int t = threadIdx.x;
+    int64_t carry = 0;
+    for (int32_t base = 0; base < n; base += kScanChunk) {
+        const int m = min(kScanChunk, n - base);
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            const int i = k * kThreads + t;
+            buf[i] = i < m ? v[base + i] : 0;
+        }
         __syncthreads();
-        part[threadIdx.x] += add;
+        int64_t run = 0;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            run += buf[t * kScanPer + k];
+            buf[t * kScanPer + k] = run;
+        }
+        tot[t] = run;
         __syncthreads();
-    }
-    int64_t acc = part[threadIdx.x] - s;
-    for (int i = b; i < e; ++i) {
-        acc += v[i];
-        v[i] = acc;
+        for (int off = 1; off < kThreads; off <<= 1) {
+            const int64_t add = t >= off ? tot[t - off] : 0;
+            __syncthreads();
+            tot[t] += add;
+            __syncthreads();
+        }
+        const int64_t before = carry + (t > 0 ? tot[t - 1] : 0);
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) buf[t * kScanPer + k] += before;
+        carry += tot[kThreads - 1];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            const int i = k * kThreads + t;
+            if (i < m) v[base + i] = buf[i];
+        }
+        __syncthreads();
     }
 }
 
@@ -204,12 +230,6 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 __device__ __forceinline__ uint32_t from_right(uint32_t v)
 {
     return __builtin_amdgcn_mov_dpp(v, 0x130 /* wave_shl:1 */, 0xF, 0xF, true);
-}
-
-// lane i <- lane i-1 (lane 0 gets 0; it is never owned)
-__device__ __forceinline__ uint32_t from_left(uint32_t v)
-{
-    return __builtin_amdgcn_mov_dpp(v, 0x138 /* wave_shr:1 */, 0xF, 0xF, true);
 }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
@@ -240,26 +260,29 @@ __device__ __forceinline__ int32_t add_bit(int32_t acc, uint64_t m)
 struct RowState {
     uint32_t c;        // keys of the current row
     uint32_t c_right;  // keys of the current row, one lane to the right
-    uint64_t fb;       // previous row: [above > current] per column
+    uint64_t fb;       // previous row: [above(x) > current(x)]
     uint64_t fbr;      // previous row: [above(x) > current(x+1)]
-    uint64_t fbl;      // previous row: [above(x) > current(x-1)]
+    uint64_t q;        // previous row: [current(x) >= above(x+1)]
 };
 
 __device__ __forceinline__ void row_start(RowState& s, uint32_t above, uint32_t cur)
 {
     s.c = cur;
     s.c_right = from_right(cur);
-    const uint32_t c_left = from_left(cur);
+    const uint32_t above_right = from_right(above);
     s.fb = ballot(above > cur);
     s.fbr = ballot(above > s.c_right);
-    s.fbl = ballot(above > c_left);
+    s.q = ballot(cur >= above_right);
 }
 
 struct HistRef {
-    int32_t* hist;     // LDS
+    int32_t* hist;     // LDS: kMaxLdsBins counters, then one spare word per lane
     uint32_t key_lo;   // 4 * first bin of the window
     uint32_t key_span; // 4 * window width
+    uint32_t spare;    // byte offset of this lane's spare word (absorbs adds that do not count)
 };
+
+__device__ __forceinline__ uint32_t spare_offset() { return (uint32_t)(kMaxLdsBins + lane_id()) * 4u; }
 
 __device__ __forceinline__ void hist_add(const HistRef& H, uint32_t key, int32_t v)
 {
@@ -273,15 +296,18 @@ __device__ __forceinline__ void row_step(RowState& s, uint32_t below, uint64_t o
 {
     const uint32_t c = s.c;
     const uint32_t b_right = from_right(below);
-    const uint32_t b_left = from_left(below);
+    // The four comparisons of this row pair.  The lower-left one comes out of q
+    // shifted by a lane, [c(x) > b(x-1)] = ~[b(x-1) >= c(x)], which saves moving
+    // the lower row to the right; the next row reads q itself as its upper-right
+    // comparison.
     const uint64_t fr = ballot(c > s.c_right);
     const uint64_t fb = ballot(c > below);
     const uint64_t fbr = ballot(c > b_right);
-    const uint64_t fbl = ballot(c > b_left);
+    const uint64_t q = ballot(below >= s.c_right);
     if (!CHECK || own) {
-        // vertex-comparison bits of the 8 neighbours
-        uint64_t er = fr, eb = fb, dbr = fbr, dbl = fbl;
-        uint64_t el = ~(fr << 1), et = ~s.fb, dtl = ~(s.fbr << 1), dtr = ~(s.fbl >> 1);
+        // vertex-comparison bits of the 8 neighbours (later voxels win ties)
+        uint64_t er = fr, eb = fb, dbr = fbr, dbl = ~(q << 1);
+        uint64_t el = ~(fr << 1), et = ~s.fb, dtl = ~(s.fbr << 1), dtr = s.q;
         if constexpr (CONS == CONS_TOP) {
             er = ~er; eb = ~eb; dbr = ~dbr; dbl = ~dbl;
             el = ~el; et = ~et; dtl = ~dtl; dtr = ~dtr;
@@ -294,16 +320,31 @@ __device__ __forceinline__ void row_step(RowState& s, uint32_t below, uint64_t o
         if constexpr (SIGN > 0) v = sub_bit(sub_bit(sub_bit(sub_bit(1, tt), tr), tb), tl);
         else v = add_bit(add_bit(add_bit(add_bit(-1, tt), tr), tb), tl);
         uint32_t key = c;
+#if ECC_ATOMIC_MODE == 0
+        // only lanes that own the voxel and carry a non-zero count
         bool hit = lane_bit(own) && v != 0;
         if constexpr (WIN) {
             key -= H.key_lo;
             hit = hit && key < H.key_span;
         }
         if (hit) hist_add(H, key, v);
+#else
+        // every lane adds; lanes that do not count add into their spare word
+  #if ECC_ATOMIC_MODE == 1
+        bool hit = lane_bit(own);
+  #else
+        bool hit = lane_bit(own) && v != 0;
+  #endif
+        if constexpr (WIN) {
+            key -= H.key_lo;
+            hit = hit && key < H.key_span;
+        }
+        hist_add(H, hit ? key : H.spare, v);
+#endif
     }
     s.fb = fb;
     s.fbr = fbr;
-    s.fbl = fbl;
+    s.q = q;
     s.c = below;
     s.c_right = b_right;
 }
@@ -323,10 +364,13 @@ __device__ __forceinline__ void flush_hist(const int32_t* hist, const EccLaunch&
     for (int j = threadIdx.x; j < L.width; j += blockDim.x) dst[j] = hist[j];
 }
 
-// A flag the whole wave shares (the binning parameters may come from device
-// memory, which the compiler cannot prove uniform); branching on it must not
-// make the code behind the branch divergent.
+// Values the whole wave shares, read back from the first lane so that the
+// compiler treats them as uniform: the binning parameters may come from device
+// memory, and brick coordinates come out of integer divisions that the compiler
+// expands into vector arithmetic.  Without this, branches on them are lowered
+// as divergent and the row masks that depend on them leave scalar registers.
 __device__ __forceinline__ bool uniform_flag(int32_t f) { return __builtin_amdgcn_readfirstlane(f) != 0; }
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
 
 // Raw buffer loads: one 32-bit per-lane byte offset (the column) plus one scalar
 // byte offset (the row) against a resource whose base is the brick's first row.
@@ -383,53 +427,61 @@ __device__ __forceinline__ void plane_step(const uint32_t (&Bc)[NR + 2], const u
 #pragma unroll
         for (int r = 1; r <= NR; ++r) {
             const uint64_t own = (FULL || r <= rows_owned) ? own_x : 0ull;
-            if constexpr (SA != 0) row_step<CONS, SA, WIN, !FULL>(sa, Bc[r + 1], own, H);
-            if constexpr (HASB) row_step<CONS, SB, WIN, !FULL>(sb, comb(r + 1), own, H);
+            if constexpr (SA != 0) row_step<CONS, SA, WIN, false>(sa, Bc[r + 1], own, H);
+            if constexpr (HASB) row_step<CONS, SB, WIN, false>(sb, comb(r + 1), own, H);
         }
     } else {
         if constexpr (SA != 0) {
             row_start(sa, Bc[0], Bc[1]);
 #pragma unroll
             for (int r = 1; r <= NR; ++r)
-                row_step<CONS, SA, WIN, !FULL>(sa, Bc[r + 1], (FULL || r <= rows_owned) ? own_x : 0ull, H);
+                row_step<CONS, SA, WIN, false>(sa, Bc[r + 1], (FULL || r <= rows_owned) ? own_x : 0ull, H);
         }
         if constexpr (HASB) {
             row_start(sb, comb(0), comb(1));
 #pragma unroll
             for (int r = 1; r <= NR; ++r)
-                row_step<CONS, SB, WIN, !FULL>(sb, comb(r + 1), (FULL || r <= rows_owned) ? own_x : 0ull, H);
+                row_step<CONS, SB, WIN, false>(sb, comb(r + 1), (FULL || r <= rows_owned) ? own_x : 0ull, H);
         }
     }
 }
 
-// The planes of one 3D brick.  FULL: every row of the brick and its halo lies
-// inside the image (no per-row checks).  Plane z+2 is being loaded while plane z
-// is processed.
+// The planes of one 3D brick.  Row r of the brick is image row y0 - 1 + r.
+// FULL: every row of the brick and its halo lies inside the image.  Otherwise
+// the rows outside [0, n1) read the nearest row inside (so every load is in
+// bounds) and take the sentinel key, and rows past the brick's owned rows count
+// nothing; both without branches, so boundary bricks cost about what inner ones
+// do.  Plane indices are 32-bit (see brick_2d).
 template <int DT, int CONS, bool WIN, bool FULL, bool IDENT>
 __device__ __forceinline__ void brick_3d(const EccLaunch& L, const BinParams& P, const HistRef& H, int64_t y0,
-                                         int64_t z0, int64_t zend, uint32_t xob, uint32_t oob, uint64_t own_x,
+                                         uint32_t z0, uint32_t zend, uint32_t xob, uint32_t oob, uint64_t own_x,
                                          int rows_owned, int r_lo, int r_hi)
 {
     constexpr int NR = kRows3;
     using T = typename ValT<DT>::T;
-    const int64_t n0 = L.g.n0, n1 = L.g.n1, n2 = L.g.n2;
-    const int64_t row_bytes = n2 * (int64_t)sizeof(T);
+    const uint32_t n0 = (uint32_t)L.g.n0;
+    const int64_t n1 = L.g.n1, n2 = L.g.n2;
+    const uint32_t row_bytes = (uint32_t)(n2 * (int64_t)sizeof(T));
     const char* img = (const char*)L.data;
+    // first row read: y0 - 1, or the first row inside the image
+    const int64_t ybase = y0 - 1 + (FULL ? 0 : r_lo);
 
-    auto row_ok = [&](int r) -> bool { return FULL || (r >= r_lo && r < r_hi); };
-    auto load_plane = [&](int64_t z, T (&raw)[NR + 2]) {
-        const __amdgpu_buffer_rsrc_t rs = rsrc_at(img + (z * n1 + (y0 - 1)) * row_bytes);
+    auto load_plane = [&](uint32_t z, T (&raw)[NR + 2]) {
+        const __amdgpu_buffer_rsrc_t rs = rsrc_at(img + ((int64_t)z * n1 + ybase) * (int64_t)row_bytes);
         uint32_t soff = 0;
 #pragma unroll
         for (int r = 0; r < NR + 2; ++r) {
-            raw[r] = row_ok(r) ? buffer_load<T>(rs, xob, soff) : T(0);
-            soff = advance(soff, (uint32_t)row_bytes);
+            raw[r] = buffer_load<T>(rs, xob, soff);
+            // advance while the next row still lies inside the image
+            if (FULL || (r >= r_lo && r + 1 < r_hi)) soff = advance(soff, row_bytes);
         }
     };
     auto keys = [&](const T (&raw)[NR + 2], uint32_t (&B)[NR + 2]) {
 #pragma unroll
-        for (int r = 0; r < NR + 2; ++r)
-            B[r] = row_ok(r) ? key_of<DT, IDENT>(raw[r], P, oob) : kSentinel;
+        for (int r = 0; r < NR + 2; ++r) {
+            const uint32_t outside = (FULL || (r >= r_lo && r < r_hi)) ? 0u : ~0u;
+            B[r] = key_of<DT, IDENT>(raw[r], P, oob | outside);
+        }
     };
 
     uint32_t Bc[NR + 2], Bn[NR + 2];
@@ -437,7 +489,7 @@ __device__ __forceinline__ void brick_3d(const EccLaunch& L, const BinParams& P,
     load_plane(z0, raw);
     keys(raw, Bc);
     if (ECC_PREFETCH2 && z0 + 1 < n0) load_plane(z0 + 1, raw);
-    for (int64_t z = z0; z < zend; ++z) {
+    for (uint32_t z = z0; z < zend; ++z) {
         const bool has1 = z + 1 < n0;
         if constexpr (ECC_PREFETCH2) {
             if (has1) keys(raw, Bn);
@@ -508,15 +560,13 @@ __device__ __forceinline__ void brick_2d(const void* data, uint32_t n1, int64_t 
         row_start(s, above, key_of<DT, IDENT>(img[(int64_t)y0 * n2 + xo], P, oob));
     }
     T raw[CH];
-    if (uniform_flag(y0 + CH < n1)) load_chunk_full(y0 + 1, raw);
+    if (y0 + CH < n1) load_chunk_full(y0 + 1, raw);
     else load_chunk(y0 + 1, raw);
     for (uint32_t y = y0; y < yend; y += CH) {
         // Uniform per chunk: the rows below (y+1 .. y+CH) all lie in the image,
-        // and the rows owned (y .. y+CH-1) all lie in the brick.  (Read back
-        // through uniform_flag: otherwise the compiler lowers these branches as
-        // divergent and moves the row masks out of scalar registers.)
-        const bool keys_full = uniform_flag(y + CH < n1);
-        const bool own_full = uniform_flag(y + CH <= yend);
+        // and the rows owned (y .. y+CH-1) all lie in the brick.
+        const bool keys_full = y + CH < n1;
+        const bool own_full = y + CH <= yend;
         uint32_t b[CH];
         if (keys_full) {
 #pragma unroll
@@ -526,8 +576,8 @@ __device__ __forceinline__ void brick_2d(const void* data, uint32_t n1, int64_t 
             for (uint32_t k = 0; k < CH; ++k)
                 b[k] = (y + 1 + k < n1) ? key_of<DT, IDENT>(raw[k], P, oob) : kSentinel;
         }
-        if (uniform_flag(y + CH < yend)) {
-            if (uniform_flag(y + 2 * CH < n1)) load_chunk_full(y + CH + 1, raw);
+        if (y + CH < yend) {
+            if (y + 2 * CH < n1) load_chunk_full(y + CH + 1, raw);
             else load_chunk(y + CH + 1, raw);
         }
         if (own_full) {
@@ -576,6 +626,9 @@ template <int DT, int CONS, bool WIN>
 __device__ __forceinline__ void run_brick_3d(const EccLaunch& L, const BinParams& P, const HistRef& H,
                                              int64_t chunk, uint32_t xc, uint32_t yb, uint32_t zb)
 {
+    xc = uniform_u32(xc);
+    yb = uniform_u32(yb);
+    zb = uniform_u32(zb);
     constexpr int NR = kRows3;
     using T = typename ValT<DT>::T;
     const int64_t n0 = L.g.n0, n1 = L.g.n1, n2 = L.g.n2;
@@ -584,8 +637,8 @@ __device__ __forceinline__ void run_brick_3d(const EccLaunch& L, const BinParams
     const uint32_t xob = w.xo * (uint32_t)sizeof(T);
     const int64_t y0 = (int64_t)yb * NR;
     const int rows_owned = (int)((n1 - y0) < NR ? (n1 - y0) : NR);
-    const int64_t z0 = (int64_t)zb * L.depth;
-    const int64_t zend = (z0 + L.depth < n0) ? z0 + L.depth : n0;
+    const uint32_t z0 = zb * (uint32_t)L.depth;
+    const uint32_t zend = ((int64_t)z0 + L.depth < n0) ? z0 + (uint32_t)L.depth : (uint32_t)n0;
     // rows r in [r_lo, r_hi) of the brick (row r is y0 - 1 + r) lie inside the image
     const int r_lo = (y0 == 0) ? 1 : 0;
     const int r_hi = (int)((n1 - (y0 - 1)) < NR + 2 ? (n1 - (y0 - 1)) : NR + 2);
@@ -604,6 +657,8 @@ template <int DT, int CONS, bool WIN>
 __device__ __forceinline__ void run_brick_2d(const EccLaunch& L, const BinParams& P, const HistRef& H,
                                              int64_t chunk, uint32_t xc, uint32_t yb)
 {
+    xc = uniform_u32(xc);
+    yb = uniform_u32(yb);
     const int64_t n1 = L.g.n1, n2 = L.g.n2;
     const WaveCols w = wave_cols((int64_t)xc * chunk, wave_id(), n2);
     if (!w.active) return;

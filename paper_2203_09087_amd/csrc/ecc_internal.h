@@ -44,10 +44,7 @@ constexpr int kMaxLdsBins = 4096;
 // Brick shapes of the wave kernels (64 x-lanes, 62 of them owned).  The
 // ECC_* macros exist for tuning builds; the defaults are the shipped shapes.
 #ifndef ECC_ROWS3
-#define ECC_ROWS3 16
-#endif
-#ifndef ECC_PLANES3
-#define ECC_PLANES3 32
+#define ECC_ROWS3 8
 #endif
 #ifndef ECC_CHUNK2
 #define ECC_CHUNK2 16
@@ -56,16 +53,24 @@ constexpr int kMaxLdsBins = 4096;
 #define ECC_PREFETCH2 0   // 3D: plane z+2 in flight while plane z is processed
 #endif
 #ifndef ECC_WAVES_PER_EU_3D
-#define ECC_WAVES_PER_EU_3D 5   // resident waves per SIMD the 3D kernels are compiled for
+#define ECC_WAVES_PER_EU_3D 7   // resident waves per SIMD the 3D kernels are compiled for
 #endif
 #ifndef ECC_WAVES_PER_EU_2D
 #define ECC_WAVES_PER_EU_2D 5   // resident waves per SIMD the 2D kernels are compiled for
+#endif
+#ifndef ECC_MAX_WGS_PER_CU_3D
+#define ECC_MAX_WGS_PER_CU_3D 2   // resident workgroups per CU a single 3D image launches
+#endif
+#ifndef ECC_MAX_WGS_PER_CU_2D
+#define ECC_MAX_WGS_PER_CU_2D 3   // resident workgroups per CU a single 2D image launches
+#endif
+#ifndef ECC_ATOMIC_MODE
+#define ECC_ATOMIC_MODE 1  // LDS adds: 0 exec-masked non-zero owned lanes; 1 all lanes, the rest to spare words; 2 select non-zero
 #endif
 #ifndef ECC_INTERLEAVE
 #define ECC_INTERLEAVE 0  // 3D: advance the two 2D problems of a plane row by row together
 #endif
 constexpr int kRows3 = ECC_ROWS3;      // rows per 3D brick
-constexpr int kPlanes3 = ECC_PLANES3;  // planes per 3D brick
 constexpr int kChunk2 = ECC_CHUNK2;    // rows loaded together in the 2D kernel
 // Waves per workgroup of the main kernels (x-chunk = waves * 62 columns).
 constexpr int kMaxWaves = 9;
@@ -83,7 +88,7 @@ struct EccLaunch {
     int64_t depth;                 // planes (3D) or rows (2D) per workgroup brick
     int32_t* partials;             // [grid][width] workgroup histograms
     int64_t* out;                  // the caller's output (VCEC window, zeroed by block 0)
-    uint32_t* counter;             // unused by the main kernels (kept 0 for the merge)
+    uint32_t* counter;             // the merge's counter (unused by the main kernels)
 };
 
 // ---------------------------------------------------------------- batches
@@ -150,11 +155,11 @@ hipError_t launch_params_from_minmax(const uint32_t* mm, int blocks, int dtype, 
                                      BinParams* out, hipStream_t s);
 hipError_t launch_ecc(const EccLaunch& L, hipStream_t s);
 // Sums the `rows` partial histograms into out[bin_lo..bin_lo+width) (through
-// `level2`, kMergeGroups*width int64 of scratch), re-arms the counters and, with
-// `scan`, prefix-sums out[0..nbins).  counters[0] is the brick counter of the
-// main kernel, counters[1] and counters[2..] belong to the merge.
-constexpr int kMergeGroups = 16;
-constexpr int kCounterWords = 256;   // >= 2 + kMaxLdsBins / 64
+// `level2`, kMergeGroups*width int64 of scratch) and, with `scan`, prefix-sums
+// out[0..nbins).  counters[0] is the merge's last-block counter, which the merge
+// re-arms.
+constexpr int kMergeGroups = 32;
+constexpr int kCounterWords = 256;
 hipError_t launch_merge(const int32_t* partials, int rows, int32_t width, int32_t bin_lo, int64_t* level2,
                         int64_t* out, int32_t nbins, uint32_t* counters, bool scan, hipStream_t s);
 

@@ -17,9 +17,9 @@ using namespace dev;
 template <int DT, int CONS, bool WIN>
 __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU_3D))) void k_ecc_3d(EccLaunch L)
 {
-    __shared__ int32_t hist[kMaxLdsBins];
+    __shared__ int32_t hist[kMaxLdsBins + 64];
     const BinParams P = L.params_dev ? *L.params_dev : L.params;
-    const HistRef H{hist, (uint32_t)L.bin_lo << 2, (uint32_t)L.width << 2};
+    const HistRef H{hist, (uint32_t)L.bin_lo << 2, (uint32_t)L.width << 2, spare_offset()};
     zero_hist(hist, L.width);
     const int64_t chunk = (int64_t)(blockDim.x >> 6) * 62;
     const uint32_t nxc = (uint32_t)((L.g.n2 + chunk - 1) / chunk);
@@ -35,9 +35,9 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
 template <int DT, int CONS, bool WIN>
 __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU_2D))) void k_ecc_2d(EccLaunch L)
 {
-    __shared__ int32_t hist[kMaxLdsBins];
+    __shared__ int32_t hist[kMaxLdsBins + 64];
     const BinParams P = L.params_dev ? *L.params_dev : L.params;
-    const HistRef H{hist, (uint32_t)L.bin_lo << 2, (uint32_t)L.width << 2};
+    const HistRef H{hist, (uint32_t)L.bin_lo << 2, (uint32_t)L.width << 2, spare_offset()};
     zero_hist(hist, L.width);
     const int64_t chunk = (int64_t)(blockDim.x >> 6) * 62;
     const uint32_t nxc = (uint32_t)((L.g.n2 + chunk - 1) / chunk);
@@ -97,10 +97,14 @@ __global__ __launch_bounds__(kThreads) void k_params(const uint32_t* mm, int blo
 // --------------------------------------------------------- merge and scan
 
 // Partial histograms -> VCEC window -> (optionally) ECC, without atomics on the
-// bins: block (bx, g) sums a contiguous group of partial rows for bins
-// bx*64..bx*64+63 into level2[g]; the last of the groups of a bin block adds the
-// group sums into out; the last bin block prefix-sums out[0..nbins) and re-arms
-// every counter for the next call.
+// Merge of the workgroup histograms, in two launches with no fence between
+// blocks of one launch (a device-scope release per block costs an L2 write-back
+// on every XCD that takes part):
+//   k_merge_groups: block (bx, g) sums rows [r0, r1) of group g for bins
+//                   bx*256 .. +255 into level2[g] (int64);
+//   k_merge_final:  block bx adds the groups of its bins into out; with `scan`
+//                   the last block to finish prefix-sums out[0..nbins) and
+//                   re-arms its counter.
 
 // True in every thread of the block that is the last of `total` to arrive.
 __device__ __forceinline__ bool last_to_arrive(uint32_t* counter, uint32_t total)
@@ -114,37 +118,34 @@ __device__ __forceinline__ bool last_to_arrive(uint32_t* counter, uint32_t total
     return last;
 }
 
-__global__ __launch_bounds__(kThreads) void k_merge(const int32_t* partials, int rows, int32_t width,
-                                                    int32_t bin_lo, int64_t* level2, int64_t* out,
-                                                    int32_t nbins, uint32_t* counters, int scan)
+__global__ __launch_bounds__(kThreads) void k_merge_groups(const int32_t* __restrict__ partials, int rows,
+                                                           int32_t width, int64_t* __restrict__ level2)
 {
-    __shared__ int64_t acc[kThreads];
-    const int col = threadIdx.x & 63, lane_row = threadIdx.x >> 6;
-    const int j = blockIdx.x * 64 + col;
+    const int j = blockIdx.x * kThreads + threadIdx.x;
     const int G = gridDim.y, g = blockIdx.y;
     const int r0 = (int)((int64_t)rows * g / G), r1 = (int)((int64_t)rows * (g + 1) / G);
+    if (j >= width) return;
     int64_t s = 0;
-    if (j < width)
-        for (int r = r0 + lane_row; r < r1; r += kWaves) s += partials[(size_t)r * (size_t)width + j];
-    acc[threadIdx.x] = s;
-    __syncthreads();
-    if (lane_row == 0 && j < width)
-        level2[(size_t)g * width + j] = acc[col] + acc[col + 64] + acc[col + 128] + acc[col + 192];
+#pragma unroll 8
+    for (int r = r0; r < r1; ++r) s += partials[(size_t)r * (size_t)width + j];
+    level2[(size_t)g * width + j] = s;
+}
 
-    if (!last_to_arrive(&counters[2 + blockIdx.x], (uint32_t)G)) return;
-    if (threadIdx.x < 64 && j < width) {
+__global__ __launch_bounds__(kThreads) void k_merge_final(const int64_t* __restrict__ level2, int groups,
+                                                          int32_t width, int32_t bin_lo, int64_t* out,
+                                                          int32_t nbins, uint32_t* counter, int scan)
+{
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    if (j < width) {
         int64_t t = 0;
-        for (int gg = 0; gg < G; ++gg) t += level2[(size_t)gg * width + j];
+#pragma unroll 8
+        for (int g = 0; g < groups; ++g) t += level2[(size_t)g * width + j];
         out[bin_lo + j] = t;
     }
-    if (threadIdx.x == 0) atomicExch(&counters[2 + blockIdx.x], 0u);
-
-    if (!last_to_arrive(&counters[1], gridDim.x)) return;
-    if (scan) block_scan_inplace(out, nbins);
-    if (threadIdx.x == 0) {
-        atomicExch(&counters[0], 0u);
-        atomicExch(&counters[1], 0u);
-    }
+    if (!scan) return;
+    if (!last_to_arrive(counter, gridDim.x)) return;
+    block_scan_inplace(out, nbins);
+    if (threadIdx.x == 0) atomicExch(counter, 0u);
 }
 
 }  // namespace
@@ -243,9 +244,14 @@ int resident_wgs_per_cu(int ndim, int dtype, int construction, bool windowed, in
 hipError_t launch_merge(const int32_t* partials, int rows, int32_t width, int32_t bin_lo, int64_t* level2,
                         int64_t* out, int32_t nbins, uint32_t* counters, bool scan, hipStream_t s)
 {
-    const dim3 grid((width + 63) / 64, (unsigned)(rows < kMergeGroups ? rows : kMergeGroups));
-    hipLaunchKernelGGL(k_merge, grid, dim3(kThreads), 0, s, partials, rows, width, bin_lo, level2, out,
-                       nbins, counters, scan ? 1 : 0);
+    const unsigned bx = (unsigned)((width + kThreads - 1) / kThreads);
+    const int groups = rows < kMergeGroups ? rows : kMergeGroups;
+    hipLaunchKernelGGL(k_merge_groups, dim3(bx, (unsigned)groups), dim3(kThreads), 0, s, partials, rows, width,
+                       level2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_merge_final, dim3(bx), dim3(kThreads), 0, s, level2, groups, width, bin_lo, out, nbins,
+                       counters, scan ? 1 : 0);
     return hipGetLastError();
 }
 
