@@ -263,7 +263,8 @@ Sizes plan_sizes(const ecc_ctx* ctx, const Job& j, int32_t nbins)
 {
     Sizes s;
     const int64_t cols = (j.g.n2 + 61) / 62;
-    s.waves = (int)(cols <= ecc::kMaxWaves ? cols : 8);
+    const int64_t max_waves = j.ndim == 3 ? ECC_MAX_WAVES_3D : ecc::kMaxWaves;
+    s.waves = (int)(cols <= max_waves ? cols : std::min<int64_t>(8, max_waves));
     const int64_t chunk = 62 * (int64_t)s.waves;
     const int64_t nxc = (j.g.n2 + chunk - 1) / chunk;
     const int64_t target = 2 * (int64_t)ctx->cu_count;

@@ -58,6 +58,9 @@ constexpr int kMaxLdsBins = 4096;
 #ifndef ECC_WAVES_PER_EU_2D
 #define ECC_WAVES_PER_EU_2D 5   // resident waves per SIMD the 2D kernels are compiled for
 #endif
+#ifndef ECC_MAX_WAVES_3D
+#define ECC_MAX_WAVES_3D 9   // waves per workgroup of a single 3D image (a whole row up to 558 columns)
+#endif
 #ifndef ECC_MAX_WGS_PER_CU_3D
 #define ECC_MAX_WGS_PER_CU_3D 2   // resident workgroups per CU a single 3D image launches
 #endif
@@ -68,7 +71,7 @@ constexpr int kMaxLdsBins = 4096;
 #define ECC_ATOMIC_MODE 1  // LDS adds: 0 exec-masked non-zero owned lanes; 1 all lanes, the rest to spare words; 2 select non-zero
 #endif
 #ifndef ECC_INTERLEAVE
-#define ECC_INTERLEAVE 0  // 3D: advance the two 2D problems of a plane row by row together
+#define ECC_INTERLEAVE 1  // 3D: advance the two 2D problems of a plane row by row together
 #endif
 constexpr int kRows3 = ECC_ROWS3;      // rows per 3D brick
 constexpr int kChunk2 = ECC_CHUNK2;    // rows loaded together in the 2D kernel
