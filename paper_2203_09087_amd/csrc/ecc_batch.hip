@@ -48,8 +48,8 @@ template <int DT, int CONS, bool WIN>
 __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU_3D)))
 void k_ecc_batch(BatchLaunch B)
 {
-    __shared__ int32_t hist[kMaxLdsBins + 64];
-    const HistRef H{hist, (uint32_t)B.bin_lo << 2, (uint32_t)B.width << 2, spare_offset()};
+    __shared__ int32_t hist[kLdsWords];
+    const HistRef H = hist_ref(hist, B.bin_lo, B.width);
     const int64_t chunk = (int64_t)(blockDim.x >> 6) * 62;
     const int s_end = B.wg_seg[blockIdx.x + 1];
     for (int si = B.wg_seg[blockIdx.x]; si < s_end; ++si) {
@@ -71,9 +71,7 @@ void k_ecc_batch(BatchLaunch B)
             else
                 run_brick_2d<DT, CONS, WIN>(L, P, H, chunk, bb % nxc, bb / nxc);
         }
-        __syncthreads();
-        int32_t* dst = B.partials + (size_t)S.slot * (size_t)B.width;
-        for (int j = threadIdx.x; j < B.width; j += blockDim.x) dst[j] = hist[j];
+        flush_hist(hist, B.partials + (size_t)S.slot * (size_t)B.width, B.width);
     }
 }
 

@@ -69,8 +69,10 @@ template <> struct ValT<DT_U8> { using T = uint8_t; };
 template <> struct ValT<DT_U16> { using T = uint16_t; };
 template <> struct ValT<DT_F32> { using T = float; };
 
-// Key (4 * bin, the bin's LDS byte address) of one value, OR-ed with `oob`
-// (0, or ~0 for lanes outside the image, which makes the key the sentinel).
+// Key (bin << kKeyShift, its LDS byte address) of one value, OR-ed with `oob`:
+// the lane's histogram copy (copy << 2), or ~0 for lanes outside the image,
+// which makes the key the sentinel.  Keys of one bin in different copies order
+// by copy; that refines the order of values without changing any cell's bin.
 // IDENT: integer data with nbins == hi - lo + 1, where the bin is the level.
 template <int DT, bool IDENT>
 __device__ __forceinline__ uint32_t key_of(typename ValT<DT>::T v, const BinParams& p, uint32_t oob)
@@ -86,17 +88,17 @@ __device__ __forceinline__ uint32_t key_of(typename ValT<DT>::T v, const BinPara
         // the conversion saturates: negative values and -inf give 0
         uint32_t b;
         asm("v_cvt_u32_f64 %0, %1" : "=v"(b) : "v"(t));
-        return (b << 2) | oob;
+        return (b << kKeyShift) | oob;
     } else {
         uint32_t a = (uint32_t)v;
         a = min(max(a, p.ilo), p.ihi) - p.ilo;
-        if constexpr (IDENT) return (a << 2) | oob;
+        if constexpr (IDENT) return (a << kKeyShift) | oob;
         // floor(a * nbins / D): a * nbins < 2^32 is exact in double, and rcp is
         // 1/D rounded up, so the product never falls below an integer it should
         // reach and stays below the next one (a < D <= 65536).
         const uint32_t n = __umul24(a, (uint32_t)p.nbins);
         const uint32_t b = (uint32_t)__dmul_rn((double)n, p.rcp);
-        return (b << 2) | oob;
+        return (b << kKeyShift) | oob;
     }
 }
 
@@ -236,6 +238,7 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_bal
 
 __device__ __forceinline__ bool lane_bit(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
+
 // acc - [lane bit of m]
 __device__ __forceinline__ int32_t sub_bit(int32_t acc, uint64_t m)
 {
@@ -276,13 +279,18 @@ __device__ __forceinline__ void row_start(RowState& s, uint32_t above, uint32_t 
 }
 
 struct HistRef {
-    int32_t* hist;     // LDS: kMaxLdsBins counters, then one spare word per lane
-    uint32_t key_lo;   // 4 * first bin of the window
-    uint32_t key_span; // 4 * window width
+    int32_t* hist;     // LDS: kReplicas * kMaxLdsBins counters, then one spare word per lane
+    uint32_t key_lo;   // key of the first bin of the window (copy 0)
+    uint32_t key_span; // keys in the window
     uint32_t spare;    // byte offset of this lane's spare word (absorbs adds that do not count)
 };
 
-__device__ __forceinline__ uint32_t spare_offset() { return (uint32_t)(kMaxLdsBins + lane_id()) * 4u; }
+__device__ __forceinline__ uint32_t spare_offset() { return (uint32_t)(kReplicas * kMaxLdsBins + lane_id()) * 4u; }
+
+__device__ __forceinline__ HistRef hist_ref(int32_t* hist, int32_t bin_lo, int32_t width)
+{
+    return HistRef{hist, (uint32_t)bin_lo << kKeyShift, (uint32_t)width << kKeyShift, spare_offset()};
+}
 
 __device__ __forceinline__ void hist_add(const HistRef& H, uint32_t key, int32_t v)
 {
@@ -295,15 +303,15 @@ template <int CONS, int SIGN, bool WIN, bool CHECK = true>
 __device__ __forceinline__ void row_step(RowState& s, uint32_t below, uint64_t own, const HistRef& H)
 {
     const uint32_t c = s.c;
-    const uint32_t b_right = from_right(below);
     // The four comparisons of this row pair.  The lower-left one comes out of q
     // shifted by a lane, [c(x) > b(x-1)] = ~[b(x-1) >= c(x)], which saves moving
-    // the lower row to the right; the next row reads q itself as its upper-right
+    // the lower row to the left; the next row reads q itself as its upper-right
     // comparison.
+    const uint32_t b_right = from_right(below);
     const uint64_t fr = ballot(c > s.c_right);
-    const uint64_t fb = ballot(c > below);
     const uint64_t fbr = ballot(c > b_right);
     const uint64_t q = ballot(below >= s.c_right);
+    const uint64_t fb = ballot(c > below);
     if (!CHECK || own) {
         // vertex-comparison bits of the 8 neighbours (later voxels win ties)
         uint64_t er = fr, eb = fb, dbr = fbr, dbl = ~(q << 1);
@@ -353,15 +361,20 @@ __device__ __forceinline__ void row_step(RowState& s, uint32_t below, uint64_t o
 
 __device__ __forceinline__ void zero_hist(int32_t* hist, int width)
 {
-    for (int j = threadIdx.x; j < width; j += blockDim.x) hist[j] = 0;
+    for (int j = threadIdx.x; j < kReplicas * width; j += blockDim.x) hist[j] = 0;
     __syncthreads();
 }
 
-__device__ __forceinline__ void flush_hist(const int32_t* hist, const EccLaunch& L)
+// Writes the workgroup histogram (copies summed) to dst[0..width).
+__device__ __forceinline__ void flush_hist(const int32_t* hist, int32_t* dst, int width)
 {
     __syncthreads();
-    int32_t* dst = L.partials + (size_t)blockIdx.x * (size_t)L.width;
-    for (int j = threadIdx.x; j < L.width; j += blockDim.x) dst[j] = hist[j];
+    for (int j = threadIdx.x; j < width; j += blockDim.x) {
+        int32_t t = 0;
+#pragma unroll
+        for (int r = 0; r < kReplicas; ++r) t += hist[j * kReplicas + r];
+        dst[j] = t;
+    }
 }
 
 // Values the whole wave shares, read back from the first lane so that the
@@ -599,7 +612,7 @@ __device__ __forceinline__ void brick_2d(const void* data, uint32_t n1, int64_t 
 // halo, lanes 1..62 own columns x0 + 62 * wave + lane - 1.
 struct WaveCols {
     bool active;       // the wave owns at least one column of the image
-    uint32_t oob;      // 0 if this lane's column lies inside the image, else ~0
+    uint32_t oob;      // this lane's histogram copy << 2 if its column lies inside the image, else ~0
     uint64_t own_x;    // owned lanes
     uint32_t xo;       // this lane's column, clamped into the image
 };
@@ -615,7 +628,7 @@ __device__ __forceinline__ WaveCols wave_cols(int64_t x0, int wave, int64_t n2)
     const int64_t x = first - 1 + (int64_t)lane_id();
     const bool x_ok = x >= 0 && x < n2;
     const uint64_t xmask = ballot(x_ok);
-    w.oob = x_ok ? 0u : ~0u;
+    w.oob = x_ok ? (lane_id() % kReplicas) << 2 : ~0u;
     w.own_x = xmask & kOwnLanes;
     w.xo = (uint32_t)(x < 0 ? 0 : (x >= n2 ? n2 - 1 : x));
     return w;

@@ -17,9 +17,9 @@ using namespace dev;
 template <int DT, int CONS, bool WIN>
 __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU_3D))) void k_ecc_3d(EccLaunch L)
 {
-    __shared__ int32_t hist[kMaxLdsBins + 64];
+    __shared__ int32_t hist[kLdsWords];
     const BinParams P = L.params_dev ? *L.params_dev : L.params;
-    const HistRef H{hist, (uint32_t)L.bin_lo << 2, (uint32_t)L.width << 2, spare_offset()};
+    const HistRef H = hist_ref(hist, L.bin_lo, L.width);
     zero_hist(hist, L.width);
     const int64_t chunk = (int64_t)(blockDim.x >> 6) * 62;
     const uint32_t nxc = (uint32_t)((L.g.n2 + chunk - 1) / chunk);
@@ -28,16 +28,16 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
     const uint32_t nbricks = nxc * nyb * nzb;
     for (uint32_t brick = blockIdx.x; brick < nbricks; brick += gridDim.x)
         run_brick_3d<DT, CONS, WIN>(L, P, H, chunk, brick % nxc, (brick / nxc) % nyb, brick / (nxc * nyb));
-    flush_hist(hist, L);
+    flush_hist(hist, L.partials + (size_t)blockIdx.x * (size_t)L.width, L.width);
 }
 
 // 2D images.  A workgroup brick is a contiguous x-chunk x L.depth rows.
 template <int DT, int CONS, bool WIN>
 __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU_2D))) void k_ecc_2d(EccLaunch L)
 {
-    __shared__ int32_t hist[kMaxLdsBins + 64];
+    __shared__ int32_t hist[kLdsWords];
     const BinParams P = L.params_dev ? *L.params_dev : L.params;
-    const HistRef H{hist, (uint32_t)L.bin_lo << 2, (uint32_t)L.width << 2, spare_offset()};
+    const HistRef H = hist_ref(hist, L.bin_lo, L.width);
     zero_hist(hist, L.width);
     const int64_t chunk = (int64_t)(blockDim.x >> 6) * 62;
     const uint32_t nxc = (uint32_t)((L.g.n2 + chunk - 1) / chunk);
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
     const uint32_t nbricks = nxc * nyb;
     for (uint32_t brick = blockIdx.x; brick < nbricks; brick += gridDim.x)
         run_brick_2d<DT, CONS, WIN>(L, P, H, chunk, brick % nxc, brick / nxc);
-    flush_hist(hist, L);
+    flush_hist(hist, L.partials + (size_t)blockIdx.x * (size_t)L.width, L.width);
 }
 
 // ------------------------------------------------------------------- minmax
