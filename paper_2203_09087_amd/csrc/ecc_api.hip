@@ -289,7 +289,7 @@ Sizes plan_sizes(const ecc_ctx* ctx, const Job& j, int32_t nbins)
     s.off_params = kCounterBytes;
     s.off_mm = s.off_params + align_up(sizeof(ecc::BinParams));
     s.off_level2 = s.off_mm + align_up((size_t)kMinmaxBlocks * 2 * sizeof(uint32_t));
-    s.off_partials = s.off_level2 + align_up((size_t)ecc::kMergeGroups * (size_t)s.window * sizeof(int64_t));
+    s.off_partials = s.off_level2 + align_up(ecc::kLevel2Words * sizeof(int64_t));
     s.total = s.off_partials + align_up((size_t)s.grid * (size_t)s.window * sizeof(int32_t));
     return s;
 }
@@ -393,10 +393,10 @@ ecc_status enqueue_batch(ecc_ctx* ctx, const std::vector<Job>& jobs, int32_t nbi
         im.params = host_params(j, nbins);
         im.out = j.out;
         bricks[(size_t)i] = ecc::batch_bricks(im, waves);
-        // work of one brick: voxels visited times the 2D problems per voxel
-        const double cols = std::min<double>((double)j.g.n2, 62.0 * waves);
-        brick_cost[(size_t)i] = j.ndim == 3 ? 2.0 * cols * ecc::kRows3 * (double)im.depth
-                                            : 1.0 * cols * (double)im.depth;
+        // time of one brick: a team of wpb waves walks its rows (two 2D problems
+        // per row in 3D); W / wpb teams of a workgroup share one pass
+        const double teams = (double)(waves / im.wpb);
+        brick_cost[(size_t)i] = (j.ndim == 3 ? 2.0 * ecc::kRows3 : 1.0) * (double)im.depth / teams;
     }
     // One launch per dtype present; the bricks of its images, in order, are cut
     // into one contiguous run per workgroup with about equal work.

@@ -50,7 +50,7 @@ void k_ecc_batch(BatchLaunch B)
 {
     __shared__ int32_t hist[kLdsWords];
     const HistRef H = hist_ref(hist, B.bin_lo, B.width);
-    const int64_t chunk = (int64_t)(blockDim.x >> 6) * 62;
+    const int W = (int)(blockDim.x >> 6), wave = wave_id();
     const int s_end = B.wg_seg[blockIdx.x + 1];
     for (int si = B.wg_seg[blockIdx.x]; si < s_end; ++si) {
         const BatchSeg S = B.segs[si];
@@ -63,13 +63,20 @@ void k_ecc_batch(BatchLaunch B)
         L.g = I.g;
         L.depth = I.depth;
         zero_hist(hist, B.width);
+        // the workgroup's waves form W / wpb teams of wpb waves; team t takes
+        // bricks b0 + t, b0 + t + teams, ... (waves beyond the last team idle)
+        const int wpb = uniform_u32((uint32_t)I.wpb);
+        const int teams = W / wpb, team = wave / wpb, xw = wave - team * wpb;
+        const int64_t chunk = 62 * (int64_t)wpb;
         const uint32_t nxc = (uint32_t)I.nxc, nyb = (uint32_t)I.nyb;
-        for (int64_t b = S.b0; b < S.b1; ++b) {
-            const uint32_t bb = (uint32_t)b;
-            if (I.ndim == 3)
-                run_brick_3d<DT, CONS, WIN>(L, P, H, chunk, bb % nxc, (bb / nxc) % nyb, bb / (nxc * nyb));
-            else
-                run_brick_2d<DT, CONS, WIN>(L, P, H, chunk, bb % nxc, bb / nxc);
+        if (team < teams) {
+            for (int64_t b = S.b0 + team; b < S.b1; b += teams) {
+                const uint32_t bb = (uint32_t)b;
+                if (I.ndim == 3)
+                    run_brick_3d<DT, CONS, WIN>(L, P, H, chunk, bb % nxc, (bb / nxc) % nyb, bb / (nxc * nyb), xw);
+                else
+                    run_brick_2d<DT, CONS, WIN>(L, P, H, chunk, bb % nxc, bb / nxc, xw);
+            }
         }
         flush_hist(hist, B.partials + (size_t)S.slot * (size_t)B.width, B.width);
     }
@@ -116,7 +123,9 @@ hipError_t launch_batch_d(const BatchLaunch& B, hipStream_t s)
 
 int64_t batch_bricks(BatchImage& im, int waves)
 {
-    const int64_t chunk = 62 * (int64_t)waves;
+    const int64_t cols = (im.g.n2 + 61) / 62;
+    im.wpb = (int32_t)(cols < waves ? cols : waves);
+    const int64_t chunk = 62 * (int64_t)im.wpb;
     im.nxc = (int32_t)((im.g.n2 + chunk - 1) / chunk);
     if (im.ndim == 3) {
         im.depth = 8;

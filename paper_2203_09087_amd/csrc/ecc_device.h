@@ -635,9 +635,10 @@ __device__ __forceinline__ WaveCols wave_cols(int64_t x0, int wave, int64_t n2)
 }
 
 // One 3D workgroup brick (x-chunk xc, row block yb, plane block zb) for this wave.
+// `xw`: this wave's place among the waves of the brick (columns xw*62 ..).
 template <int DT, int CONS, bool WIN>
 __device__ __forceinline__ void run_brick_3d(const EccLaunch& L, const BinParams& P, const HistRef& H,
-                                             int64_t chunk, uint32_t xc, uint32_t yb, uint32_t zb)
+                                             int64_t chunk, uint32_t xc, uint32_t yb, uint32_t zb, int xw)
 {
     xc = uniform_u32(xc);
     yb = uniform_u32(yb);
@@ -645,7 +646,7 @@ __device__ __forceinline__ void run_brick_3d(const EccLaunch& L, const BinParams
     constexpr int NR = kRows3;
     using T = typename ValT<DT>::T;
     const int64_t n0 = L.g.n0, n1 = L.g.n1, n2 = L.g.n2;
-    const WaveCols w = wave_cols((int64_t)xc * chunk, wave_id(), n2);
+    const WaveCols w = wave_cols((int64_t)xc * chunk, xw, n2);
     if (!w.active) return;
     const uint32_t xob = w.xo * (uint32_t)sizeof(T);
     const int64_t y0 = (int64_t)yb * NR;
@@ -668,12 +669,12 @@ __device__ __forceinline__ void run_brick_3d(const EccLaunch& L, const BinParams
 // One 2D workgroup brick (x-chunk xc, row block yb) for this wave.
 template <int DT, int CONS, bool WIN>
 __device__ __forceinline__ void run_brick_2d(const EccLaunch& L, const BinParams& P, const HistRef& H,
-                                             int64_t chunk, uint32_t xc, uint32_t yb)
+                                             int64_t chunk, uint32_t xc, uint32_t yb, int xw)
 {
     xc = uniform_u32(xc);
     yb = uniform_u32(yb);
     const int64_t n1 = L.g.n1, n2 = L.g.n2;
-    const WaveCols w = wave_cols((int64_t)xc * chunk, wave_id(), n2);
+    const WaveCols w = wave_cols((int64_t)xc * chunk, xw, n2);
     if (!w.active) return;
     const uint32_t y0 = yb * (uint32_t)L.depth;
     const uint32_t yend = (int64_t)y0 + L.depth < n1 ? y0 + (uint32_t)L.depth : (uint32_t)n1;

@@ -113,9 +113,9 @@ struct BatchImage {
     Geom g;
     int32_t ndim, dtype;
     int32_t auto_range;   // parameters come from the min/max keys mm[2*i], mm[2*i+1]
-    int32_t nxc;          // x-chunks of 62 * waves columns
+    int32_t nxc;          // x-chunks of 62 * wpb columns
     int32_t nyb;          // row blocks (3D: kRows3 rows; 2D: `depth` rows)
-    int32_t pad;
+    int32_t wpb;          // waves per brick; a workgroup works on kBatchWaves / wpb bricks side by side
     int64_t depth;        // planes (3D) or rows (2D) per brick
     int64_t nvox;
     BinParams params;     // explicit or default range
@@ -160,7 +160,10 @@ hipError_t launch_ecc_batch(const BatchLaunch& B, int construction, hipStream_t 
 hipError_t launch_merge_batch(const BatchLaunch& B, bool scan, hipStream_t s);
 // Bricks of one batch image for the batched launch shape (sets nxc, nyb, depth).
 int64_t batch_bricks(BatchImage& im, int waves);
-constexpr int kBatchWaves = 4;   // waves per workgroup of the batched kernel
+#ifndef ECC_BATCH_WAVES
+#define ECC_BATCH_WAVES 9
+#endif
+constexpr int kBatchWaves = ECC_BATCH_WAVES;   // waves per workgroup of the batched kernel
 
 // Launchers (ecc_kernels.hip).  All enqueue on `s` and return the launch status.
 hipError_t launch_minmax(const void* data, int dtype, int64_t nvox, uint32_t* mm_out, int blocks,
@@ -169,10 +172,12 @@ hipError_t launch_params_from_minmax(const uint32_t* mm, int blocks, int dtype, 
                                      BinParams* out, hipStream_t s);
 hipError_t launch_ecc(const EccLaunch& L, hipStream_t s);
 // Sums the `rows` partial histograms into out[bin_lo..bin_lo+width) (through
-// `level2`, kMergeGroups*width int64 of scratch) and, with `scan`, prefix-sums
+// `level2`, kLevel2Words int64 of scratch) and, with `scan`, prefix-sums
 // out[0..nbins).  counters[0] is the merge's last-block counter, which the merge
 // re-arms.
 constexpr int kMergeGroups = 32;
+// group sums (kMergeGroups x window) and per-group totals of 256-bin blocks
+constexpr size_t kLevel2Words = (size_t)kMergeGroups * (kMaxLdsBins + kMaxLdsBins / 256);
 constexpr int kCounterWords = 256;
 hipError_t launch_merge(const int32_t* partials, int rows, int32_t width, int32_t bin_lo, int64_t* level2,
                         int64_t* out, int32_t nbins, uint32_t* counters, bool scan, hipStream_t s);

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
     const uint32_t nzb = (uint32_t)((L.g.n0 + L.depth - 1) / L.depth);
     const uint32_t nbricks = nxc * nyb * nzb;
     for (uint32_t brick = blockIdx.x; brick < nbricks; brick += gridDim.x)
-        run_brick_3d<DT, CONS, WIN>(L, P, H, chunk, brick % nxc, (brick / nxc) % nyb, brick / (nxc * nyb));
+        run_brick_3d<DT, CONS, WIN>(L, P, H, chunk, brick % nxc, (brick / nxc) % nyb, brick / (nxc * nyb), wave_id());
     flush_hist(hist, L.partials + (size_t)blockIdx.x * (size_t)L.width, L.width);
 }
 
@@ -44,7 +44,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
     const uint32_t nyb = (uint32_t)((L.g.n1 + L.depth - 1) / L.depth);
     const uint32_t nbricks = nxc * nyb;
     for (uint32_t brick = blockIdx.x; brick < nbricks; brick += gridDim.x)
-        run_brick_2d<DT, CONS, WIN>(L, P, H, chunk, brick % nxc, brick / nxc);
+        run_brick_2d<DT, CONS, WIN>(L, P, H, chunk, brick % nxc, brick / nxc, wave_id());
     flush_hist(hist, L.partials + (size_t)blockIdx.x * (size_t)L.width, L.width);
 }
 
@@ -96,15 +96,19 @@ __global__ __launch_bounds__(kThreads) void k_params(const uint32_t* mm, int blo
 
 // --------------------------------------------------------- merge and scan
 
-// Partial histograms -> VCEC window -> (optionally) ECC, without atomics on the
 // Merge of the workgroup histograms, in two launches with no fence between
 // blocks of one launch (a device-scope release per block costs an L2 write-back
 // on every XCD that takes part):
 //   k_merge_groups: block (bx, g) sums rows [r0, r1) of group g for bins
-//                   bx*256 .. +255 into level2[g] (int64);
-//   k_merge_final:  block bx adds the groups of its bins into out; with `scan`
-//                   the last block to finish prefix-sums out[0..nbins) and
-//                   re-arms its counter.
+//                   bx*256 .. +255 into level2[g] (int64), and with `btot` also
+//                   the total of those 256 sums into btot[g][bx];
+//   k_merge_final:  block bx adds the groups of its bins.  When the window is
+//                   the whole histogram and `scan` is set, every block scans its
+//                   own bins, offset by the totals of the blocks before it (from
+//                   btot), so the ECC needs no last-block pass.  Otherwise the
+//                   block writes the VCEC of its bins, and with `scan` the last
+//                   block to finish prefix-sums out[0..nbins) and re-arms its
+//                   counter (histograms wider than one LDS window).
 
 // True in every thread of the block that is the last of `total` to arrive.
 __device__ __forceinline__ bool last_to_arrive(uint32_t* counter, uint32_t total)
@@ -118,30 +122,73 @@ __device__ __forceinline__ bool last_to_arrive(uint32_t* counter, uint32_t total
     return last;
 }
 
+// Inclusive scan of one value per thread across the block; returns the
+// thread's scanned value, and the block total in *total.
+__device__ __forceinline__ int64_t block_scan_values(int64_t v, int64_t* total)
+{
+    __shared__ int64_t buf[kThreads];
+    const int t = threadIdx.x;
+    buf[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kThreads; off <<= 1) {
+        const int64_t add = t >= off ? buf[t - off] : 0;
+        __syncthreads();
+        buf[t] += add;
+        __syncthreads();
+    }
+    const int64_t r = buf[t];
+    *total = buf[kThreads - 1];
+    __syncthreads();
+    return r;
+}
+
 __global__ __launch_bounds__(kThreads) void k_merge_groups(const int32_t* __restrict__ partials, int rows,
-                                                           int32_t width, int64_t* __restrict__ level2)
+                                                           int32_t width, int64_t* __restrict__ level2,
+                                                           int64_t* __restrict__ btot)
 {
     const int j = blockIdx.x * kThreads + threadIdx.x;
     const int G = gridDim.y, g = blockIdx.y;
     const int r0 = (int)((int64_t)rows * g / G), r1 = (int)((int64_t)rows * (g + 1) / G);
-    if (j >= width) return;
     int64_t s = 0;
+    if (j < width) {
 #pragma unroll 8
-    for (int r = r0; r < r1; ++r) s += partials[(size_t)r * (size_t)width + j];
-    level2[(size_t)g * width + j] = s;
+        for (int r = r0; r < r1; ++r) s += partials[(size_t)r * (size_t)width + j];
+        level2[(size_t)g * width + j] = s;
+    }
+    if (btot) {
+        int64_t total;
+        block_scan_values(s, &total);
+        if (threadIdx.x == 0) btot[(size_t)g * gridDim.x + blockIdx.x] = total;
+    }
 }
 
-__global__ __launch_bounds__(kThreads) void k_merge_final(const int64_t* __restrict__ level2, int groups,
+__global__ __launch_bounds__(kThreads) void k_merge_final(const int64_t* __restrict__ level2,
+                                                          const int64_t* __restrict__ btot, int groups,
                                                           int32_t width, int32_t bin_lo, int64_t* out,
                                                           int32_t nbins, uint32_t* counter, int scan)
 {
     const int j = blockIdx.x * kThreads + threadIdx.x;
+    int64_t t = 0;
     if (j < width) {
-        int64_t t = 0;
 #pragma unroll 8
         for (int g = 0; g < groups; ++g) t += level2[(size_t)g * width + j];
-        out[bin_lo + j] = t;
     }
+    if (btot) {
+        // offset = sum of the bins of the blocks before this one
+        int64_t part = 0;
+        const int n = groups * (int)blockIdx.x;
+        for (int i = threadIdx.x; i < n; i += kThreads) {
+            const int g = i / (int)blockIdx.x, b = i - g * (int)blockIdx.x;
+            part += btot[(size_t)g * gridDim.x + b];
+        }
+        int64_t offset;
+        block_scan_values(part, &offset);
+        int64_t dummy;
+        const int64_t inc = block_scan_values(t, &dummy);
+        if (j < width) out[bin_lo + j] = offset + inc;
+        return;
+    }
+    if (j < width) out[bin_lo + j] = t;
     if (!scan) return;
     if (!last_to_arrive(counter, gridDim.x)) return;
     block_scan_inplace(out, nbins);
@@ -246,12 +293,14 @@ hipError_t launch_merge(const int32_t* partials, int rows, int32_t width, int32_
 {
     const unsigned bx = (unsigned)((width + kThreads - 1) / kThreads);
     const int groups = rows < kMergeGroups ? rows : kMergeGroups;
+    // one window holding every bin: blocks scan their own bins (see k_merge_final)
+    int64_t* btot = (scan && bin_lo == 0 && width == nbins) ? level2 + (size_t)kMergeGroups * width : nullptr;
     hipLaunchKernelGGL(k_merge_groups, dim3(bx, (unsigned)groups), dim3(kThreads), 0, s, partials, rows, width,
-                       level2);
+                       level2, btot);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_merge_final, dim3(bx), dim3(kThreads), 0, s, level2, groups, width, bin_lo, out, nbins,
-                       counters, scan ? 1 : 0);
+    hipLaunchKernelGGL(k_merge_final, dim3(bx), dim3(kThreads), 0, s, level2, btot, groups, width, bin_lo, out,
+                       nbins, counters, scan ? 1 : 0);
     return hipGetLastError();
 }
 
