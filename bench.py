@@ -327,10 +327,25 @@ def main():
             for a, o in zip(dev_imgs, outs):
                 ctx.compute(a, 256, out=o, stream=stream)
         ms_p, _ = timed_calls(per_image, stream, 5, 2)
-        mb, mp = float(np.mean(ms_b)), float(np.mean(ms_p))
+        # the same batch planned once and replayed from a captured HIP graph
+        plan = ctx.plan_batch(dev_imgs, 256, outs=outs)
+        gs = torch.cuda.Stream(dev)
+        gs.wait_stream(stream)
+        with torch.cuda.stream(gs):
+            plan.launch(stream=gs)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=gs):
+            plan.launch(stream=gs)
+        ms_g, _ = timed_calls(graph.replay, stream, 5, 2)
+        torch.cuda.synchronize()
+        plan.close()
+        mb, mp, mg = float(np.mean(ms_b)), float(np.mean(ms_p)), float(np.mean(ms_g))
         result["batched"] = {"images": len(imgs), "voxels": nv, "ms": round(mb, 3),
                              "images_per_s": round(len(imgs) / (mb * 1e-3), 1),
                              "gvox_s": round(nv / (mb * 1e-3) / 1e9, 2),
+                             "hbm_frac": round(nv / (mb * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                             "graph_replay_ms": round(mg, 3),
                              "per_image_calls_ms": round(mp, 3),
                              "speedup_vs_per_image": round(mp / mb, 3)}
         del dev_imgs, outs

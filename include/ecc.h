@@ -130,6 +130,29 @@ ecc_status ecc_compute_ex(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, voi
 ecc_status ecc_compute_batch(ecc_ctx* ctx, const ecc_image* imgs, int32_t count, int32_t nbins,
                              void* hip_stream);
 
+/* A planned batch (Sec. 5's many-files workload, kept on the device): the
+ * tables of ecc_compute_batch built once and copied to device memory owned by
+ * the plan, so that each launch enqueues kernels only -- no allocation, no host
+ * copy, no host synchronisation -- and may be captured into a HIP graph and
+ * replayed.  The plan keeps the images' and outputs' device addresses, shapes,
+ * dtypes and range modes; the image contents may change between launches (AUTO
+ * ranges are recomputed on every launch).  The caller keeps every image and
+ * output alive until the plan is destroyed.  Launches of one plan must not
+ * overlap in time (they share the plan's scratch); plans of one context follow
+ * the context's threading rule.  Results are identical to ecc_compute_batch.
+ * ecc_batch_plan_create: imgs is a HOST array of `count` (>= 1) descriptors, as
+ * for ecc_compute_batch; blocks until the tables are on the device.
+ * Errors: ECC_ERR_INVALID_ARG (bad descriptor or argument; *plan stays null),
+ * ECC_ERR_OUT_OF_MEMORY, ECC_ERR_DEVICE; messages via ecc_last_error(ctx). */
+typedef struct ecc_batch_plan ecc_batch_plan;
+ecc_status ecc_batch_plan_create(ecc_ctx* ctx, const ecc_image* imgs, int32_t count, int32_t nbins,
+                                 ecc_batch_plan** plan);
+/* Enqueues one run of the planned batch on hip_stream (asynchronous). */
+ecc_status ecc_batch_plan_launch(ecc_batch_plan* plan, void* hip_stream);
+/* Releases the plan's device memory; waits for nothing (the caller must have
+ * synchronized its launches).  A null plan is accepted and ignored. */
+ecc_status ecc_batch_plan_destroy(ecc_batch_plan* plan);
+
 /* Kernel timing, for measurement tools (the method itself does not need it).
  * With enable != 0, every later call on `ctx` records a pair of HIP events on its
  * stream around each launch of the histogram kernel (the voxel pass of Sec. 2.3

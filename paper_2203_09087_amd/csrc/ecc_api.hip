@@ -17,6 +17,8 @@
 #include "../../include/ecc.h"
 #include "ecc_internal.h"
 
+struct ecc_batch_plan;
+
 struct ecc_ctx {
     int device = 0;
     int construction = 0;
@@ -367,22 +369,45 @@ ecc_status ensure_staging(ecc_ctx* ctx, size_t bytes)
     return ECC_OK;
 }
 
-// Byte layout of the batch tables (identical in the pinned staging buffer and in
-// the device scratch) followed by the partial histogram rows on the device.
+// Byte layout of the batch tables, relative to the start of the tables (the
+// same in the pinned staging buffer and in device memory), followed by the
+// partial histogram rows on the device.
 struct BatchLayout {
     size_t images, segs, wg_seg, slot_off, slots, mm, pieces, tables_end, partials, total;
 };
 
-ecc_status enqueue_batch(ecc_ctx* ctx, const std::vector<Job>& jobs, int32_t nbins, hipStream_t stream)
+struct BatchGroup {
+    int dtype;
+    int grid;
+    size_t wg_seg_first;
+};
+
+// Host form of a batch: descriptor tables, workgroup segments and launch groups.
+struct BatchTables {
+    int count = 0;
+    int32_t nbins = 0, window = 0;
+    std::vector<ecc::BatchImage> images;
+    std::vector<ecc::BatchSeg> segs;
+    std::vector<int32_t> wg_seg, slot_off, slots;
+    std::vector<uint32_t> mm;
+    std::vector<ecc::BatchPiece> pieces;
+    std::vector<BatchGroup> groups;
+    BatchLayout lay;
+};
+
+void build_batch_tables(int cu_count, const std::vector<Job>& jobs, int32_t nbins, BatchTables& T)
 {
     const int count = (int)jobs.size();
     const int waves = ecc::kBatchWaves;
-    std::vector<ecc::BatchImage> images((size_t)count);
+    T.count = count;
+    T.nbins = nbins;
+    T.window = std::min<int32_t>(nbins, ecc::kMaxLdsBins);
+    T.images.assign((size_t)count, ecc::BatchImage{});
     std::vector<int64_t> bricks((size_t)count);
     std::vector<double> brick_cost((size_t)count);
     for (int i = 0; i < count; ++i) {
         const Job& j = jobs[(size_t)i];
-        ecc::BatchImage& im = images[(size_t)i];
+        ecc::BatchImage& im = T.images[(size_t)i];
         memset(&im, 0, sizeof im);
         im.data = j.data;
         im.g = j.g;
@@ -400,24 +425,20 @@ ecc_status enqueue_batch(ecc_ctx* ctx, const std::vector<Job>& jobs, int32_t nbi
     }
     // One launch per dtype present; the bricks of its images, in order, are cut
     // into one contiguous run per workgroup with about equal work.
-    std::vector<ecc::BatchSeg> segs;
-    std::vector<int32_t> wg_seg;
-    struct Group { int dtype; int grid; size_t wg_seg_first; };
-    std::vector<Group> groups;
     for (int dt = 0; dt < 3; ++dt) {
         double total = 0;
         int64_t nbr = 0;
         for (int i = 0; i < count; ++i)
-            if (images[(size_t)i].dtype == dt) { total += bricks[(size_t)i] * brick_cost[(size_t)i]; nbr += bricks[(size_t)i]; }
+            if (T.images[(size_t)i].dtype == dt) { total += bricks[(size_t)i] * brick_cost[(size_t)i]; nbr += bricks[(size_t)i]; }
         if (nbr == 0) continue;
-        const int G = (int)std::max<int64_t>(1, std::min<int64_t>(nbr, 2 * (int64_t)ctx->cu_count));
-        Group gr{dt, G, wg_seg.size()};
+        const int G = (int)std::max<int64_t>(1, std::min<int64_t>(nbr, 2 * (int64_t)cu_count));
+        BatchGroup gr{dt, G, T.wg_seg.size()};
         const double per = total / G;
         int wg = 0;
         double acc = 0;   // work assigned to workgroups 0..wg-1 plus the current one
-        wg_seg.push_back((int32_t)segs.size());
+        T.wg_seg.push_back((int32_t)T.segs.size());
         for (int i = 0; i < count; ++i) {
-            if (images[(size_t)i].dtype != dt) continue;
+            if (T.images[(size_t)i].dtype != dt) continue;
             int64_t b = 0;
             while (b < bricks[(size_t)i]) {
                 // bricks of image i that still fit in workgroup wg's share
@@ -425,88 +446,93 @@ ecc_status enqueue_batch(ecc_ctx* ctx, const std::vector<Job>& jobs, int32_t nbi
                 int64_t take = (int64_t)std::ceil(room / brick_cost[(size_t)i] - 1e-9);
                 if (wg == G - 1) take = bricks[(size_t)i] - b;
                 take = std::max<int64_t>(1, std::min<int64_t>(take, bricks[(size_t)i] - b));
-                segs.push_back(ecc::BatchSeg{i, (int32_t)segs.size(), b, b + take});
+                T.segs.push_back(ecc::BatchSeg{i, (int32_t)T.segs.size(), b, b + take});
                 acc += take * brick_cost[(size_t)i];
                 b += take;
                 if (acc >= per * (wg + 1) - 1e-9 && wg < G - 1) {
                     ++wg;
-                    wg_seg.push_back((int32_t)segs.size());
+                    T.wg_seg.push_back((int32_t)T.segs.size());
                 }
             }
         }
-        while ((int)(wg_seg.size() - gr.wg_seg_first) < G + 1) wg_seg.push_back((int32_t)segs.size());
-        groups.push_back(gr);
+        while ((int)(T.wg_seg.size() - gr.wg_seg_first) < G + 1) T.wg_seg.push_back((int32_t)T.segs.size());
+        T.groups.push_back(gr);
     }
-    const int nseg = (int)segs.size();
+    const int nseg = (int)T.segs.size();
     // partial rows of every image
-    std::vector<int32_t> slot_off((size_t)count + 1, 0), slots((size_t)nseg);
-    for (const auto& sg : segs) slot_off[(size_t)sg.image + 1]++;
-    for (int i = 0; i < count; ++i) slot_off[(size_t)i + 1] += slot_off[(size_t)i];
+    T.slot_off.assign((size_t)count + 1, 0);
+    T.slots.assign((size_t)nseg, 0);
+    for (const auto& sg : T.segs) T.slot_off[(size_t)sg.image + 1]++;
+    for (int i = 0; i < count; ++i) T.slot_off[(size_t)i + 1] += T.slot_off[(size_t)i];
     {
-        std::vector<int32_t> fill(slot_off.begin(), slot_off.end() - 1);
-        for (const auto& sg : segs) slots[(size_t)fill[(size_t)sg.image]++] = sg.slot;
+        std::vector<int32_t> fill(T.slot_off.begin(), T.slot_off.end() - 1);
+        for (const auto& sg : T.segs) T.slots[(size_t)fill[(size_t)sg.image]++] = sg.slot;
     }
     // pieces of the AUTO images for the min/max pass
-    std::vector<ecc::BatchPiece> pieces;
     const int64_t piece = int64_t(1) << 20;
     for (int i = 0; i < count; ++i)
-        if (images[(size_t)i].auto_range)
-            for (int64_t b = 0; b < images[(size_t)i].nvox; b += piece)
-                pieces.push_back(ecc::BatchPiece{i, 0, b, std::min(images[(size_t)i].nvox, b + piece)});
-    std::vector<uint32_t> mm((size_t)count * 2);
-    for (int i = 0; i < count; ++i) { mm[2 * (size_t)i] = 0xFFFFFFFFu; mm[2 * (size_t)i + 1] = 0u; }
+        if (T.images[(size_t)i].auto_range)
+            for (int64_t b = 0; b < T.images[(size_t)i].nvox; b += piece)
+                T.pieces.push_back(ecc::BatchPiece{i, 0, b, std::min(T.images[(size_t)i].nvox, b + piece)});
+    T.mm.assign((size_t)count * 2, 0u);
+    for (int i = 0; i < count; ++i) T.mm[2 * (size_t)i] = 0xFFFFFFFFu;
 
-    const int32_t window = std::min<int32_t>(nbins, ecc::kMaxLdsBins);
-    BatchLayout lay;
-    lay.images = kCounterBytes;   // the single-image counters stay untouched
-    lay.segs = align_up(lay.images + images.size() * sizeof(ecc::BatchImage));
-    lay.wg_seg = align_up(lay.segs + segs.size() * sizeof(ecc::BatchSeg));
-    lay.slot_off = align_up(lay.wg_seg + wg_seg.size() * sizeof(int32_t));
-    lay.slots = align_up(lay.slot_off + slot_off.size() * sizeof(int32_t));
-    lay.mm = align_up(lay.slots + slots.size() * sizeof(int32_t));
-    lay.pieces = align_up(lay.mm + mm.size() * sizeof(uint32_t));
-    lay.tables_end = align_up(lay.pieces + pieces.size() * sizeof(ecc::BatchPiece));
+    BatchLayout& lay = T.lay;
+    lay.images = 0;
+    lay.segs = align_up(lay.images + T.images.size() * sizeof(ecc::BatchImage));
+    lay.wg_seg = align_up(lay.segs + T.segs.size() * sizeof(ecc::BatchSeg));
+    lay.slot_off = align_up(lay.wg_seg + T.wg_seg.size() * sizeof(int32_t));
+    lay.slots = align_up(lay.slot_off + T.slot_off.size() * sizeof(int32_t));
+    lay.mm = align_up(lay.slots + T.slots.size() * sizeof(int32_t));
+    lay.pieces = align_up(lay.mm + T.mm.size() * sizeof(uint32_t));
+    lay.tables_end = align_up(lay.pieces + T.pieces.size() * sizeof(ecc::BatchPiece));
     lay.partials = lay.tables_end;
-    lay.total = lay.partials + align_up((size_t)nseg * (size_t)window * sizeof(int32_t));
+    lay.total = lay.partials + align_up((size_t)nseg * (size_t)T.window * sizeof(int32_t));
+}
 
-    ecc_status st = ensure_ws(ctx, lay.total);
-    if (st != ECC_OK) return st;
-    if ((st = ensure_staging(ctx, lay.tables_end - lay.images)) != ECC_OK) return st;
-    char* h = (char*)ctx->staging - lay.images;   // staging holds bytes [lay.images, lay.tables_end)
-    memcpy(h + lay.images, images.data(), images.size() * sizeof(ecc::BatchImage));
-    memcpy(h + lay.segs, segs.data(), segs.size() * sizeof(ecc::BatchSeg));
-    memcpy(h + lay.wg_seg, wg_seg.data(), wg_seg.size() * sizeof(int32_t));
-    memcpy(h + lay.slot_off, slot_off.data(), slot_off.size() * sizeof(int32_t));
-    memcpy(h + lay.slots, slots.data(), slots.size() * sizeof(int32_t));
-    memcpy(h + lay.mm, mm.data(), mm.size() * sizeof(uint32_t));
-    if (!pieces.empty()) memcpy(h + lay.pieces, pieces.data(), pieces.size() * sizeof(ecc::BatchPiece));
-    char* d = (char*)ctx->ws;
-    hipError_t e;
-    if ((e = hipMemcpyAsync(d + lay.images, h + lay.images, lay.tables_end - lay.images, hipMemcpyHostToDevice,
-                            stream)) != hipSuccess)
-        return hip_fail(ctx, e, "hipMemcpyAsync(batch tables)");
-    if ((e = hipEventRecord(ctx->staging_done, stream)) != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
-    ctx->staging_pending = true;
+// Copies the tables into host memory laid out as lay (bytes [0, tables_end)).
+void pack_batch_tables(const BatchTables& T, char* h)
+{
+    const BatchLayout& lay = T.lay;
+    memcpy(h + lay.images, T.images.data(), T.images.size() * sizeof(ecc::BatchImage));
+    memcpy(h + lay.segs, T.segs.data(), T.segs.size() * sizeof(ecc::BatchSeg));
+    memcpy(h + lay.wg_seg, T.wg_seg.data(), T.wg_seg.size() * sizeof(int32_t));
+    memcpy(h + lay.slot_off, T.slot_off.data(), T.slot_off.size() * sizeof(int32_t));
+    memcpy(h + lay.slots, T.slots.data(), T.slots.size() * sizeof(int32_t));
+    memcpy(h + lay.mm, T.mm.data(), T.mm.size() * sizeof(uint32_t));
+    if (!T.pieces.empty()) memcpy(h + lay.pieces, T.pieces.data(), T.pieces.size() * sizeof(ecc::BatchPiece));
+}
 
+// Enqueues the kernels of a batch whose tables are at device address d (layout
+// T.lay).  reset_mm: re-initialise the AUTO min/max keys on the device first
+// (plans; a per-call upload carries them already).
+ecc_status launch_batch_kernels(ecc_ctx* ctx, const BatchTables& T, char* d, bool reset_mm, hipStream_t stream)
+{
+    const BatchLayout& lay = T.lay;
     ecc::BatchLaunch B;
     memset(&B, 0, sizeof B);
     B.images = (const ecc::BatchImage*)(d + lay.images);
-    B.count = count;
+    B.count = T.count;
     B.segs = (const ecc::BatchSeg*)(d + lay.segs);
     B.slot_off = (const int32_t*)(d + lay.slot_off);
     B.slots = (const int32_t*)(d + lay.slots);
     B.mm = (uint32_t*)(d + lay.mm);
     B.partials = (int32_t*)(d + lay.partials);
-    B.nbins = nbins;
-    B.waves = waves;
-    B.windowed = window < nbins ? 1 : 0;
-    if ((e = ecc::launch_minmax_batch(B.images, (const ecc::BatchPiece*)(d + lay.pieces), (int)pieces.size(), B.mm,
-                                      stream)) != hipSuccess)
-        return hip_fail(ctx, e, "batch minmax launch");
-    for (int32_t b0 = 0; b0 < nbins; b0 += window) {
+    B.nbins = T.nbins;
+    B.waves = ecc::kBatchWaves;
+    B.windowed = T.window < T.nbins ? 1 : 0;
+    hipError_t e;
+    if (!T.pieces.empty()) {
+        if (reset_mm && (e = ecc::launch_mm_init(B.mm, T.count, stream)) != hipSuccess)
+            return hip_fail(ctx, e, "batch min/max init launch");
+        if ((e = ecc::launch_minmax_batch(B.images, (const ecc::BatchPiece*)(d + lay.pieces), (int)T.pieces.size(),
+                                          B.mm, stream)) != hipSuccess)
+            return hip_fail(ctx, e, "batch minmax launch");
+    }
+    for (int32_t b0 = 0; b0 < T.nbins; b0 += T.window) {
         B.bin_lo = b0;
-        B.width = std::min<int32_t>(window, nbins - b0);
-        for (const Group& gr : groups) {
+        B.width = std::min<int32_t>(T.window, T.nbins - b0);
+        for (const BatchGroup& gr : T.groups) {
             B.dtype = gr.dtype;
             B.grid = gr.grid;
             B.wg_seg = (const int32_t*)(d + lay.wg_seg) + gr.wg_seg_first;
@@ -514,13 +540,40 @@ ecc_status enqueue_batch(ecc_ctx* ctx, const std::vector<Job>& jobs, int32_t nbi
                 hipSuccess)
                 return hip_fail(ctx, e, "batch launch");
         }
-        if ((e = ecc::launch_merge_batch(B, b0 + B.width >= nbins, stream)) != hipSuccess)
+        if ((e = ecc::launch_merge_batch(B, b0 + B.width >= T.nbins, stream)) != hipSuccess)
             return hip_fail(ctx, e, "batch merge launch");
     }
     return ECC_OK;
 }
 
+ecc_status enqueue_batch(ecc_ctx* ctx, const std::vector<Job>& jobs, int32_t nbins, hipStream_t stream)
+{
+    BatchTables T;
+    build_batch_tables(ctx->cu_count, jobs, nbins, T);
+    // the tables follow the single-image counters in the scratch (never overwritten)
+    const size_t base = kCounterBytes;
+    ecc_status st = ensure_ws(ctx, base + T.lay.total);
+    if (st != ECC_OK) return st;
+    if ((st = ensure_staging(ctx, T.lay.tables_end)) != ECC_OK) return st;
+    pack_batch_tables(T, (char*)ctx->staging);
+    char* d = (char*)ctx->ws + base;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(d, ctx->staging, T.lay.tables_end, hipMemcpyHostToDevice, stream)) != hipSuccess)
+        return hip_fail(ctx, e, "hipMemcpyAsync(batch tables)");
+    if ((e = hipEventRecord(ctx->staging_done, stream)) != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
+    ctx->staging_pending = true;
+    return launch_batch_kernels(ctx, T, d, false, stream);
+}
+
 }  // namespace
+
+// A planned batch: its tables and partial rows live in device memory owned by
+// the plan, written once at creation.
+struct ecc_batch_plan {
+    ecc_ctx* ctx = nullptr;
+    BatchTables tables;
+    void* dbuf = nullptr;
+};
 
 extern "C" {
 
@@ -665,6 +718,66 @@ ecc_status ecc_kernel_time(ecc_ctx* ctx, double* total_ms, int64_t* launches)
     *launches = ctx->tcount;
     ctx->tms = 0.0;
     ctx->tcount = 0;
+    return ECC_OK;
+}
+
+ecc_status ecc_batch_plan_create(ecc_ctx* ctx, const ecc_image* imgs, int32_t count, int32_t nbins,
+                                 ecc_batch_plan** plan)
+{
+    if (!ctx) return ECC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (!plan) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_batch_plan_create: null plan pointer");
+    *plan = nullptr;
+    if (count < 1) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_batch_plan_create: count must be at least 1");
+    if (!imgs) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_batch_plan_create: null descriptor array");
+    std::vector<Job> jobs((size_t)count);
+    for (int32_t i = 0; i < count; ++i) {
+        char where[64];
+        snprintf(where, sizeof where, "ecc_batch_plan_create: image %d", i);
+        ecc_status st = validate(ctx, imgs[i], nbins, where, &jobs[i]);
+        if (st != ECC_OK) return st;
+    }
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed");
+    ecc_batch_plan* p = new (std::nothrow) ecc_batch_plan;
+    if (!p) return fail(ctx, ECC_ERR_OUT_OF_MEMORY, "ecc_batch_plan_create: out of host memory");
+    p->ctx = ctx;
+    build_batch_tables(ctx->cu_count, jobs, nbins, p->tables);
+    const BatchLayout& lay = p->tables.lay;
+    std::vector<char> host(lay.tables_end);
+    pack_batch_tables(p->tables, host.data());
+    hipError_t e = hipMalloc(&p->dbuf, lay.total);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(ctx, e, "hipMalloc(batch plan)");
+    }
+    if ((e = hipMemcpy(p->dbuf, host.data(), lay.tables_end, hipMemcpyHostToDevice)) != hipSuccess) {
+        (void)hipFree(p->dbuf);
+        delete p;
+        return hip_fail(ctx, e, "hipMemcpy(batch plan tables)");
+    }
+    *plan = p;
+    return ECC_OK;
+}
+
+ecc_status ecc_batch_plan_launch(ecc_batch_plan* plan, void* hip_stream)
+{
+    if (!plan) return ECC_ERR_INVALID_ARG;
+    ecc_ctx* ctx = plan->ctx;
+    ctx->err.clear();
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed");
+    return launch_batch_kernels(ctx, plan->tables, (char*)plan->dbuf, true, (hipStream_t)hip_stream);
+}
+
+ecc_status ecc_batch_plan_destroy(ecc_batch_plan* plan)
+{
+    if (!plan) return ECC_OK;
+    {
+        DeviceGuard g(plan->ctx->device);
+        if (plan->dbuf) (void)hipFree(plan->dbuf);
+    }
+    delete plan;
     return ECC_OK;
 }
 

@@ -32,6 +32,16 @@ __device__ void minmax_piece(const BatchImage& I, const BatchPiece& pc, uint32_t
     }
 }
 
+// Initial min/max keys of every image: lo = ~0, hi = 0.
+__global__ __launch_bounds__(kThreads) void k_mm_init(uint32_t* mm, int count)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i < count) {
+        mm[2 * i] = 0xFFFFFFFFu;
+        mm[2 * i + 1] = 0u;
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_minmax_batch(const BatchImage* images, const BatchPiece* pieces,
                                                            uint32_t* mm)
 {
@@ -142,6 +152,13 @@ hipError_t launch_minmax_batch(const BatchImage* images, const BatchPiece* piece
 {
     if (npieces <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_minmax_batch, dim3(npieces), dim3(kThreads), 0, s, images, pieces, mm);
+    return hipGetLastError();
+}
+
+hipError_t launch_mm_init(uint32_t* mm, int count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mm_init, dim3((count + kThreads - 1) / kThreads), dim3(kThreads), 0, s, mm, count);
     return hipGetLastError();
 }
 

@@ -155,6 +155,9 @@ struct BatchLaunch {
 hipError_t launch_minmax_batch(const BatchImage* images, const BatchPiece* pieces, int npieces, uint32_t* mm,
                                hipStream_t s);
 hipError_t launch_ecc_batch(const BatchLaunch& B, int construction, hipStream_t s);
+// Sets mm[2i] = ~0, mm[2i+1] = 0 for the `count` images (a kernel, so that the
+// enqueue stays valid inside a captured graph).
+hipError_t launch_mm_init(uint32_t* mm, int count, hipStream_t s);
 // Sums every image's partial rows into its out[bin_lo .. bin_lo+width) and, with
 // `scan`, prefix-sums its out[0 .. nbins).
 hipError_t launch_merge_batch(const BatchLaunch& B, bool scan, hipStream_t s);

@@ -31,7 +31,8 @@ CONSTRUCTIONS = {"vertex": ECC_VERTEX, "top": ECC_TOP}
 
 # Symbols declared in include/ecc.h.
 EXPORTED = ("ecc_create", "ecc_destroy", "ecc_last_error", "ecc_compute", "ecc_compute_ex",
-            "ecc_compute_batch", "ecc_set_kernel_timing", "ecc_kernel_time")
+            "ecc_compute_batch", "ecc_set_kernel_timing", "ecc_kernel_time", "ecc_batch_plan_create",
+            "ecc_batch_plan_launch", "ecc_batch_plan_destroy")
 
 
 class ecc_image(ctypes.Structure):
@@ -84,6 +85,12 @@ def load_library(path: str = LIB_PATH):
     lib.ecc_set_kernel_timing.restype = ctypes.c_int
     lib.ecc_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64p]
     lib.ecc_kernel_time.restype = ctypes.c_int
+    lib.ecc_batch_plan_create.argtypes = [vp, ctypes.POINTER(ecc_image), i32, i32, ctypes.POINTER(vp)]
+    lib.ecc_batch_plan_create.restype = ctypes.c_int
+    lib.ecc_batch_plan_launch.argtypes = [vp, vp]
+    lib.ecc_batch_plan_launch.restype = ctypes.c_int
+    lib.ecc_batch_plan_destroy.argtypes = [vp]
+    lib.ecc_batch_plan_destroy.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -132,6 +139,22 @@ def ecc_kernel_time(ctx: int):
     ms, n = ctypes.c_double(), ctypes.c_int64()
     st = load_library().ecc_kernel_time(ctx, ctypes.byref(ms), ctypes.byref(n))
     return st, ms.value, n.value
+
+
+def ecc_batch_plan_create(ctx: int, imgs, nbins: int):
+    """(status, plan handle or None)."""
+    arr = (ecc_image * max(1, len(imgs)))(*imgs)
+    h = ctypes.c_void_p()
+    st = load_library().ecc_batch_plan_create(ctx, arr, len(imgs), int(nbins), ctypes.byref(h))
+    return st, h.value
+
+
+def ecc_batch_plan_launch(plan: int, stream: int = 0) -> int:
+    return load_library().ecc_batch_plan_launch(plan, stream)
+
+
+def ecc_batch_plan_destroy(plan: int) -> int:
+    return load_library().ecc_batch_plan_destroy(plan)
 
 
 # ------------------------------------------------------ torch convenience
@@ -229,3 +252,40 @@ class Context:
         st, ms, n = ecc_kernel_time(self.handle)
         self._check(st)
         return ms, n
+
+    def plan_batch(self, images, nbins: int, value_ranges=None, outs=None):
+        """A BatchPlan over device tensors (kept alive by the plan object)."""
+        return BatchPlan(self, images, nbins, value_ranges, outs)
+
+
+class BatchPlan:
+    """A planned batch on a Context: launch() enqueues kernels only, so it can be
+    captured into a HIP graph.  Holds references to its images and outputs."""
+
+    def __init__(self, ctx: Context, images, nbins: int, value_ranges=None, outs=None):
+        import torch
+        self.ctx = ctx
+        self.images = list(images)
+        self.outs = outs if outs is not None else [
+            torch.empty(int(nbins), dtype=torch.int64, device=t.device) for t in self.images]
+        if value_ranges is None:
+            value_ranges = [None] * len(self.images)
+        descs = [make_image(t, o, r) for t, o, r in zip(self.images, self.outs, value_ranges)]
+        st, h = ecc_batch_plan_create(ctx.handle, descs, nbins)
+        ctx._check(st)
+        self.handle = h
+
+    def launch(self, stream=None):
+        self.ctx._check(ecc_batch_plan_launch(self.handle, self.ctx._stream(stream)))
+        return self.outs
+
+    def close(self):
+        if self.handle:
+            ecc_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

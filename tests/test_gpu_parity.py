@@ -284,3 +284,76 @@ def test_kernel_timing_counts_launches_and_changes_nothing(ctxs):
     ctx.compute(img, 256, out=got)
     ms, n = ctx.kernel_time()
     assert n == 0
+
+
+def _plan_inputs(seed):
+    from paper_2203_09087_amd import synth
+    rng = np.random.default_rng(seed)
+    imgs = [synth.smoothed_noise_u8((70, 90), 1.5, seed), synth.smoothed_noise_u8((12, 30, 41), 1.5, seed + 1),
+            rng.integers(0, 4096, (33, 600)).astype(np.uint16), rng.standard_normal((5, 9, 700)).astype(np.float32),
+            synth.smoothed_noise_u8((1, 1), 1.0, seed + 2)]
+    ranges = [None, (0, 255), "auto", "auto", None]
+    return imgs, ranges
+
+
+@pytest.mark.parametrize("cons", CONS)
+def test_batch_plan_matches_batch_and_oracle(ctxs, oracle_mod, cons):
+    """A planned batch gives the ECCs of ecc_compute_batch, launch after launch,
+    and follows changes of the image contents (AUTO ranges recomputed)."""
+    ctx = ctxs[cons]
+    imgs, ranges = _plan_inputs(40)
+    say(f"case: batch plan, {cons}, {len(imgs)} mixed images, 512 bins")
+    dev = [to_dev(a) for a in imgs]
+    plan = ctx.plan_batch(dev, 512, value_ranges=ranges)
+    try:
+        want_batch = [o.cpu().numpy() for o in ctx.compute_batch(dev, 512, value_ranges=ranges)]
+        for _ in range(3):
+            got = [o.cpu().numpy() for o in plan.launch()]
+            torch.cuda.synchronize()
+            for g, w in zip(got, want_batch):
+                assert np.array_equal(g, w)
+        for a, r, g in zip(imgs, ranges, got):
+            assert np.array_equal(g, oracle_mod.ecc(a, 512, cons, value_range=r))
+        # new contents in the same buffers
+        imgs2, _ = _plan_inputs(41)
+        for d, a in zip(dev, imgs2):
+            d.copy_(to_dev(a))
+        got2 = [o.cpu().numpy() for o in plan.launch()]
+        torch.cuda.synchronize()
+        for a, r, g in zip(imgs2, ranges, got2):
+            assert np.array_equal(g, oracle_mod.ecc(a, 512, cons, value_range=r))
+    finally:
+        plan.close()
+
+
+def test_batch_plan_graph_replay(ctxs, oracle_mod):
+    """A planned batch captured into a HIP graph: every replay, with eager work
+    and synchronisation between replays, equals the eager result."""
+    ctx = ctxs["vertex"]
+    imgs, ranges = _plan_inputs(42)
+    say("case: batch plan captured in a graph, 4 replays")
+    dev = [to_dev(a) for a in imgs]
+    plan = ctx.plan_batch(dev, 512, value_ranges=ranges)
+    try:
+        eager = [o.clone() for o in plan.launch()]
+        torch.cuda.synchronize()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            plan.launch(stream=s)          # warm-up on the capture stream
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            plan.launch(stream=s)
+        for k in range(4):
+            for o in plan.outs:
+                o.fill_(-1)
+            ctx.compute(dev[0], 64)            # unrelated eager work in between
+            g.replay()
+            torch.cuda.synchronize()
+            for o, e in zip(plan.outs, eager):
+                assert torch.equal(o, e), f"replay {k}"
+        for a, r, o in zip(imgs, ranges, plan.outs):
+            assert np.array_equal(o.cpu().numpy(), oracle_mod.ecc(a, 512, "vertex", value_range=r))
+    finally:
+        plan.close()
