@@ -223,6 +223,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-side", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--traffic", action="store_true", help="only the program the counter passes profile")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarize the two counter passes into the profiles folder")
@@ -256,6 +257,10 @@ def main():
     def step():
         ctx.compute(vol_d, nbins, value_range=(lo, hi), out=out, stream=stream)
 
+    shape = None
+    if not args.no_autotune:
+        log("autotuning the launch shape ...")
+        shape = ctx.autotune(vol_d, nbins, value_range=(lo, hi), reps=3, stream=stream)
     log("timing plain 512^3 ...")
     ms, wall = timed_calls(step, stream, args.steps, args.warmup)
     # The dominant kernel alone: the same steps again with HIP events recorded
@@ -293,6 +298,7 @@ def main():
                      "traffic": traffic_bytes(), "kernel_ms": round(k_avg, 4),
                      "launches": k_launches, "algorithmic_bytes": alg_bytes,
                      "step_ms_with_kernel_events": round(float(np.mean(ms_k)), 4)},
+        "launch_shape": shape,
         "p50_ms": round(float(np.percentile(ms, 50)), 4),
         "p99_ms": round(float(np.percentile(ms, 99)), 4),
         "wall_s": round(wall, 3),
@@ -307,6 +313,8 @@ def main():
         log("generating 16384^2 u16 GRF ...")
         img2 = synth.quantize_u16(synth.grf((16384, 16384), seed=4), 4096)
         img2_d = torch.from_numpy(img2.view(np.int16)).to(dev)
+        if not args.no_autotune:
+            ctx.autotune(img2_d, nbins, value_range="auto", reps=3, stream=stream)
         ms2, _ = timed_calls(lambda: ctx.compute(img2_d, nbins, value_range="auto", out=out,
                                                  stream=stream), stream, 20, 3)
         m2 = float(np.mean(ms2))

@@ -130,6 +130,29 @@ ecc_status ecc_compute_ex(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, voi
 ecc_status ecc_compute_batch(ecc_ctx* ctx, const ecc_image* imgs, int32_t count, int32_t nbins,
                              void* hip_stream);
 
+/* Launch shape of the single-image kernel: waves per workgroup (a workgroup
+ * covers waves * 62 consecutive columns), rows (2D) or planes (3D) per
+ * workgroup brick, and resident workgroups per CU aimed for.  `ms` is the mean
+ * time of one call measured by ecc_autotune. */
+typedef struct {
+    int32_t waves;
+    int32_t wgs_per_cu;
+    int64_t depth;
+    double ms;
+} ecc_launch_shape;
+
+/* Times a set of launch shapes for the image `img` on hip_stream (`reps` calls
+ * each, after one warm-up; the calls overwrite img->out) and makes `ctx` use the
+ * fastest for every later call on an image with the same ndim, dims, dtype and
+ * filtration and nbins on the same side of 4096.  Every shape gives the same
+ * ECC; only the time differs.  Blocks until the timing runs have finished.
+ * chosen (HOST pointer, may be null) receives the chosen shape.  Not for use
+ * during graph capture.
+ * Errors: as ecc_compute_ex, plus ECC_ERR_INVALID_ARG for reps outside
+ * [1, 1000]. */
+ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32_t reps, void* hip_stream,
+                        ecc_launch_shape* chosen);
+
 /* A planned batch (Sec. 5's many-files workload, kept on the device): the
  * tables of ecc_compute_batch built once and copied to device memory owned by
  * the plan, so that each launch enqueues kernels only -- no allocation, no host

@@ -10,6 +10,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <tuple>
 #include <new>
 #include <string>
 #include <vector>
@@ -29,6 +31,8 @@ struct ecc_ctx {
     size_t staging_bytes = 0;
     hipEvent_t staging_done = nullptr;   // recorded after the last copy out of `staging`
     bool staging_pending = false;
+    // launch shapes chosen by ecc_autotune, by image shape (see TuneKey)
+    std::map<std::tuple<int, int, int, int, int64_t, int64_t, int64_t>, ecc_launch_shape> tuned;
     // kernel timing (ecc_set_kernel_timing): event pairs around histogram launches
     bool timing = false;
     std::vector<hipEvent_t> tev;   // 2 * kTimingPairs events, created on enable
@@ -261,12 +265,27 @@ struct Sizes {
 //  - grid: at most two resident workgroups per CU (more concurrent bricks cost
 //    DRAM locality), at least enough that no workgroup histogram can reach 2^31
 //    (every voxel adds at most 6 in absolute value).
-Sizes plan_sizes(const ecc_ctx* ctx, const Job& j, int32_t nbins)
+using TuneKey = std::tuple<int, int, int, int, int64_t, int64_t, int64_t>;
+
+TuneKey tune_key(const ecc_ctx* ctx, const Job& j, int32_t nbins)
+{
+    return TuneKey{j.ndim, j.dtype, ctx->construction, nbins > ecc::kMaxLdsBins ? 1 : 0, j.g.n0, j.g.n1, j.g.n2};
+}
+
+// The default launch shape of an image (waves 0 / depth 0 / wgs 0 in a forced
+// shape mean "default" for that field).
+Sizes plan_sizes(const ecc_ctx* ctx, const Job& j, int32_t nbins, const ecc_launch_shape* force = nullptr)
 {
     Sizes s;
+    const ecc_launch_shape* tuned = force;
+    if (!tuned) {
+        auto it = ctx->tuned.find(tune_key(ctx, j, nbins));
+        if (it != ctx->tuned.end()) tuned = &it->second;
+    }
     const int64_t cols = (j.g.n2 + 61) / 62;
     const int64_t max_waves = j.ndim == 3 ? ECC_MAX_WAVES_3D : ecc::kMaxWaves;
     s.waves = (int)(cols <= max_waves ? cols : std::min<int64_t>(8, max_waves));
+    if (tuned && tuned->waves > 0) s.waves = (int)std::min<int64_t>(std::min<int64_t>(tuned->waves, ecc::kMaxWaves), cols);
     const int64_t chunk = 62 * (int64_t)s.waves;
     const int64_t nxc = (j.g.n2 + chunk - 1) / chunk;
     const int64_t target = 2 * (int64_t)ctx->cu_count;
@@ -274,14 +293,18 @@ Sizes plan_sizes(const ecc_ctx* ctx, const Job& j, int32_t nbins)
         const int64_t nyb = (j.g.n1 + ecc::kRows3 - 1) / ecc::kRows3;
         int64_t d = (j.g.n0 * nxc * nyb + target - 1) / target;
         s.depth = std::min<int64_t>(std::max<int64_t>(d, 4), 32);
+        if (tuned && tuned->depth > 0) s.depth = std::min<int64_t>(tuned->depth, 256);
     } else {
         int64_t d = (j.g.n1 * nxc + target - 1) / target;
         d = std::min<int64_t>(std::max<int64_t>(d, ecc::kChunk2), 512);
+        if (tuned && tuned->depth > 0) d = std::min<int64_t>(tuned->depth, 4096);
         s.depth = (d + ecc::kChunk2 - 1) / ecc::kChunk2 * ecc::kChunk2;
     }
     const int64_t bricks = ecc::wg_bricks(j.ndim, j.g, s.waves, s.depth);
     const bool windowed = nbins > ecc::kMaxLdsBins;
-    const int per_cu = std::min(j.ndim == 3 ? ECC_MAX_WGS_PER_CU_3D : ECC_MAX_WGS_PER_CU_2D,
+    int want_per_cu = j.ndim == 3 ? ECC_MAX_WGS_PER_CU_3D : ECC_MAX_WGS_PER_CU_2D;
+    if (tuned && tuned->wgs_per_cu > 0) want_per_cu = tuned->wgs_per_cu;
+    const int per_cu = std::min(want_per_cu,
                                 ecc::resident_wgs_per_cu(j.ndim, j.dtype, ctx->construction, windowed, s.waves));
     int64_t grid = std::min<int64_t>(bricks, (int64_t)ctx->cu_count * per_cu);
     grid = std::max<int64_t>(grid, std::min<int64_t>(bricks, (j.nvox >> 27) + 1));
@@ -296,9 +319,10 @@ Sizes plan_sizes(const ecc_ctx* ctx, const Job& j, int32_t nbins)
     return s;
 }
 
-ecc_status enqueue_one(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t stream)
+ecc_status enqueue_one(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t stream,
+                       const ecc_launch_shape* force = nullptr)
 {
-    const Sizes sz = plan_sizes(ctx, j, nbins);
+    const Sizes sz = plan_sizes(ctx, j, nbins, force);
     ecc_status st = ensure_ws(ctx, sz.total);
     if (st != ECC_OK) return st;
     char* base = (char*)ctx->ws;
@@ -778,6 +802,72 @@ ecc_status ecc_batch_plan_destroy(ecc_batch_plan* plan)
         if (plan->dbuf) (void)hipFree(plan->dbuf);
     }
     delete plan;
+    return ECC_OK;
+}
+
+ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32_t reps, void* hip_stream,
+                        ecc_launch_shape* chosen)
+{
+    if (!ctx) return ECC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (!img) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_autotune: null descriptor");
+    if (reps < 1 || reps > 1000) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_autotune: reps must be in [1, 1000]");
+    Job j;
+    ecc_status st = validate(ctx, *img, nbins, "ecc_autotune", &j);
+    if (st != ECC_OK) return st;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed");
+    hipStream_t stream = (hipStream_t)hip_stream;
+    const TuneKey key = tune_key(ctx, j, nbins);
+    ctx->tuned.erase(key);
+    // candidates: the default shape, then waves, depth and workgroups per CU
+    // around it (every shape gives the same result; only the time differs)
+    const Sizes def = plan_sizes(ctx, j, nbins);
+    const int64_t cols = (j.g.n2 + 61) / 62;
+    std::vector<ecc_launch_shape> cand;
+    auto add = [&](int waves, int64_t depth, int wgs) {
+        ecc_launch_shape c = {};
+        c.waves = (int32_t)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(waves, ecc::kMaxWaves), cols));
+        c.depth = std::max<int64_t>(1, depth);
+        c.wgs_per_cu = wgs;
+        for (const auto& e : cand)
+            if (e.waves == c.waves && e.depth == c.depth && e.wgs_per_cu == c.wgs_per_cu) return;
+        cand.push_back(c);
+    };
+    const int def_wgs = j.ndim == 3 ? ECC_MAX_WGS_PER_CU_3D : ECC_MAX_WGS_PER_CU_2D;
+    add(def.waves, def.depth, def_wgs);
+    for (int wgs : {1, 2, 3, 4})
+        for (int64_t dm : {1, 2, 4}) {
+            add(def.waves, def.depth * dm / 2, wgs);
+            if (def.waves > 4) add((def.waves + 1) / 2, def.depth * dm / 2, wgs);
+        }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hip_fail(ctx, e, "hipEventCreate(autotune)");
+    }
+    ecc_launch_shape best = cand[0];
+    best.ms = HUGE_VAL;
+    for (auto& c : cand) {
+        if ((st = enqueue_one(ctx, j, nbins, stream, &c)) != ECC_OK) break;   // warm-up, sizes the scratch
+        if ((e = hipEventRecord(e0, stream)) != hipSuccess) { st = hip_fail(ctx, e, "hipEventRecord"); break; }
+        for (int r = 0; r < reps && st == ECC_OK; ++r) st = enqueue_one(ctx, j, nbins, stream, &c);
+        if (st != ECC_OK) break;
+        if ((e = hipEventRecord(e1, stream)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) {
+            st = hip_fail(ctx, e, "hipEventSynchronize(autotune)");
+            break;
+        }
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { st = hip_fail(ctx, e, "hipEventElapsedTime"); break; }
+        c.ms = ms / reps;
+        if (c.ms < best.ms) best = c;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != ECC_OK) return st;
+    ctx->tuned[key] = best;
+    if (chosen) *chosen = best;
     return ECC_OK;
 }
 

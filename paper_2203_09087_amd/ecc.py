@@ -32,7 +32,7 @@ CONSTRUCTIONS = {"vertex": ECC_VERTEX, "top": ECC_TOP}
 # Symbols declared in include/ecc.h.
 EXPORTED = ("ecc_create", "ecc_destroy", "ecc_last_error", "ecc_compute", "ecc_compute_ex",
             "ecc_compute_batch", "ecc_set_kernel_timing", "ecc_kernel_time", "ecc_batch_plan_create",
-            "ecc_batch_plan_launch", "ecc_batch_plan_destroy")
+            "ecc_batch_plan_launch", "ecc_batch_plan_destroy", "ecc_autotune")
 
 
 class ecc_image(ctypes.Structure):
@@ -47,6 +47,16 @@ class ecc_image(ctypes.Structure):
         ("lo", ctypes.c_double),
         ("hi", ctypes.c_double),
         ("out", ctypes.c_void_p),
+    ]
+
+
+class ecc_launch_shape(ctypes.Structure):
+    """Mirror of ``ecc_launch_shape`` in include/ecc.h."""
+    _fields_ = [
+        ("waves", ctypes.c_int32),
+        ("wgs_per_cu", ctypes.c_int32),
+        ("depth", ctypes.c_int64),
+        ("ms", ctypes.c_double),
     ]
 
 
@@ -91,6 +101,8 @@ def load_library(path: str = LIB_PATH):
     lib.ecc_batch_plan_launch.restype = ctypes.c_int
     lib.ecc_batch_plan_destroy.argtypes = [vp]
     lib.ecc_batch_plan_destroy.restype = ctypes.c_int
+    lib.ecc_autotune.argtypes = [vp, ctypes.POINTER(ecc_image), i32, i32, vp, ctypes.POINTER(ecc_launch_shape)]
+    lib.ecc_autotune.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -155,6 +167,13 @@ def ecc_batch_plan_launch(plan: int, stream: int = 0) -> int:
 
 def ecc_batch_plan_destroy(plan: int) -> int:
     return load_library().ecc_batch_plan_destroy(plan)
+
+
+def ecc_autotune(ctx: int, img: ecc_image, nbins: int, reps: int, stream: int = 0):
+    """(status, ecc_launch_shape)."""
+    shape = ecc_launch_shape()
+    st = load_library().ecc_autotune(ctx, ctypes.byref(img), int(nbins), int(reps), stream, ctypes.byref(shape))
+    return st, shape
 
 
 # ------------------------------------------------------ torch convenience
@@ -252,6 +271,16 @@ class Context:
         st, ms, n = ecc_kernel_time(self.handle)
         self._check(st)
         return ms, n
+
+    def autotune(self, image, nbins: int, value_range=None, reps: int = 5, stream=None):
+        """Times launch shapes for images shaped like `image` and keeps the fastest
+        for later calls on this context; returns the chosen shape as a dict."""
+        import torch
+        out = torch.empty(int(nbins), dtype=torch.int64, device=image.device)
+        st, shape = ecc_autotune(self.handle, make_image(image, out, value_range), nbins, reps,
+                                 self._stream(stream))
+        self._check(st)
+        return {"waves": shape.waves, "wgs_per_cu": shape.wgs_per_cu, "depth": shape.depth, "ms": shape.ms}
 
     def plan_batch(self, images, nbins: int, value_ranges=None, outs=None):
         """A BatchPlan over device tensors (kept alive by the plan object)."""

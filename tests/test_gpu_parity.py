@@ -357,3 +357,27 @@ def test_batch_plan_graph_replay(ctxs, oracle_mod):
             assert np.array_equal(o.cpu().numpy(), oracle_mod.ecc(a, 512, "vertex", value_range=r))
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("shape,dtype", [((40, 70, 300), np.float32), ((300, 2000), np.uint16)])
+def test_autotune_keeps_results(oracle_mod, shape, dtype):
+    """ecc_autotune picks a launch shape for the image shape; every later call
+    on that shape (using it) gives the same ECC as before and as the oracle."""
+    from paper_2203_09087_amd import ecc
+    say(f"case: autotune {shape} {np.dtype(dtype).name}")
+    rng = np.random.default_rng(50)
+    img = (rng.standard_normal(shape).astype(np.float32) if dtype == np.float32
+           else rng.integers(0, 4096, shape).astype(np.uint16))
+    rng_arg = "auto"
+    ctx = ecc.Context(0, "vertex")
+    try:
+        d = to_dev(img)
+        before = ctx.compute(d, 1000, value_range=rng_arg).cpu().numpy()
+        shape_chosen = ctx.autotune(d, 1000, value_range=rng_arg, reps=2)
+        assert shape_chosen["ms"] > 0 and shape_chosen["waves"] >= 1 and shape_chosen["depth"] >= 1
+        after = ctx.compute(d, 1000, value_range=rng_arg).cpu().numpy()
+        torch.cuda.synchronize()
+        assert np.array_equal(before, after)
+        assert np.array_equal(after, oracle_mod.ecc(img, 1000, "vertex", value_range=rng_arg))
+    finally:
+        ctx.close()
