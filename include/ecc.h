@@ -130,6 +130,21 @@ ecc_status ecc_compute_ex(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, voi
 ecc_status ecc_compute_batch(ecc_ctx* ctx, const ecc_image* imgs, int32_t count, int32_t nbins,
                              void* hip_stream);
 
+/* ECC of an image that stays in HOST memory (Sec. 4.4's streaming of volumes
+ * larger than device memory): slabs of `slab_planes` planes of the first axis
+ * (0: about 256 MiB each), each with the one plane after it, are copied to the
+ * device in turn on a copy stream of the context while the previous slab is
+ * counted on hip_stream; the slab VCECs add up exactly, since every cell is
+ * counted by the slab that owns its first-axis start.  img->data is a HOST
+ * pointer (pinned memory copies fastest, pageable memory works), img->out a
+ * device pointer.  A 2D image travels as one slab.  An AUTO range reads the
+ * volume twice (min/max first).  Asynchronous: the host image must stay
+ * unchanged until hip_stream has completed the call.  Two device slab buffers
+ * are kept by the context.  Results are identical to ecc_compute_ex.
+ * Errors: as ecc_compute_ex, plus ECC_ERR_INVALID_ARG for slab_planes < 0. */
+ecc_status ecc_compute_streamed(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int64_t slab_planes,
+                                void* hip_stream);
+
 /* Launch shape of the single-image kernel: waves per workgroup (a workgroup
  * covers waves * 62 consecutive columns), rows (2D) or planes (3D) per
  * workgroup brick, and resident workgroups per CU aimed for.  `ms` is the mean

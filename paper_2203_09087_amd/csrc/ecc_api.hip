@@ -31,6 +31,12 @@ struct ecc_ctx {
     size_t staging_bytes = 0;
     hipEvent_t staging_done = nullptr;   // recorded after the last copy out of `staging`
     bool staging_pending = false;
+    // streaming (ecc_compute_streamed): two device slab buffers, a copy stream,
+    // and events ordering copies and kernels on them
+    void* slab_buf[2] = {nullptr, nullptr};
+    size_t slab_cap = 0;
+    hipStream_t copy_stream = nullptr;
+    hipEvent_t copied[2] = {nullptr, nullptr}, consumed[2] = {nullptr, nullptr};
     // launch shapes chosen by ecc_autotune, by image shape (see TuneKey)
     std::map<std::tuple<int, int, int, int, int64_t, int64_t, int64_t>, ecc_launch_shape> tuned;
     // kernel timing (ecc_set_kernel_timing): event pairs around histogram launches
@@ -313,31 +319,23 @@ Sizes plan_sizes(const ecc_ctx* ctx, const Job& j, int32_t nbins, const ecc_laun
     s.off_counters = 0;   // fixed place, shared with the batch layout (never overwritten)
     s.off_params = kCounterBytes;
     s.off_mm = s.off_params + align_up(sizeof(ecc::BinParams));
-    s.off_level2 = s.off_mm + align_up((size_t)kMinmaxBlocks * 2 * sizeof(uint32_t));
+    s.off_level2 = s.off_mm + align_up((size_t)(kMinmaxBlocks + 1) * 2 * sizeof(uint32_t));
     s.off_partials = s.off_level2 + align_up(ecc::kLevel2Words * sizeof(int64_t));
     s.total = s.off_partials + align_up((size_t)s.grid * (size_t)s.window * sizeof(int32_t));
     return s;
 }
 
-ecc_status enqueue_one(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t stream,
-                       const ecc_launch_shape* force = nullptr)
+// The histogram launches (and merges) of one image or slab.  pdev: binning
+// parameters on the device (AUTO), else the host parameters of j.  Planes
+// [0, z_own) of j's planes are counted; they are planes z_base.. of a volume
+// of n0_global planes.  accumulate: add the VCEC to out instead of writing it;
+// scan: prefix-sum out after the last window.
+ecc_status enqueue_hist(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t stream, const Sizes& sz,
+                        const ecc::BinParams* pdev, int64_t z_own, int64_t z_base, int64_t n0_global,
+                        bool accumulate, bool scan)
 {
-    const Sizes sz = plan_sizes(ctx, j, nbins, force);
-    ecc_status st = ensure_ws(ctx, sz.total);
-    if (st != ECC_OK) return st;
     char* base = (char*)ctx->ws;
-    ecc::BinParams* pdev = nullptr;
     uint32_t* counters = (uint32_t*)(base + sz.off_counters);
-    hipError_t e;
-    if (j.range_mode == ECC_RANGE_AUTO) {
-        uint32_t* mm = (uint32_t*)(base + sz.off_mm);
-        pdev = (ecc::BinParams*)(base + sz.off_params);
-        const int blocks = (int)std::min<int64_t>(kMinmaxBlocks, (j.nvox + 4095) / 4096);
-        if ((e = ecc::launch_minmax(j.data, j.dtype, j.nvox, mm, blocks, stream)) != hipSuccess)
-            return hip_fail(ctx, e, "minmax launch");
-        if ((e = ecc::launch_params_from_minmax(mm, blocks, j.dtype, nbins, pdev, stream)) != hipSuccess)
-            return hip_fail(ctx, e, "params launch");
-    }
     ecc::EccLaunch L;
     L.data = j.data;
     L.ndim = j.ndim;
@@ -350,9 +348,13 @@ ecc_status enqueue_one(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t st
     L.grid = sz.grid;
     L.waves = sz.waves;
     L.depth = sz.depth;
+    L.z_own = z_own;
+    L.z_base = z_base;
+    L.n0_global = n0_global;
     L.partials = (int32_t*)(base + sz.off_partials);
     L.out = j.out;
     L.counter = counters;
+    hipError_t e;
     for (int32_t b0 = 0; b0 < nbins; b0 += sz.window) {
         L.bin_lo = b0;
         L.width = std::min<int32_t>(sz.window, nbins - b0);
@@ -360,10 +362,31 @@ ecc_status enqueue_one(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t st
         if ((e = timed_launch(ctx, stream, [&] { return ecc::launch_ecc(L, stream); })) != hipSuccess)
             return hip_fail(ctx, e, "ecc launch");
         if ((e = ecc::launch_merge(L.partials, L.grid, L.width, L.bin_lo, (int64_t*)(base + sz.off_level2),
-                                   j.out, nbins, counters, last, stream)) != hipSuccess)
+                                   j.out, nbins, counters, accumulate, scan && last, stream)) != hipSuccess)
             return hip_fail(ctx, e, "merge launch");
     }
     return ECC_OK;
+}
+
+ecc_status enqueue_one(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t stream,
+                       const ecc_launch_shape* force = nullptr)
+{
+    const Sizes sz = plan_sizes(ctx, j, nbins, force);
+    ecc_status st = ensure_ws(ctx, sz.total);
+    if (st != ECC_OK) return st;
+    char* base = (char*)ctx->ws;
+    ecc::BinParams* pdev = nullptr;
+    hipError_t e;
+    if (j.range_mode == ECC_RANGE_AUTO) {
+        uint32_t* mm = (uint32_t*)(base + sz.off_mm);
+        pdev = (ecc::BinParams*)(base + sz.off_params);
+        const int blocks = (int)std::min<int64_t>(kMinmaxBlocks, (j.nvox + 4095) / 4096);
+        if ((e = ecc::launch_minmax(j.data, j.dtype, j.nvox, mm, blocks, stream)) != hipSuccess)
+            return hip_fail(ctx, e, "minmax launch");
+        if ((e = ecc::launch_params_from_minmax(mm, blocks, j.dtype, nbins, pdev, stream)) != hipSuccess)
+            return hip_fail(ctx, e, "params launch");
+    }
+    return enqueue_hist(ctx, j, nbins, stream, sz, pdev, j.g.n0, 0, j.g.n0, false, true);
 }
 
 // ------------------------------------------------------------------ batches
@@ -591,6 +614,127 @@ ecc_status enqueue_batch(ecc_ctx* ctx, const std::vector<Job>& jobs, int32_t nbi
 
 }  // namespace
 
+// ------------------------------------------------------------- streaming
+
+ecc_status ensure_streaming(ecc_ctx* ctx, size_t slab_bytes)
+{
+    hipError_t e;
+    if (!ctx->copy_stream) {
+        if ((e = hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking)) != hipSuccess) {
+            ctx->copy_stream = nullptr;
+            return hip_fail(ctx, e, "hipStreamCreate(copy)");
+        }
+        for (int b = 0; b < 2; ++b) {
+            if ((e = hipEventCreateWithFlags(&ctx->copied[b], hipEventDisableTiming)) != hipSuccess ||
+                (e = hipEventCreateWithFlags(&ctx->consumed[b], hipEventDisableTiming)) != hipSuccess)
+                return hip_fail(ctx, e, "hipEventCreate(streaming)");
+        }
+    }
+    if (slab_bytes <= ctx->slab_cap) return ECC_OK;
+    // the old buffers may still be read by enqueued work
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
+    for (int b = 0; b < 2; ++b) {
+        if (ctx->slab_buf[b]) (void)hipFree(ctx->slab_buf[b]);
+        ctx->slab_buf[b] = nullptr;
+    }
+    ctx->slab_cap = 0;
+    for (int b = 0; b < 2; ++b) {
+        if ((e = hipMalloc(&ctx->slab_buf[b], slab_bytes)) != hipSuccess) {
+            ctx->slab_buf[b] = nullptr;
+            return hip_fail(ctx, e, "hipMalloc(slab)");
+        }
+    }
+    ctx->slab_cap = slab_bytes;
+    return ECC_OK;
+}
+
+// Copies planes [z0, z0 + n) of the host volume into slab buffer b on the copy
+// stream, after the kernels that last read that buffer.
+ecc_status stream_copy(ecc_ctx* ctx, const char* host, size_t plane_bytes, int64_t z0, int64_t n, int b)
+{
+    hipError_t e;
+    if ((e = hipStreamWaitEvent(ctx->copy_stream, ctx->consumed[b], 0)) != hipSuccess)
+        return hip_fail(ctx, e, "hipStreamWaitEvent(copy)");
+    if ((e = hipMemcpyAsync(ctx->slab_buf[b], host + (size_t)z0 * plane_bytes, (size_t)n * plane_bytes,
+                            hipMemcpyHostToDevice, ctx->copy_stream)) != hipSuccess)
+        return hip_fail(ctx, e, "hipMemcpyAsync(slab)");
+    if ((e = hipEventRecord(ctx->copied[b], ctx->copy_stream)) != hipSuccess)
+        return hip_fail(ctx, e, "hipEventRecord(copied)");
+    return ECC_OK;
+}
+
+ecc_status enqueue_streamed(ecc_ctx* ctx, const Job& vol, int32_t nbins, int64_t slab_planes, hipStream_t stream)
+{
+    const int64_t N = vol.g.n0;
+    const size_t esize = vol.dtype == ECC_U8 ? 1 : (vol.dtype == ECC_U16 ? 2 : 4);
+    const size_t plane_bytes = (size_t)(vol.g.n1 * vol.g.n2) * esize;
+    int64_t S = slab_planes;
+    if (S <= 0) S = std::max<int64_t>(1, (int64_t)((size_t)256 << 20) / (int64_t)plane_bytes);
+    S = std::min<int64_t>(S, N);
+    const int64_t nslabs = (N + S - 1) / S;
+    ecc_status st = ensure_streaming(ctx, (size_t)(std::min<int64_t>(S + 1, N)) * plane_bytes);
+    if (st != ECC_OK) return st;
+    // one scratch size for every slab (the first is the largest), fixed before
+    // anything is enqueued so that no slab reallocates it
+    Job first = vol;
+    first.g.n0 = std::min<int64_t>(S + 1, N);
+    first.nvox = first.g.n0 * vol.g.n1 * vol.g.n2;
+    const Sizes sz = plan_sizes(ctx, first, nbins);
+    if ((st = ensure_ws(ctx, sz.total)) != ECC_OK) return st;
+    hipError_t e;
+    // the slab buffers are free once work already on `stream` is done
+    for (int b = 0; b < 2; ++b)
+        if ((e = hipEventRecord(ctx->consumed[b], stream)) != hipSuccess)
+            return hip_fail(ctx, e, "hipEventRecord(consumed)");
+    const char* host = (const char*)vol.data;
+    char* base = (char*)ctx->ws;
+    ecc::BinParams* pdev = nullptr;
+    if (vol.range_mode == ECC_RANGE_AUTO) {
+        // pass 1: min/max keys of every slab's own planes, folded on the device
+        uint32_t* mm = (uint32_t*)(base + sz.off_mm);
+        uint32_t* acc = mm + 2 * kMinmaxBlocks;
+        pdev = (ecc::BinParams*)(base + sz.off_params);
+        for (int64_t k = 0; k < nslabs; ++k) {
+            const int b = (int)(k & 1);
+            const int64_t z0 = k * S, n = std::min<int64_t>(S, N - z0);
+            if ((st = stream_copy(ctx, host, plane_bytes, z0, n, b)) != ECC_OK) return st;
+            if ((e = hipStreamWaitEvent(stream, ctx->copied[b], 0)) != hipSuccess)
+                return hip_fail(ctx, e, "hipStreamWaitEvent(compute)");
+            const int64_t nv = n * vol.g.n1 * vol.g.n2;
+            const int blocks = (int)std::min<int64_t>(kMinmaxBlocks, (nv + 4095) / 4096);
+            if ((e = ecc::launch_minmax(ctx->slab_buf[b], vol.dtype, nv, mm, blocks, stream)) != hipSuccess ||
+                (e = ecc::launch_mm_fold(mm, blocks, acc, k == 0, stream)) != hipSuccess)
+                return hip_fail(ctx, e, "streamed minmax launch");
+            if ((e = hipEventRecord(ctx->consumed[b], stream)) != hipSuccess)
+                return hip_fail(ctx, e, "hipEventRecord(consumed)");
+        }
+        if ((e = ecc::launch_params_from_minmax(acc, 1, vol.dtype, nbins, pdev, stream)) != hipSuccess)
+            return hip_fail(ctx, e, "params launch");
+    }
+    // pass 2: slab k counts its own planes [k*S, k*S + n) and reads one collar
+    // plane beyond them (the plane its last plane pairs with)
+    for (int64_t k = 0; k < nslabs; ++k) {
+        const int b = (int)(k & 1);
+        const int64_t z0 = k * S, n = std::min<int64_t>(S, N - z0);
+        const int64_t loaded = std::min<int64_t>(n + 1, N - z0);
+        if ((st = stream_copy(ctx, host, plane_bytes, z0, loaded, b)) != ECC_OK) return st;
+        if ((e = hipStreamWaitEvent(stream, ctx->copied[b], 0)) != hipSuccess)
+            return hip_fail(ctx, e, "hipStreamWaitEvent(compute)");
+        Job slab = vol;
+        slab.data = ctx->slab_buf[b];
+        slab.g.n0 = loaded;
+        slab.nvox = loaded * vol.g.n1 * vol.g.n2;
+        Sizes ssz = plan_sizes(ctx, slab, nbins);
+        ssz.off_counters = sz.off_counters;   // the layout of the scratch sized above
+        if (ssz.total > sz.total) ssz = sz;
+        if ((st = enqueue_hist(ctx, slab, nbins, stream, ssz, pdev, n, z0, N, k > 0, k == nslabs - 1)) != ECC_OK)
+            return st;
+        if ((e = hipEventRecord(ctx->consumed[b], stream)) != hipSuccess)
+            return hip_fail(ctx, e, "hipEventRecord(consumed)");
+    }
+    return ECC_OK;
+}
+
 // A planned batch: its tables and partial rows live in device memory owned by
 // the plan, written once at creation.
 struct ecc_batch_plan {
@@ -635,6 +779,12 @@ ecc_status ecc_destroy(ecc_ctx* ctx)
         if (ctx->staging) (void)hipHostFree(ctx->staging);
         if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
         for (hipEvent_t ev : ctx->tev) (void)hipEventDestroy(ev);
+        for (int b = 0; b < 2; ++b) {
+            if (ctx->slab_buf[b]) (void)hipFree(ctx->slab_buf[b]);
+            if (ctx->copied[b]) (void)hipEventDestroy(ctx->copied[b]);
+            if (ctx->consumed[b]) (void)hipEventDestroy(ctx->consumed[b]);
+        }
+        if (ctx->copy_stream) (void)hipStreamDestroy(ctx->copy_stream);
     }
     delete ctx;
     return ECC_OK;
@@ -869,6 +1019,25 @@ ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32
     ctx->tuned[key] = best;
     if (chosen) *chosen = best;
     return ECC_OK;
+}
+
+ecc_status ecc_compute_streamed(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int64_t slab_planes,
+                                void* hip_stream)
+{
+    if (!ctx) return ECC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (!img) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_compute_streamed: null descriptor");
+    if (slab_planes < 0) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_compute_streamed: negative slab_planes");
+    Job j;
+    ecc_status st = validate(ctx, *img, nbins, "ecc_compute_streamed", &j);
+    if (st != ECC_OK) return st;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed");
+    if (j.ndim == 2) {   // a 2D image travels as one slab of one plane
+        j.ndim = 3;
+        j.g = {1, j.g.n1, j.g.n2};
+    }
+    return enqueue_streamed(ctx, j, nbins, slab_planes, (hipStream_t)hip_stream);
 }
 
 }  // extern "C"

@@ -72,6 +72,9 @@ void k_ecc_batch(BatchLaunch B)
         L.data = I.data;
         L.g = I.g;
         L.depth = I.depth;
+        L.z_own = I.g.n0;
+        L.z_base = 0;
+        L.n0_global = I.g.n0;
         zero_hist(hist, B.width);
         // the workgroup's waves form W / wpb teams of wpb waves; team t takes
         // bricks b0 + t, b0 + t + teams, ... (waves beyond the last team idle)

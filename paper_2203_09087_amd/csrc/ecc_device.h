@@ -518,7 +518,9 @@ __device__ __forceinline__ void brick_3d(const EccLaunch& L, const BinParams& P,
             else plane_step<CONS, WIN, FULL, +1, false, NR>(Bc, Bn, own_x, rows_owned, H);
         } else {
             // top filtration: plane z enters with -1 + [z == 0] + [z == n0-1]
-            const int ca = -1 + (z == 0) + (z == n0 - 1);
+            // (positions in the whole volume)
+            const int64_t zg = L.z_base + (int64_t)z;
+            const int ca = -1 + (zg == 0) + (zg == L.n0_global - 1);
             if (has1) {
                 if (ca < 0) plane_step<CONS, WIN, FULL, -1, true, NR>(Bc, Bn, own_x, rows_owned, H);
                 else plane_step<CONS, WIN, FULL, 0, true, NR>(Bc, Bn, own_x, rows_owned, H);
@@ -645,14 +647,15 @@ __device__ __forceinline__ void run_brick_3d(const EccLaunch& L, const BinParams
     zb = uniform_u32(zb);
     constexpr int NR = kRows3;
     using T = typename ValT<DT>::T;
-    const int64_t n0 = L.g.n0, n1 = L.g.n1, n2 = L.g.n2;
+    const int64_t n1 = L.g.n1, n2 = L.g.n2;
     const WaveCols w = wave_cols((int64_t)xc * chunk, xw, n2);
     if (!w.active) return;
     const uint32_t xob = w.xo * (uint32_t)sizeof(T);
     const int64_t y0 = (int64_t)yb * NR;
     const int rows_owned = (int)((n1 - y0) < NR ? (n1 - y0) : NR);
     const uint32_t z0 = zb * (uint32_t)L.depth;
-    const uint32_t zend = ((int64_t)z0 + L.depth < n0) ? z0 + (uint32_t)L.depth : (uint32_t)n0;
+    const int64_t z_own = L.z_own;   // planes counted (the image's, or a slab's)
+    const uint32_t zend = ((int64_t)z0 + L.depth < z_own) ? z0 + (uint32_t)L.depth : (uint32_t)z_own;
     // rows r in [r_lo, r_hi) of the brick (row r is y0 - 1 + r) lie inside the image
     const int r_lo = (y0 == 0) ? 1 : 0;
     const int r_hi = (int)((n1 - (y0 - 1)) < NR + 2 ? (n1 - (y0 - 1)) : NR + 2);

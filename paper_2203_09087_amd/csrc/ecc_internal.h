@@ -100,6 +100,11 @@ struct EccLaunch {
     int32_t grid;                  // number of workgroups
     int32_t waves;                 // waves per workgroup (x-chunk = 62 * waves columns)
     int64_t depth;                 // planes (3D) or rows (2D) per workgroup brick
+    // 3D slab of a larger volume (streaming): planes [0, z_own) of the g.n0 in
+    // memory are counted (a plane beyond them is the collar the last one needs);
+    // plane 0 is plane z_base of a volume of n0_global planes.  A whole image
+    // has z_own = g.n0, z_base = 0, n0_global = g.n0.
+    int64_t z_own, z_base, n0_global;
     int32_t* partials;             // [grid][width] workgroup histograms
     int64_t* out;                  // the caller's output (VCEC window, zeroed by block 0)
     uint32_t* counter;             // the merge's counter (unused by the main kernels)
@@ -182,8 +187,11 @@ constexpr int kMergeGroups = 32;
 // group sums (kMergeGroups x window) and per-group totals of 256-bin blocks
 constexpr size_t kLevel2Words = (size_t)kMergeGroups * (kMaxLdsBins + kMaxLdsBins / 256);
 constexpr int kCounterWords = 256;
+// accumulate: add to out instead of writing it (slabs of a streamed volume).
 hipError_t launch_merge(const int32_t* partials, int rows, int32_t width, int32_t bin_lo, int64_t* level2,
-                        int64_t* out, int32_t nbins, uint32_t* counters, bool scan, hipStream_t s);
+                        int64_t* out, int32_t nbins, uint32_t* counters, bool accumulate, bool scan, hipStream_t s);
+// Folds `blocks` min/max key pairs into the running pair acc (first: start it).
+hipError_t launch_mm_fold(const uint32_t* mm, int blocks, uint32_t* acc, bool first, hipStream_t s);
 
 // Workgroup bricks of an image for a launch shape.
 int64_t wg_bricks(int ndim, const Geom& g, int waves, int64_t depth);

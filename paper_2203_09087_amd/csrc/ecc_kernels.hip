@@ -24,7 +24,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
     const int64_t chunk = (int64_t)(blockDim.x >> 6) * 62;
     const uint32_t nxc = (uint32_t)((L.g.n2 + chunk - 1) / chunk);
     const uint32_t nyb = (uint32_t)((L.g.n1 + kRows3 - 1) / kRows3);
-    const uint32_t nzb = (uint32_t)((L.g.n0 + L.depth - 1) / L.depth);
+    const uint32_t nzb = (uint32_t)((L.z_own + L.depth - 1) / L.depth);
     const uint32_t nbricks = nxc * nyb * nzb;
     for (uint32_t brick = blockIdx.x; brick < nbricks; brick += gridDim.x)
         run_brick_3d<DT, CONS, WIN>(L, P, H, chunk, brick % nxc, (brick / nxc) % nyb, brick / (nxc * nyb), wave_id());
@@ -165,7 +165,8 @@ __global__ __launch_bounds__(kThreads) void k_merge_groups(const int32_t* __rest
 __global__ __launch_bounds__(kThreads) void k_merge_final(const int64_t* __restrict__ level2,
                                                           const int64_t* __restrict__ btot, int groups,
                                                           int32_t width, int32_t bin_lo, int64_t* out,
-                                                          int32_t nbins, uint32_t* counter, int scan)
+                                                          int32_t nbins, uint32_t* counter, int accumulate,
+                                                          int scan)
 {
     const int j = blockIdx.x * kThreads + threadIdx.x;
     int64_t t = 0;
@@ -188,16 +189,38 @@ __global__ __launch_bounds__(kThreads) void k_merge_final(const int64_t* __restr
         if (j < width) out[bin_lo + j] = offset + inc;
         return;
     }
-    if (j < width) out[bin_lo + j] = t;
+    if (j < width) out[bin_lo + j] = (accumulate ? out[bin_lo + j] : 0) + t;
     if (!scan) return;
     if (!last_to_arrive(counter, gridDim.x)) return;
     block_scan_inplace(out, nbins);
     if (threadIdx.x == 0) atomicExch(counter, 0u);
 }
 
+// Folds the per-block min/max keys of one slab into a running pair acc[0..1]
+// (first: start the pair).
+__global__ __launch_bounds__(kThreads) void k_mm_fold(const uint32_t* mm, int blocks, uint32_t* acc, int first)
+{
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    for (int i = threadIdx.x; i < blocks; i += kThreads) {
+        lo = min(lo, mm[2 * i]);
+        hi = max(hi, mm[2 * i + 1]);
+    }
+    block_minmax(lo, hi);
+    if (threadIdx.x == 0) {
+        acc[0] = first ? lo : min(acc[0], lo);
+        acc[1] = first ? hi : max(acc[1], hi);
+    }
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------- launchers
+
+hipError_t launch_mm_fold(const uint32_t* mm, int blocks, uint32_t* acc, bool first, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mm_fold, dim3(1), dim3(kThreads), 0, s, mm, blocks, acc, first ? 1 : 0);
+    return hipGetLastError();
+}
 
 int64_t wg_bricks(int ndim, const Geom& g, int waves, int64_t depth)
 {
@@ -289,18 +312,20 @@ int resident_wgs_per_cu(int ndim, int dtype, int construction, bool windowed, in
 }
 
 hipError_t launch_merge(const int32_t* partials, int rows, int32_t width, int32_t bin_lo, int64_t* level2,
-                        int64_t* out, int32_t nbins, uint32_t* counters, bool scan, hipStream_t s)
+                        int64_t* out, int32_t nbins, uint32_t* counters, bool accumulate, bool scan, hipStream_t s)
 {
     const unsigned bx = (unsigned)((width + kThreads - 1) / kThreads);
     const int groups = rows < kMergeGroups ? rows : kMergeGroups;
-    // one window holding every bin: blocks scan their own bins (see k_merge_final)
-    int64_t* btot = (scan && bin_lo == 0 && width == nbins) ? level2 + (size_t)kMergeGroups * width : nullptr;
+    // one window holding every bin, written afresh: blocks scan their own bins
+    // (see k_merge_final)
+    int64_t* btot = (scan && !accumulate && bin_lo == 0 && width == nbins)
+                        ? level2 + (size_t)kMergeGroups * width : nullptr;
     hipLaunchKernelGGL(k_merge_groups, dim3(bx, (unsigned)groups), dim3(kThreads), 0, s, partials, rows, width,
                        level2, btot);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_merge_final, dim3(bx), dim3(kThreads), 0, s, level2, btot, groups, width, bin_lo, out,
-                       nbins, counters, scan ? 1 : 0);
+                       nbins, counters, accumulate ? 1 : 0, scan ? 1 : 0);
     return hipGetLastError();
 }
 

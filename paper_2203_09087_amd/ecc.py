@@ -32,7 +32,7 @@ CONSTRUCTIONS = {"vertex": ECC_VERTEX, "top": ECC_TOP}
 # Symbols declared in include/ecc.h.
 EXPORTED = ("ecc_create", "ecc_destroy", "ecc_last_error", "ecc_compute", "ecc_compute_ex",
             "ecc_compute_batch", "ecc_set_kernel_timing", "ecc_kernel_time", "ecc_batch_plan_create",
-            "ecc_batch_plan_launch", "ecc_batch_plan_destroy", "ecc_autotune")
+            "ecc_batch_plan_launch", "ecc_batch_plan_destroy", "ecc_autotune", "ecc_compute_streamed")
 
 
 class ecc_image(ctypes.Structure):
@@ -103,6 +103,8 @@ def load_library(path: str = LIB_PATH):
     lib.ecc_batch_plan_destroy.restype = ctypes.c_int
     lib.ecc_autotune.argtypes = [vp, ctypes.POINTER(ecc_image), i32, i32, vp, ctypes.POINTER(ecc_launch_shape)]
     lib.ecc_autotune.restype = ctypes.c_int
+    lib.ecc_compute_streamed.argtypes = [vp, ctypes.POINTER(ecc_image), i32, ctypes.c_int64, vp]
+    lib.ecc_compute_streamed.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -174,6 +176,10 @@ def ecc_autotune(ctx: int, img: ecc_image, nbins: int, reps: int, stream: int = 
     shape = ecc_launch_shape()
     st = load_library().ecc_autotune(ctx, ctypes.byref(img), int(nbins), int(reps), stream, ctypes.byref(shape))
     return st, shape
+
+
+def ecc_compute_streamed(ctx: int, img: ecc_image, nbins: int, slab_planes: int = 0, stream: int = 0) -> int:
+    return load_library().ecc_compute_streamed(ctx, ctypes.byref(img), int(nbins), int(slab_planes), stream)
 
 
 # ------------------------------------------------------ torch convenience
@@ -271,6 +277,20 @@ class Context:
         st, ms, n = ecc_kernel_time(self.handle)
         self._check(st)
         return ms, n
+
+    def compute_streamed(self, host_image, nbins: int, value_range=None, out=None, slab_planes: int = 0,
+                         stream=None):
+        """ECC of a CPU tensor (ideally pinned) streamed to the device in slabs of
+        the first axis; `out` is a device tensor.  The host tensor must stay
+        unchanged until the stream has finished."""
+        import torch
+        if host_image.is_cuda:
+            raise ValueError("compute_streamed takes a host (CPU) tensor")
+        if out is None:
+            out = torch.empty(int(nbins), dtype=torch.int64, device=torch.device("cuda", self.device))
+        im = make_image(host_image, out, value_range)
+        self._check(ecc_compute_streamed(self.handle, im, nbins, slab_planes, self._stream(stream)))
+        return out
 
     def autotune(self, image, nbins: int, value_range=None, reps: int = 5, stream=None):
         """Times launch shapes for images shaped like `image` and keeps the fastest
