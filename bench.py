@@ -358,6 +358,17 @@ def main():
                              "speedup_vs_per_image": round(mp / mb, 3)}
         del dev_imgs, outs
 
+    if not args.no_side:
+        log("streaming the 512^3 f32 field from pinned host memory ...")
+        host = torch.from_numpy(vol).pin_memory()
+        ms_s, _ = timed_calls(lambda: ctx.compute_streamed(host, nbins, value_range=(lo, hi), out=out,
+                                                           stream=stream), stream, 5, 1)
+        msv = float(np.mean(ms_s))
+        result["streamed_from_host"] = {"shape": [512, 512, 512], "slab_planes": "auto (256 MiB)",
+                                        "ms": round(msv, 3), "gvox_s": round(nvox / (msv * 1e-3) / 1e9, 2),
+                                        "host_to_device_gb_s": round(nvox * 4 / (msv * 1e-3) / 1e9, 1)}
+        del host
+
     if not args.no_side and not args.no_serve:
         result["serving"] = serving_leg(dev)
 
