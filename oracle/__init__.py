@@ -65,6 +65,9 @@ def _load():
                                    ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_int, i64p]
         lib.oracle_ecc.restype = ctypes.c_int
+        fltp = ctypes.POINTER(ctypes.c_float)
+        lib.oracle_smooth13.argtypes = [fltp, fltp, ctypes.c_int64, ctypes.c_int64, fltp]
+        lib.oracle_smooth13.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -152,3 +155,20 @@ def vcec(image, nbins: int, construction: str = "vertex", value_range=None, thre
     """VCEC of an image: the bins, then every cell enumerated once."""
     b, _ = bins(image, nbins, value_range)
     return vcec_from_bins(b, nbins, construction, threads)
+
+
+def smooth13(image, taps):
+    """One separable 13-tap smoothing pass of a 2D float32 image (rows, then
+    columns; border pixels repeated; float32 sums in tap order)."""
+    lib = _load()
+    a = np.ascontiguousarray(image, dtype=np.float32)
+    w = np.ascontiguousarray(taps, dtype=np.float32)
+    if a.ndim != 2 or w.shape != (13,):
+        raise ValueError("smooth13 takes a 2D image and 13 taps")
+    out = np.empty_like(a)
+    fltp = ctypes.POINTER(ctypes.c_float)
+    rc = lib.oracle_smooth13(a.ctypes.data_as(fltp), out.ctypes.data_as(fltp), a.shape[0], a.shape[1],
+                             w.ctypes.data_as(fltp))
+    if rc != 0:
+        raise ValueError("oracle_smooth13 rejected the arguments")
+    return out

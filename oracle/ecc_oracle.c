@@ -311,3 +311,43 @@ int oracle_ecc(const void* data, int dtype, int ndim, const int64_t* dims, int32
     free(vcec);
     return rc;
 }
+
+/* Separable 13-tap smoothing of a 2D float32 image, the smoothing step of the
+ * pipeline workload (Sec. 5, "Pipeline" and "Gaussian smoothing
+ * implementation": a discrete Gaussian convolution of width 13, applied along
+ * one axis and then the other).  The paper fixes neither the boundary nor the
+ * evaluation order; this library's reading:
+ *   rows:    tmp[y][x] = sum_{k=0..12} w[k] * in[y][clamp(x + k - 6)]
+ *   columns: out[y][x] = sum_{k=0..12} w[k] * tmp[clamp(y + k - 6)][x]
+ * clamp() repeats the border pixel; every sum starts from 0.0f and adds the
+ * terms in the order k = 0..12, each product and each sum rounded once in IEEE
+ * float32 (no fused multiply-add).  `out` may be `in`.  Returns 0, or -1 for an
+ * empty image, -2 if memory runs out. */
+static int64_t clamp_index(int64_t i, int64_t n) { return i < 0 ? 0 : (i >= n ? n - 1 : i); }
+
+int oracle_smooth13(const float* in, float* out, int64_t n1, int64_t n2, const float* w)
+{
+    if (n1 < 1 || n2 < 1) return -1;
+    float* tmp = (float*)malloc((size_t)n1 * (size_t)n2 * sizeof(float));
+    if (!tmp) return -2;
+    for (int64_t y = 0; y < n1; ++y)
+        for (int64_t x = 0; x < n2; ++x) {
+            float acc = 0.0f;
+            for (int k = 0; k < 13; ++k) {
+                const float p = w[k] * in[y * n2 + clamp_index(x + k - 6, n2)];
+                acc = acc + p;
+            }
+            tmp[y * n2 + x] = acc;
+        }
+    for (int64_t y = 0; y < n1; ++y)
+        for (int64_t x = 0; x < n2; ++x) {
+            float acc = 0.0f;
+            for (int k = 0; k < 13; ++k) {
+                const float p = w[k] * tmp[clamp_index(y + k - 6, n1) * n2 + x];
+                acc = acc + p;
+            }
+            out[y * n2 + x] = acc;
+        }
+    free(tmp);
+    return 0;
+}
