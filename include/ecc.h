@@ -145,6 +145,19 @@ ecc_status ecc_compute_batch(ecc_ctx* ctx, const ecc_image* imgs, int32_t count,
 ecc_status ecc_compute_streamed(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int64_t slab_planes,
                                 void* hip_stream);
 
+/* One separable 13-tap smoothing pass of a 2D float32 image: the smoothing step
+ * of the smoothing + ECC pipeline (Sec. 5, a discrete Gaussian convolution of
+ * width 13 applied along each axis).  Rows first, then columns; each output is
+ * the sum over k = 0..12, in that order from 0, of taps[k] times the neighbour
+ * at offset k - 6 (border pixels repeated), every product and sum rounded once
+ * in float32.  in, out: device pointers to n1 * n2 floats (row-major), out may
+ * equal in; taps: HOST array of 13 floats.  The context keeps an n1 * n2 float
+ * intermediate buffer.  Asynchronous on hip_stream.
+ * Errors: ECC_ERR_INVALID_ARG (null pointer, n1 or n2 outside [1, 2^31], more
+ * than 2^40 pixels), ECC_ERR_OUT_OF_MEMORY, ECC_ERR_DEVICE. */
+ecc_status ecc_smooth13(ecc_ctx* ctx, const float* in, float* out, int64_t n1, int64_t n2, const float* taps,
+                        void* hip_stream);
+
 /* Launch shape of the single-image kernel: waves per workgroup (a workgroup
  * covers waves * 62 consecutive columns), rows (2D) or planes (3D) per
  * workgroup brick, and resident workgroups per CU aimed for.  `ms` is the mean

@@ -37,6 +37,9 @@ struct ecc_ctx {
     size_t slab_cap = 0;
     hipStream_t copy_stream = nullptr;
     hipEvent_t copied[2] = {nullptr, nullptr}, consumed[2] = {nullptr, nullptr};
+    // intermediate buffer of ecc_smooth13
+    void* smooth_tmp = nullptr;
+    size_t smooth_cap = 0;
     // launch shapes chosen by ecc_autotune, by image shape (see TuneKey)
     std::map<std::tuple<int, int, int, int, int64_t, int64_t, int64_t>, ecc_launch_shape> tuned;
     // kernel timing (ecc_set_kernel_timing): event pairs around histogram launches
@@ -785,6 +788,7 @@ ecc_status ecc_destroy(ecc_ctx* ctx)
             if (ctx->consumed[b]) (void)hipEventDestroy(ctx->consumed[b]);
         }
         if (ctx->copy_stream) (void)hipStreamDestroy(ctx->copy_stream);
+        if (ctx->smooth_tmp) (void)hipFree(ctx->smooth_tmp);
     }
     delete ctx;
     return ECC_OK;
@@ -1038,6 +1042,39 @@ ecc_status ecc_compute_streamed(ecc_ctx* ctx, const ecc_image* img, int32_t nbin
         j.g = {1, j.g.n1, j.g.n2};
     }
     return enqueue_streamed(ctx, j, nbins, slab_planes, (hipStream_t)hip_stream);
+}
+
+ecc_status ecc_smooth13(ecc_ctx* ctx, const float* in, float* out, int64_t n1, int64_t n2, const float* taps,
+                        void* hip_stream)
+{
+    if (!ctx) return ECC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (!in || !out || !taps) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_smooth13: null pointer");
+    if (n1 < 1 || n2 < 1 || n1 > (int64_t(1) << 31) || n2 > (int64_t(1) << 31) || n1 * n2 > (int64_t(1) << 40))
+        return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_smooth13: dims out of range");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed");
+    const size_t bytes = (size_t)n1 * (size_t)n2 * sizeof(float);
+    hipError_t e;
+    if (bytes > ctx->smooth_cap) {
+        if (ctx->smooth_tmp) {
+            if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
+            (void)hipFree(ctx->smooth_tmp);
+            ctx->smooth_tmp = nullptr;
+            ctx->smooth_cap = 0;
+        }
+        if ((e = hipMalloc(&ctx->smooth_tmp, bytes)) != hipSuccess) {
+            ctx->smooth_tmp = nullptr;
+            return hip_fail(ctx, e, "hipMalloc(smoothing buffer)");
+        }
+        ctx->smooth_cap = bytes;
+    }
+    ecc::Taps13 w;
+    for (int k = 0; k < 13; ++k) w.w[k] = taps[k];
+    if ((e = ecc::launch_smooth13(in, out, (float*)ctx->smooth_tmp, n1, n2, w, (hipStream_t)hip_stream)) !=
+        hipSuccess)
+        return hip_fail(ctx, e, "smoothing launch");
+    return ECC_OK;
 }
 
 }  // extern "C"

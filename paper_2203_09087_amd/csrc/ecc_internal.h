@@ -174,6 +174,14 @@ int64_t batch_bricks(BatchImage& im, int waves);
 constexpr int kBatchWaves = ECC_BATCH_WAVES;   // waves per workgroup of the batched kernel
 
 // Launchers (ecc_kernels.hip).  All enqueue on `s` and return the launch status.
+
+// 13 smoothing taps (ecc_smooth.hip): tap k weights the neighbour at offset k - 6.
+struct Taps13 {
+    float w[13];
+};
+// Rows (in -> tmp), then columns (tmp -> out) of an n1 x n2 float image; out may be in.
+hipError_t launch_smooth13(const float* in, float* out, float* tmp, int64_t n1, int64_t n2, const Taps13& w,
+                           hipStream_t s);
 hipError_t launch_minmax(const void* data, int dtype, int64_t nvox, uint32_t* mm_out, int blocks,
                          hipStream_t s);
 hipError_t launch_params_from_minmax(const uint32_t* mm, int blocks, int dtype, int32_t nbins,

@@ -32,7 +32,8 @@ CONSTRUCTIONS = {"vertex": ECC_VERTEX, "top": ECC_TOP}
 # Symbols declared in include/ecc.h.
 EXPORTED = ("ecc_create", "ecc_destroy", "ecc_last_error", "ecc_compute", "ecc_compute_ex",
             "ecc_compute_batch", "ecc_set_kernel_timing", "ecc_kernel_time", "ecc_batch_plan_create",
-            "ecc_batch_plan_launch", "ecc_batch_plan_destroy", "ecc_autotune", "ecc_compute_streamed")
+            "ecc_batch_plan_launch", "ecc_batch_plan_destroy", "ecc_autotune", "ecc_compute_streamed",
+            "ecc_smooth13")
 
 
 class ecc_image(ctypes.Structure):
@@ -105,6 +106,9 @@ def load_library(path: str = LIB_PATH):
     lib.ecc_autotune.restype = ctypes.c_int
     lib.ecc_compute_streamed.argtypes = [vp, ctypes.POINTER(ecc_image), i32, ctypes.c_int64, vp]
     lib.ecc_compute_streamed.restype = ctypes.c_int
+    fltp = ctypes.POINTER(ctypes.c_float)
+    lib.ecc_smooth13.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_int64, fltp, vp]
+    lib.ecc_smooth13.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -180,6 +184,11 @@ def ecc_autotune(ctx: int, img: ecc_image, nbins: int, reps: int, stream: int = 
 
 def ecc_compute_streamed(ctx: int, img: ecc_image, nbins: int, slab_planes: int = 0, stream: int = 0) -> int:
     return load_library().ecc_compute_streamed(ctx, ctypes.byref(img), int(nbins), int(slab_planes), stream)
+
+
+def ecc_smooth13(ctx: int, in_ptr: int, out_ptr: int, n1: int, n2: int, taps, stream: int = 0) -> int:
+    w = (ctypes.c_float * 13)(*[float(t) for t in taps])
+    return load_library().ecc_smooth13(ctx, in_ptr, out_ptr, int(n1), int(n2), w, stream)
 
 
 # ------------------------------------------------------ torch convenience
@@ -290,6 +299,20 @@ class Context:
             out = torch.empty(int(nbins), dtype=torch.int64, device=torch.device("cuda", self.device))
         im = make_image(host_image, out, value_range)
         self._check(ecc_compute_streamed(self.handle, im, nbins, slab_planes, self._stream(stream)))
+        return out
+
+    def smooth13(self, image, taps, out=None, stream=None):
+        """One separable 13-tap smoothing pass of a 2D float32 device tensor
+        (out may be image itself)."""
+        import torch
+        if image.dtype != torch.float32 or image.dim() != 2 or not image.is_contiguous():
+            raise ValueError("smooth13 takes a contiguous 2D float32 tensor")
+        if len(taps) != 13:
+            raise ValueError("smooth13 takes 13 taps")
+        if out is None:
+            out = torch.empty_like(image)
+        self._check(ecc_smooth13(self.handle, image.data_ptr(), out.data_ptr(), image.shape[0], image.shape[1],
+                                 taps, self._stream(stream)))
         return out
 
     def autotune(self, image, nbins: int, value_range=None, reps: int = 5, stream=None):

@@ -18,7 +18,7 @@ HEADER = os.path.join(ROOT, "include", "ecc.h")
 def _declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(ecc_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(ecc_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_boundary():
