@@ -73,10 +73,11 @@ COPY_BYTES = 512 << 20
 
 
 def kernel_sources_sha256():
+    """Hash of the sources the histogram kernel is compiled from."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2203_09087_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in ("ecc_internal.h", "ecc_device.h", "ecc_kernels.hip"):
         h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()
 
@@ -97,6 +98,10 @@ def traffic_run():
         b.copy_(a)
     ctx = ecc.Context(0, "vertex")
     out = torch.empty(4096, dtype=torch.int64, device=dev)
+    # the launch shape the benchmark times (the tuner's own launches come first;
+    # the summary reads the last three dispatches of the histogram kernel)
+    shape = ctx.autotune(vol_d, 4096, value_range=(lo, hi), reps=3)
+    log(f"traffic run shape {shape}")
     for _ in range(3):
         ctx.compute(vol_d, 4096, value_range=(lo, hi), out=out)
     torch.cuda.synchronize()
@@ -111,13 +116,23 @@ def write_traffic(fetch_csv, write_csv):
     import csv
 
     def per_kernel(path, counter):
-        vals = {}
+        # one value per dispatch (rows of one dispatch summed), in dispatch order
+        per = {}
         for r in csv.DictReader(open(path)):
             if r["Counter_Name"] == counter:
-                vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+                key = (int(r["Dispatch_Id"]), r["Kernel_Name"])
+                per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+        vals = {}
+        for (_, name), v in sorted(per.items()):
+            vals.setdefault(name, []).append(v)
         return vals
 
     f, w = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    # the histogram kernel's last three dispatches are the timed launch shape
+    for vals in (f, w):
+        for k in vals:
+            if "k_ecc_3d" in k:
+                vals[k] = vals[k][-3:]
     copy = [k for k in f if "copy" in k.lower()]
     ecck = [k for k in f if "k_ecc_3d" in k]
     if not copy or not ecck:
@@ -155,6 +170,103 @@ def write_traffic(fetch_csv, write_csv):
     with open(TRAFFIC_FILE, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
+
+
+TRACE_FILE = os.path.join(ROOT, "profiles", "k_ecc_3d_f32_512cubed_trace.md")
+SQ_FILE = os.path.join(ROOT, "profiles", "k_ecc_3d_f32_512cubed_sq.md")
+MAIN_KERNEL = "k_ecc_3d<2, 0, false>"
+
+
+def write_trace_summary(db_path, bench_json):
+    """Summarizes a `rocprofv3 --kernel-trace` database of `bench.py --no-side
+    --no-serve --no-cpu` into the profiles folder: every kernel's statistics, and
+    the histogram kernel's mean over the timed launches (the last 2 * steps
+    dispatches: the timed pass and the pass with kernel events) beside the
+    kernel time the benchmark measured itself."""
+    import sqlite3
+    res = json.loads([l for l in open(bench_json) if l.startswith("{")][-1])
+    steps = int(res["steps"])
+    con = sqlite3.connect(db_path)
+    rows = con.execute("select name, start, end from kernels order by start").fetchall()
+    stats = {}
+    for name, a, b in rows:
+        stats.setdefault(name, []).append((b - a) / 1000.0)
+    main = [(b - a) / 1000.0 for name, a, b in rows if MAIN_KERNEL in name]
+    timed = main[-2 * steps:]
+    total = sum(sum(v) for v in stats.values())
+    out = ["# Kernel trace: 512^3 float32 GRF step (bench.py defaults without side runs)", "",
+           "Commands (on one MI355X, from /tmp, $REPO the repository root):", "",
+           f"    rocprofv3 --kernel-trace --stats -d $REPO/gpurun_out/prof -o run -- python3 $REPO/bench.py "
+           f"--steps {steps} --warmup {res['warmup']} --no-cpu --no-side --no-serve > $REPO/gpurun_out/prof.json",
+           "    python3 $REPO/bench.py --trace-summary $REPO/gpurun_out/prof/run_results.db $REPO/gpurun_out/prof.json", "",
+           f"Histogram kernel `{MAIN_KERNEL}` over the {len(timed)} timed launches "
+           f"(launch shape {res.get('launch_shape')}): mean {np.mean(timed):.2f} us, "
+           f"min {np.min(timed):.2f} us, max {np.max(timed):.2f} us.  The benchmark's own HIP-event "
+           f"measurement in the same run: {res['roofline']['kernel_ms'] * 1000:.2f} us per launch "
+           f"(roofline.kernel_ms); step {res['ms_per_step'] * 1000:.1f} us.  Earlier dispatches of the "
+           "kernel are the launch-shape tuner's candidates.", "",
+           "| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---:|---:|---:|---:|---:|"]
+    for name, v in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
+        short = name.replace("ecc::(anonymous namespace)::", "")
+        short = short if len(short) < 70 else short[:67] + "..."
+        out.append(f"| `{short}` | {len(v)} | {np.mean(v):.2f} | {np.min(v):.2f} | {np.max(v):.2f} | "
+                   f"{100 * sum(v) / total:.2f} |")
+    with open(TRACE_FILE, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
+def write_sq_summary(csv_a, csv_b):
+    """Summarizes two SQ counter passes over `bench.py --traffic` (the last three
+    dispatches of the histogram kernel, the timed launch shape) into the
+    profiles folder, with the issue-rate figures derived from them."""
+    import csv
+    vals, meta = {}, {}
+    for path in (csv_a, csv_b):
+        per = {}
+        for r in csv.DictReader(open(path)):
+            if MAIN_KERNEL not in r["Kernel_Name"]:
+                continue
+            key = (int(r["Dispatch_Id"]), r["Counter_Name"])
+            per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+            meta = {k: r[k] for k in ("Grid_Size", "Workgroup_Size", "LDS_Block_Size", "Scratch_Size")}
+        ids = sorted({d for d, _ in per})[-3:]
+        for (d, c), v in per.items():
+            if d in ids:
+                vals.setdefault(c, []).append(v)
+    m = {c: float(np.mean(v)) for c, v in vals.items()}
+    simds, xcds = 1024, 8
+    cyc = m["GRBM_GUI_ACTIVE"] / xcds
+    row_steps = 2 * 512 ** 3 / 62
+    slots = cyc / 4
+    out = [f"# SQ counters: `{MAIN_KERNEL}`, 512^3 float32 GRF, vertex, 4096 bins", "",
+           "Commands (one pass each, from /tmp, $REPO the repository root):", "",
+           "    timeout -s KILL 120 rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_WAVE_CYCLES "
+           "SQ_BUSY_CYCLES SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU --output-format csv -d $REPO/gpurun_out/sqa -o run "
+           "-- python3 $REPO/bench.py --traffic",
+           "    timeout -s KILL 120 rocprofv3 --pmc SQ_INST_CYCLES_SALU SQ_ACTIVE_INST_LDS SQ_LDS_BANK_CONFLICT "
+           "SQ_WAIT_ANY SQ_INSTS_VMEM SQ_ACTIVE_INST_ANY GRBM_GUI_ACTIVE SQ_ACTIVE_INST_MISC --output-format csv "
+           "-d $REPO/gpurun_out/sqb -o run -- python3 $REPO/bench.py --traffic",
+           "    python3 $REPO/bench.py --sq-summary $REPO/gpurun_out/sqa/run_counter_collection.csv "
+           "$REPO/gpurun_out/sqb/run_counter_collection.csv", "",
+           f"Dispatch: grid {meta.get('Grid_Size')} work-items, workgroup {meta.get('Workgroup_Size')}, "
+           f"LDS {meta.get('LDS_Block_Size')} B, scratch {meta.get('Scratch_Size')} B.  Means over the last three "
+           "dispatches (the timed launch shape).", "",
+           "| counter | value |", "|---|---:|"]
+    for c in sorted(m):
+        out.append(f"| {c} | {m[c]:.4g} |")
+    out += ["", "Derived (GRBM_GUI_ACTIVE summed over 8 XCDs; 1024 SIMDs; a slot is one SIMD's",
+            "four-cycle issue turn; a row step is one 64-lane row of one 2D problem, 2 * 512^3 / 62 of them):", "",
+            f"* kernel cycles per XCD: {cyc:.0f} ({cyc / 2.4e3:.1f} us at 2.4 GHz)",
+            f"* VALU instructions per slot per SIMD: {m['SQ_INSTS_VALU'] / simds / slots:.2f}; "
+            f"SALU: {m['SQ_INSTS_SALU'] / simds / slots:.2f}",
+            f"* instructions per row step: VALU {m['SQ_INSTS_VALU'] / row_steps:.1f}, "
+            f"SALU {m['SQ_INSTS_SALU'] / row_steps:.1f}, LDS {m['SQ_INSTS_LDS'] / row_steps:.2f}, "
+            f"VMEM {m['SQ_INSTS_VMEM'] / row_steps:.2f}",
+            f"* mean resident waves per SIMD: {4 * m['SQ_WAVE_CYCLES'] / (cyc * simds):.2f}"]
+    with open(SQ_FILE, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print("\n".join(out))
 
 
 def cpu_baseline(vol, nbins, lo, hi, target_s=12.0):
@@ -256,9 +368,19 @@ def main():
     ap.add_argument("--traffic", action="store_true", help="only the program the counter passes profile")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarize the two counter passes into the profiles folder")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("RESULTS_DB", "BENCH_JSON"),
+                    help="summarize a kernel-trace database into the profiles folder")
+    ap.add_argument("--sq-summary", nargs=2, metavar=("CSV_A", "CSV_B"),
+                    help="summarize the two SQ counter passes into the profiles folder")
     args = ap.parse_args()
     if args.write_traffic:
         write_traffic(*args.write_traffic)
+        return
+    if args.trace_summary:
+        write_trace_summary(*args.trace_summary)
+        return
+    if args.sq_summary:
+        write_sq_summary(*args.sq_summary)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; the histogram of a multi-GPU "

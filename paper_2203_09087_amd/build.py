@@ -12,7 +12,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libecc_hip.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("ecc_api.hip", "ecc_kernels.hip", "ecc_batch.hip", "ecc_smooth.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("ecc_api.hip", "ecc_kernels.hip", "ecc_reduce.hip", "ecc_batch.hip", "ecc_smooth.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -173,7 +173,8 @@ int64_t batch_bricks(BatchImage& im, int waves);
 #endif
 constexpr int kBatchWaves = ECC_BATCH_WAVES;   // waves per workgroup of the batched kernel
 
-// Launchers (ecc_kernels.hip).  All enqueue on `s` and return the launch status.
+// Launchers (ecc_kernels.hip: histogram kernels; ecc_reduce.hip: min/max,
+// parameters, merge).  All enqueue on `s` and return the launch status.
 
 // 13 smoothing taps (ecc_smooth.hip): tap k weights the neighbour at offset k - 6.
 struct Taps13 {

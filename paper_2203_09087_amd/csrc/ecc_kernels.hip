@@ -1,7 +1,7 @@
-// ecc_kernels.hip -- gfx950 kernels of the ECC library for one image: the
-// persistent main kernels (2D and 3D), the AUTO-range min/max pass, and the merge
-// of workgroup histograms with the prefix scan.  The method and its mapping to
-// the hardware are described in ecc_device.h.
+// ecc_kernels.hip -- the histogram kernels of the ECC library for one image (2D
+// and 3D) and their launchers.  The method and its mapping to the hardware are
+// described in ecc_device.h; the min/max pass and the merge are in
+// ecc_reduce.hip.
 #include "ecc_device.h"
 
 namespace ecc {
@@ -48,179 +48,10 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
     flush_hist(hist, L.partials + (size_t)blockIdx.x * (size_t)L.width, L.width);
 }
 
-// ------------------------------------------------------------------- minmax
-
-// Grid-stride min/max over the image with 16-byte loads; the unaligned head and
-// the tail are read element by element.  Writes one (lo, hi) pair per block.
-template <int DT>
-__global__ __launch_bounds__(kThreads) void k_minmax(const void* data, int64_t nvox, uint32_t* mm)
-{
-    using T = typename ValT<DT>::T;
-    constexpr int PER = 16 / (int)sizeof(T);
-    const T* __restrict__ img = (const T*)data;
-    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
-    const int64_t tid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    const int64_t nthreads = (int64_t)gridDim.x * kThreads;
-    const uintptr_t addr = (uintptr_t)data;
-    int64_t head = (int64_t)(((16 - (addr & 15)) & 15) / sizeof(T));
-    if (head > nvox) head = nvox;
-    if (tid < head) mm_take<DT>(img[tid], lo, hi);
-    const int64_t nvec = (nvox - head) / PER;
-    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-    const u32x4* __restrict__ vec = (const u32x4*)(img + head);
-    for (int64_t i = tid; i < nvec; i += nthreads) {
-        const u32x4 w = __builtin_nontemporal_load(vec + i);
-        const T* e = (const T*)&w;
-#pragma unroll
-        for (int k = 0; k < PER; ++k) mm_take<DT>(e[k], lo, hi);
-    }
-    for (int64_t i = head + nvec * PER + tid; i < nvox; i += nthreads) mm_take<DT>(img[i], lo, hi);
-    block_minmax(lo, hi);
-    if (threadIdx.x == 0) {
-        mm[2 * blockIdx.x] = lo;
-        mm[2 * blockIdx.x + 1] = hi;
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void k_params(const uint32_t* mm, int blocks, int dtype,
-                                                     int32_t nbins, BinParams* out)
-{
-    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
-    for (int i = threadIdx.x; i < blocks; i += kThreads) {
-        lo = min(lo, mm[2 * i]);
-        hi = max(hi, mm[2 * i + 1]);
-    }
-    block_minmax(lo, hi);
-    if (threadIdx.x == 0) *out = params_from_keys(lo, hi, dtype, nbins);
-}
-
-// --------------------------------------------------------- merge and scan
-
-// Merge of the workgroup histograms, in two launches with no fence between
-// blocks of one launch (a device-scope release per block costs an L2 write-back
-// on every XCD that takes part):
-//   k_merge_groups: block (bx, g) sums rows [r0, r1) of group g for bins
-//                   bx*256 .. +255 into level2[g] (int64), and with `btot` also
-//                   the total of those 256 sums into btot[g][bx];
-//   k_merge_final:  block bx adds the groups of its bins.  When the window is
-//                   the whole histogram and `scan` is set, every block scans its
-//                   own bins, offset by the totals of the blocks before it (from
-//                   btot), so the ECC needs no last-block pass.  Otherwise the
-//                   block writes the VCEC of its bins, and with `scan` the last
-//                   block to finish prefix-sums out[0..nbins) and re-arms its
-//                   counter (histograms wider than one LDS window).
-
-// True in every thread of the block that is the last of `total` to arrive.
-__device__ __forceinline__ bool last_to_arrive(uint32_t* counter, uint32_t total)
-{
-    __shared__ bool last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == total - 1;
-    __syncthreads();
-    if (last) __threadfence();
-    return last;
-}
-
-// Inclusive scan of one value per thread across the block; returns the
-// thread's scanned value, and the block total in *total.
-__device__ __forceinline__ int64_t block_scan_values(int64_t v, int64_t* total)
-{
-    __shared__ int64_t buf[kThreads];
-    const int t = threadIdx.x;
-    buf[t] = v;
-    __syncthreads();
-    for (int off = 1; off < kThreads; off <<= 1) {
-        const int64_t add = t >= off ? buf[t - off] : 0;
-        __syncthreads();
-        buf[t] += add;
-        __syncthreads();
-    }
-    const int64_t r = buf[t];
-    *total = buf[kThreads - 1];
-    __syncthreads();
-    return r;
-}
-
-__global__ __launch_bounds__(kThreads) void k_merge_groups(const int32_t* __restrict__ partials, int rows,
-                                                           int32_t width, int64_t* __restrict__ level2,
-                                                           int64_t* __restrict__ btot)
-{
-    const int j = blockIdx.x * kThreads + threadIdx.x;
-    const int G = gridDim.y, g = blockIdx.y;
-    const int r0 = (int)((int64_t)rows * g / G), r1 = (int)((int64_t)rows * (g + 1) / G);
-    int64_t s = 0;
-    if (j < width) {
-#pragma unroll 8
-        for (int r = r0; r < r1; ++r) s += partials[(size_t)r * (size_t)width + j];
-        level2[(size_t)g * width + j] = s;
-    }
-    if (btot) {
-        int64_t total;
-        block_scan_values(s, &total);
-        if (threadIdx.x == 0) btot[(size_t)g * gridDim.x + blockIdx.x] = total;
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void k_merge_final(const int64_t* __restrict__ level2,
-                                                          const int64_t* __restrict__ btot, int groups,
-                                                          int32_t width, int32_t bin_lo, int64_t* out,
-                                                          int32_t nbins, uint32_t* counter, int accumulate,
-                                                          int scan)
-{
-    const int j = blockIdx.x * kThreads + threadIdx.x;
-    int64_t t = 0;
-    if (j < width) {
-#pragma unroll 8
-        for (int g = 0; g < groups; ++g) t += level2[(size_t)g * width + j];
-    }
-    if (btot) {
-        // offset = sum of the bins of the blocks before this one
-        int64_t part = 0;
-        const int n = groups * (int)blockIdx.x;
-        for (int i = threadIdx.x; i < n; i += kThreads) {
-            const int g = i / (int)blockIdx.x, b = i - g * (int)blockIdx.x;
-            part += btot[(size_t)g * gridDim.x + b];
-        }
-        int64_t offset;
-        block_scan_values(part, &offset);
-        int64_t dummy;
-        const int64_t inc = block_scan_values(t, &dummy);
-        if (j < width) out[bin_lo + j] = offset + inc;
-        return;
-    }
-    if (j < width) out[bin_lo + j] = (accumulate ? out[bin_lo + j] : 0) + t;
-    if (!scan) return;
-    if (!last_to_arrive(counter, gridDim.x)) return;
-    block_scan_inplace(out, nbins);
-    if (threadIdx.x == 0) atomicExch(counter, 0u);
-}
-
-// Folds the per-block min/max keys of one slab into a running pair acc[0..1]
-// (first: start the pair).
-__global__ __launch_bounds__(kThreads) void k_mm_fold(const uint32_t* mm, int blocks, uint32_t* acc, int first)
-{
-    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
-    for (int i = threadIdx.x; i < blocks; i += kThreads) {
-        lo = min(lo, mm[2 * i]);
-        hi = max(hi, mm[2 * i + 1]);
-    }
-    block_minmax(lo, hi);
-    if (threadIdx.x == 0) {
-        acc[0] = first ? lo : min(acc[0], lo);
-        acc[1] = first ? hi : max(acc[1], hi);
-    }
-}
-
 }  // namespace
 
 // ----------------------------------------------------------------- launchers
 
-hipError_t launch_mm_fold(const uint32_t* mm, int blocks, uint32_t* acc, bool first, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_mm_fold, dim3(1), dim3(kThreads), 0, s, mm, blocks, acc, first ? 1 : 0);
-    return hipGetLastError();
-}
 
 int64_t wg_bricks(int ndim, const Geom& g, int waves, int64_t depth)
 {
@@ -311,40 +142,5 @@ int resident_wgs_per_cu(int ndim, int dtype, int construction, bool windowed, in
     return c;
 }
 
-hipError_t launch_merge(const int32_t* partials, int rows, int32_t width, int32_t bin_lo, int64_t* level2,
-                        int64_t* out, int32_t nbins, uint32_t* counters, bool accumulate, bool scan, hipStream_t s)
-{
-    const unsigned bx = (unsigned)((width + kThreads - 1) / kThreads);
-    const int groups = rows < kMergeGroups ? rows : kMergeGroups;
-    // one window holding every bin, written afresh: blocks scan their own bins
-    // (see k_merge_final)
-    int64_t* btot = (scan && !accumulate && bin_lo == 0 && width == nbins)
-                        ? level2 + (size_t)kMergeGroups * width : nullptr;
-    hipLaunchKernelGGL(k_merge_groups, dim3(bx, (unsigned)groups), dim3(kThreads), 0, s, partials, rows, width,
-                       level2, btot);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_merge_final, dim3(bx), dim3(kThreads), 0, s, level2, btot, groups, width, bin_lo, out,
-                       nbins, counters, accumulate ? 1 : 0, scan ? 1 : 0);
-    return hipGetLastError();
-}
-
-hipError_t launch_minmax(const void* data, int dtype, int64_t nvox, uint32_t* mm, int blocks,
-                         hipStream_t s)
-{
-    switch (dtype) {
-    case DT_U8: hipLaunchKernelGGL(k_minmax<DT_U8>, dim3(blocks), dim3(kThreads), 0, s, data, nvox, mm); break;
-    case DT_U16: hipLaunchKernelGGL(k_minmax<DT_U16>, dim3(blocks), dim3(kThreads), 0, s, data, nvox, mm); break;
-    default: hipLaunchKernelGGL(k_minmax<DT_F32>, dim3(blocks), dim3(kThreads), 0, s, data, nvox, mm); break;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_params_from_minmax(const uint32_t* mm, int blocks, int dtype, int32_t nbins,
-                                     BinParams* out, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_params, dim3(1), dim3(kThreads), 0, s, mm, blocks, dtype, nbins, out);
-    return hipGetLastError();
-}
 
 }  // namespace ecc
