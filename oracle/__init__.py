@@ -88,7 +88,7 @@ def _as_image(image):
     a = np.ascontiguousarray(image)
     if a.dtype not in DTYPES:
         raise TypeError(f"unsupported dtype {a.dtype}")
-    if a.ndim < 1 or a.ndim > 3 or a.size == 0:
+    if a.ndim < 1 or a.ndim > 4 or a.size == 0:
         raise ValueError(f"unsupported shape {a.shape}")
     return a
 

@@ -1,6 +1,7 @@
 /*
  * ecc_oracle.c -- reference ("oracle") computation of the Euler characteristic
- * curve of a 1D/2D/3D grayscale image.
+ * curve of a 1D/2D/3D/4D grayscale image (the definitions are the same in every
+ * dimension, Sec. 2.1).
  *
  * TEST INFRASTRUCTURE ONLY.  This file is a plain, slow, obviously correct CPU
  * implementation used to check the GPU library bit for bit.  It shares no code,
@@ -51,7 +52,7 @@ enum { ORACLE_U8 = 0, ORACLE_U16 = 1, ORACLE_F32 = 2 };
 enum { ORACLE_VERTEX = 0, ORACLE_TOP = 1 };
 enum { ORACLE_RANGE_DEFAULT = 0, ORACLE_RANGE_EXPLICIT = 1, ORACLE_RANGE_AUTO = 2 };
 
-#define ORACLE_MAX_NDIM 3
+#define ORACLE_MAX_NDIM 4
 
 /* ---------------------------------------------------------------- binning */
 
@@ -150,6 +151,17 @@ typedef struct {
     int64_t* hist;                   /* int64[nbins], owned by the worker */
 } oracle_job;
 
+/* Advances the anchor a[1..d-1] through [0, lim[i]) (last axis fastest) and then
+ * a[0] through [a0_begin, a0_end).  Returns 0 when every anchor was visited. */
+static int next_anchor(int64_t* a, const int64_t* lim, int d, int64_t a0_end)
+{
+    for (int i = d - 1; i >= 1; --i) {
+        if (++a[i] < lim[i]) return 1;
+        a[i] = 0;
+    }
+    return ++a[0] < a0_end;
+}
+
 /* VERTEX construction.  A cell is the block of voxels  a + {0..s_0} x ... ,
  * s in {0,1}^d, lying inside the image; its dimension is |s| and its value is
  * the maximum bin over its 2^|s| voxels (its vertices). Each cell has exactly one
@@ -157,12 +169,12 @@ typedef struct {
 static void cells_vertex(oracle_job* J)
 {
     const int d = J->ndim;
-    int64_t a[ORACLE_MAX_NDIM] = {0, 0, 0};
-    int64_t lim[ORACLE_MAX_NDIM] = {1, 1, 1};
+    int64_t a[ORACLE_MAX_NDIM] = {0};
+    int64_t lim[ORACLE_MAX_NDIM];
     for (int i = 0; i < d; ++i) lim[i] = J->n[i];
-    for (a[0] = J->a0_begin; a[0] < J->a0_end; ++a[0])
-    for (a[1] = 0; a[1] < (d > 1 ? lim[1] : 1); ++a[1])
-    for (a[2] = 0; a[2] < (d > 2 ? lim[2] : 1); ++a[2]) {
+    if (J->a0_begin >= J->a0_end) return;
+    a[0] = J->a0_begin;
+    do {
         for (int s = 0; s < (1 << d); ++s) {
             int ok = 1, dim = 0;
             for (int i = 0; i < d; ++i)
@@ -178,7 +190,7 @@ static void cells_vertex(oracle_job* J)
             }
             J->hist[value] += (dim & 1) ? -1 : 1;
         }
-    }
+    } while (next_anchor(a, lim, d, J->a0_end));
 }
 
 /* TOP construction (the paper's).  Voxel v is the closed cube prod [v_i, v_i+1].
@@ -190,12 +202,12 @@ static void cells_vertex(oracle_job* J)
 static void cells_top(oracle_job* J)
 {
     const int d = J->ndim;
-    int64_t a[ORACLE_MAX_NDIM] = {0, 0, 0};
-    int64_t lim[ORACLE_MAX_NDIM] = {1, 1, 1};
+    int64_t a[ORACLE_MAX_NDIM] = {0};
+    int64_t lim[ORACLE_MAX_NDIM];
     for (int i = 0; i < d; ++i) lim[i] = J->n[i] + 1;   /* lattice points 0..n_i */
-    for (a[0] = J->a0_begin; a[0] < J->a0_end; ++a[0])
-    for (a[1] = 0; a[1] < (d > 1 ? lim[1] : 1); ++a[1])
-    for (a[2] = 0; a[2] < (d > 2 ? lim[2] : 1); ++a[2]) {
+    if (J->a0_begin >= J->a0_end) return;
+    a[0] = J->a0_begin;
+    do {
         for (int s = 0; s < (1 << d); ++s) {
             int ok = 1, dim = 0;
             int64_t vlo[ORACLE_MAX_NDIM], vhi[ORACLE_MAX_NDIM];  /* voxel range per axis */
@@ -210,18 +222,21 @@ static void cells_top(oracle_job* J)
                 }
             }
             if (!ok) continue;
+            /* minimum over the box of voxels vlo..vhi (at most 2 per axis) */
             int32_t value = J->nbins;   /* larger than any bin */
-            int64_t v[ORACLE_MAX_NDIM] = {0, 0, 0};
-            for (v[0] = vlo[0]; v[0] <= vhi[0]; ++v[0])
-            for (v[1] = (d > 1 ? vlo[1] : 0); v[1] <= (d > 1 ? vhi[1] : 0); ++v[1])
-            for (v[2] = (d > 2 ? vlo[2] : 0); v[2] <= (d > 2 ? vhi[2] : 0); ++v[2]) {
+            for (int t = 0; t < (1 << d); ++t) {
                 int64_t idx = 0;
-                for (int i = 0; i < d; ++i) idx += v[i] * J->stride[i];
-                if (J->bins[idx] < value) value = J->bins[idx];
+                int inside = 1;
+                for (int i = 0; i < d; ++i) {
+                    const int64_t v = vlo[i] + (t >> i & 1);
+                    if (v > vhi[i]) { inside = 0; break; }
+                    idx += v * J->stride[i];
+                }
+                if (inside && J->bins[idx] < value) value = J->bins[idx];
             }
             J->hist[value] += (dim & 1) ? -1 : 1;
         }
-    }
+    } while (next_anchor(a, lim, d, J->a0_end));
 }
 
 static void* oracle_worker(void* arg)
