@@ -35,7 +35,9 @@
  *
  * Conventions shared by every entry point:
  *   - Images are DEVICE pointers, contiguous, row-major, dims[0] slowest.  Any
- *     alignment is accepted.  ndim is 2 or 3; every dim is >= 1.
+ *     alignment is accepted.  ndim is 2 or 3 (also 4 for ecc_compute and
+ *     ecc_compute_ex, see there; the other entry points return
+ *     ECC_ERR_UNSUPPORTED for a 4D image); every dim is >= 1.
  *   - `out` is a DEVICE pointer to nbins int64 values, overwritten (not
  *     accumulated) with the ECC.  1 <= nbins <= 65535.
  *   - Every call validates all of its arguments on the host before anything is
@@ -83,9 +85,9 @@ typedef enum {
 /* One image of a call.  Enum-valued fields are int32_t for a fixed layout. */
 typedef struct {
     const void* data;    /* device pointer to the voxels */
-    int32_t ndim;        /* 2 or 3 */
+    int32_t ndim;        /* 2 or 3; 4 for ecc_compute_ex */
     int32_t dtype;       /* ecc_dtype */
-    int64_t dims[3];     /* dims[0] slowest; entries beyond ndim are ignored */
+    int64_t dims[4];     /* dims[0] slowest; entries beyond ndim are ignored */
     int32_t range_mode;  /* ecc_range_mode */
     int32_t reserved;    /* must be 0 */
     double lo, hi;       /* used with ECC_RANGE_EXPLICIT only */
@@ -109,16 +111,21 @@ ecc_status ecc_destroy(ecc_ctx* ctx);
 const char* ecc_last_error(const ecc_ctx* ctx);
 
 /* ECC of one image with the default range (Eq. (1), Sec. 2.3).
- * image: device pointer; ndim 2|3; dims: HOST pointer to ndim int64;
+ * image: device pointer; ndim 2|3|4; dims: HOST pointer to ndim int64;
  * dtype: ecc_dtype; out: device pointer to nbins int64 (overwritten).
+ * A 4D image (the cubical complex of Sec. 2.1 in four dimensions) is computed as
+ * signed 3D passes over its hyperplanes dims[0] and over the elementwise max
+ * (vertex) or min (top) of adjacent hyperplanes, which the context combines into
+ * a buffer of one hyperplane that it allocates (and keeps) on first use.
  * Errors: ECC_ERR_INVALID_ARG for any bad argument (nothing enqueued),
  * ECC_ERR_OUT_OF_MEMORY, ECC_ERR_DEVICE. */
 ecc_status ecc_compute(ecc_ctx* ctx, const void* image, int32_t ndim, const int64_t* dims,
                        int32_t dtype, int32_t nbins, int64_t* out, void* hip_stream);
 
 /* ECC of one image described by `img` (HOST pointer to the descriptor; its data
- * and out fields are device pointers).  Same semantics and errors as ecc_compute,
- * plus the range selection of the descriptor. */
+ * and out fields are device pointers).  Same semantics and errors as ecc_compute
+ * (ndim 2|3|4), plus the range selection of the descriptor; an AUTO range of a
+ * 4D image is the min/max of all its hyperplanes. */
 ecc_status ecc_compute_ex(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, void* hip_stream);
 
 /* ECC of `count` images in one persistent launch.  imgs: HOST array of `count`

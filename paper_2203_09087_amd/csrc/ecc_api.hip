@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <map>
 #include <tuple>
@@ -40,6 +41,9 @@ struct ecc_ctx {
     // intermediate buffer of ecc_smooth13
     void* smooth_tmp = nullptr;
     size_t smooth_cap = 0;
+    // 4D images: the max (min) of two adjacent hyperplanes
+    void* pair_buf = nullptr;
+    size_t pair_cap = 0;
     // launch shapes chosen by ecc_autotune, by image shape (see TuneKey)
     std::map<std::tuple<int, int, int, int, int64_t, int64_t, int64_t>, ecc_launch_shape> tuned;
     // kernel timing (ecc_set_kernel_timing): event pairs around histogram launches
@@ -152,22 +156,34 @@ ecc_status ensure_ws(ecc_ctx* ctx, size_t bytes)
 }
 
 // Validated form of one image.
+// the descriptor layout the bindings mirror
+static_assert(sizeof(ecc_image) == 80 && offsetof(ecc_image, dims) == 16 && offsetof(ecc_image, range_mode) == 48 &&
+                  offsetof(ecc_image, lo) == 56 && offsetof(ecc_image, out) == 72,
+              "ecc_image layout");
+
 struct Job {
     const void* data;
     int ndim, dtype, range_mode;
-    ecc::Geom g;
+    ecc::Geom g;          // 2D/3D: the image; 4D: one hyperplane (dims[1..3])
+    int64_t nw;           // 4D: hyperplanes (dims[0]); else 1
     int64_t nvox;
     double lo, hi;
     int64_t* out;
 };
 
-ecc_status validate(ecc_ctx* ctx, const ecc_image& im, int32_t nbins, const char* where, Job* job)
+// max_ndim: 4 for the single-image calls, 3 where 4D images are not taken.
+ecc_status validate(ecc_ctx* ctx, const ecc_image& im, int32_t nbins, const char* where, Job* job,
+                    int max_ndim = 3)
 {
     char buf[256];
     if (!im.data) { snprintf(buf, sizeof buf, "%s: null image pointer", where); return fail(ctx, ECC_ERR_INVALID_ARG, buf); }
     if (!im.out) { snprintf(buf, sizeof buf, "%s: null output pointer", where); return fail(ctx, ECC_ERR_INVALID_ARG, buf); }
-    if (im.ndim != 2 && im.ndim != 3) {
-        snprintf(buf, sizeof buf, "%s: ndim must be 2 or 3 (got %d)", where, im.ndim);
+    if (im.ndim == 4 && max_ndim < 4) {
+        snprintf(buf, sizeof buf, "%s: 4D images are computed by ecc_compute and ecc_compute_ex only", where);
+        return fail(ctx, ECC_ERR_UNSUPPORTED, buf);
+    }
+    if (im.ndim < 2 || im.ndim > 4) {
+        snprintf(buf, sizeof buf, "%s: ndim must be 2, 3 or 4 (got %d)", where, im.ndim);
         return fail(ctx, ECC_ERR_INVALID_ARG, buf);
     }
     if (im.dtype != ECC_U8 && im.dtype != ECC_U16 && im.dtype != ECC_F32) {
@@ -228,8 +244,13 @@ ecc_status validate(ecc_ctx* ctx, const ecc_image& im, int32_t nbins, const char
         job->range_mode = im.dtype == ECC_U8 ? ECC_RANGE_EXPLICIT : ECC_RANGE_AUTO;
     job->lo = im.range_mode == ECC_RANGE_DEFAULT ? 0.0 : im.lo;
     job->hi = im.range_mode == ECC_RANGE_DEFAULT ? 255.0 : im.hi;
+    job->nw = 1;
     if (im.ndim == 2) job->g = {1, im.dims[0], im.dims[1]};
-    else job->g = {im.dims[0], im.dims[1], im.dims[2]};
+    else if (im.ndim == 3) job->g = {im.dims[0], im.dims[1], im.dims[2]};
+    else {
+        job->g = {im.dims[1], im.dims[2], im.dims[3]};
+        job->nw = im.dims[0];
+    }
     job->nvox = nvox;
     job->out = im.out;
     return ECC_OK;
@@ -335,7 +356,7 @@ Sizes plan_sizes(const ecc_ctx* ctx, const Job& j, int32_t nbins, const ecc_laun
 // scan: prefix-sum out after the last window.
 ecc_status enqueue_hist(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t stream, const Sizes& sz,
                         const ecc::BinParams* pdev, int64_t z_own, int64_t z_base, int64_t n0_global,
-                        bool accumulate, bool scan)
+                        bool accumulate, bool scan, int sign = 1)
 {
     char* base = (char*)ctx->ws;
     uint32_t* counters = (uint32_t*)(base + sz.off_counters);
@@ -365,7 +386,7 @@ ecc_status enqueue_hist(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t s
         if ((e = timed_launch(ctx, stream, [&] { return ecc::launch_ecc(L, stream); })) != hipSuccess)
             return hip_fail(ctx, e, "ecc launch");
         if ((e = ecc::launch_merge(L.partials, L.grid, L.width, L.bin_lo, (int64_t*)(base + sz.off_level2),
-                                   j.out, nbins, counters, accumulate, scan && last, stream)) != hipSuccess)
+                                   j.out, nbins, counters, accumulate, scan && last, sign, stream)) != hipSuccess)
             return hip_fail(ctx, e, "merge launch");
     }
     return ECC_OK;
@@ -390,6 +411,85 @@ ecc_status enqueue_one(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t st
             return hip_fail(ctx, e, "params launch");
     }
     return enqueue_hist(ctx, j, nbins, stream, sz, pdev, j.g.n0, 0, j.g.n0, false, true);
+}
+
+// A 4D image as signed 3D passes (the cells of a 4D complex are 3D cells times
+// a vertex or an edge of the last axis, Sec. 2.1).  With H_w the hyperplanes:
+//   vertex: VCEC = sum_w V3(H_w) - sum_{w<n-1} V3(max(H_w, H_{w+1}))
+//   top:    VCEC = sum_w c_w T3(H_w) + sum_{w<n-1} T3(min(H_w, H_{w+1})),
+//           c_w = -1 + [w == 0] + [w == n-1]
+// Each pair is combined into a context buffer, then counted like a hyperplane;
+// every pass adds into (or subtracts from) the caller's output, the last one
+// scans it.  The binning parameters are the whole image's.
+ecc_status ensure_pair_buf(ecc_ctx* ctx, size_t bytes)
+{
+    if (bytes <= ctx->pair_cap) return ECC_OK;
+    hipError_t e;
+    if (ctx->pair_buf) {
+        // earlier calls on any stream may still read the old buffer
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
+        (void)hipFree(ctx->pair_buf);
+        ctx->pair_buf = nullptr;
+        ctx->pair_cap = 0;
+    }
+    if ((e = hipMalloc(&ctx->pair_buf, bytes)) != hipSuccess) {
+        ctx->pair_buf = nullptr;
+        return hip_fail(ctx, e, "hipMalloc(hyperplane pair)");
+    }
+    ctx->pair_cap = bytes;
+    return ECC_OK;
+}
+
+ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t stream)
+{
+    const int64_t nw = j4.nw;
+    const int64_t hv = j4.g.n0 * j4.g.n1 * j4.g.n2;
+    const size_t esize = j4.dtype == ECC_U8 ? 1 : (j4.dtype == ECC_U16 ? 2 : 4);
+    Job h = j4;   // one hyperplane as a 3D image
+    h.ndim = 3;
+    h.nw = 1;
+    h.nvox = hv;
+    const Sizes sz = plan_sizes(ctx, h, nbins);
+    ecc_status st = ensure_ws(ctx, sz.total);
+    if (st != ECC_OK) return st;
+    if (nw > 1 && (st = ensure_pair_buf(ctx, (size_t)hv * esize)) != ECC_OK) return st;
+    char* base = (char*)ctx->ws;
+    ecc::BinParams* pdev = nullptr;
+    hipError_t e;
+    if (j4.range_mode == ECC_RANGE_AUTO) {
+        uint32_t* mm = (uint32_t*)(base + sz.off_mm);
+        pdev = (ecc::BinParams*)(base + sz.off_params);
+        const int blocks = (int)std::min<int64_t>(kMinmaxBlocks, (j4.nvox + 4095) / 4096);
+        if ((e = ecc::launch_minmax(j4.data, j4.dtype, j4.nvox, mm, blocks, stream)) != hipSuccess)
+            return hip_fail(ctx, e, "minmax launch");
+        if ((e = ecc::launch_params_from_minmax(mm, blocks, j4.dtype, nbins, pdev, stream)) != hipSuccess)
+            return hip_fail(ctx, e, "params launch");
+    }
+    const char* img = (const char*)j4.data;
+    const bool vertex = ctx->construction == ECC_VERTEX;
+    // the passes in order: (source, sign); a null source is the pair buffer
+    struct Pass { const void* src; int sign; int64_t pair; };
+    std::vector<Pass> passes;
+    for (int64_t w = 0; w < nw; ++w) {
+        const int c = vertex ? 1 : -1 + (w == 0) + (w == nw - 1);
+        if (c != 0) passes.push_back({img + (size_t)w * (size_t)hv * esize, c, -1});
+        if (w + 1 < nw) passes.push_back({nullptr, vertex ? -1 : 1, w});
+    }
+    for (size_t k = 0; k < passes.size(); ++k) {
+        const Pass& p = passes[k];
+        h.data = p.src;
+        if (p.pair >= 0) {
+            const char* a = img + (size_t)p.pair * (size_t)hv * esize;
+            if ((e = ecc::launch_pair_combine(a, a + (size_t)hv * esize, ctx->pair_buf, j4.dtype, hv, vertex,
+                                              stream)) != hipSuccess)
+                return hip_fail(ctx, e, "pair launch");
+            h.data = ctx->pair_buf;
+        }
+        if ((st = enqueue_hist(ctx, h, nbins, stream, sz, pdev, h.g.n0, 0, h.g.n0, k > 0, k + 1 == passes.size(),
+                               p.sign)) != ECC_OK)
+            return st;
+    }
+    return ECC_OK;
 }
 
 // ------------------------------------------------------------------ batches
@@ -789,6 +889,7 @@ ecc_status ecc_destroy(ecc_ctx* ctx)
         }
         if (ctx->copy_stream) (void)hipStreamDestroy(ctx->copy_stream);
         if (ctx->smooth_tmp) (void)hipFree(ctx->smooth_tmp);
+        if (ctx->pair_buf) (void)hipFree(ctx->pair_buf);
     }
     delete ctx;
     return ECC_OK;
@@ -805,10 +906,11 @@ ecc_status ecc_compute_ex(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, voi
     ctx->err.clear();
     if (!img) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_compute_ex: null descriptor");
     Job j;
-    ecc_status st = validate(ctx, *img, nbins, "ecc_compute_ex", &j);
+    ecc_status st = validate(ctx, *img, nbins, "ecc_compute_ex", &j, 4);
     if (st != ECC_OK) return st;
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed");
+    if (j.ndim == 4) return enqueue_4d(ctx, j, nbins, (hipStream_t)hip_stream);
     return enqueue_one(ctx, j, nbins, (hipStream_t)hip_stream);
 }
 
@@ -818,7 +920,7 @@ ecc_status ecc_compute(ecc_ctx* ctx, const void* image, int32_t ndim, const int6
     if (!ctx) return ECC_ERR_INVALID_ARG;
     ctx->err.clear();
     if (!dims) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_compute: null dims");
-    if (ndim != 2 && ndim != 3) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_compute: ndim must be 2 or 3");
+    if (ndim < 2 || ndim > 4) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_compute: ndim must be 2, 3 or 4");
     ecc_image im;
     memset(&im, 0, sizeof im);
     im.data = image;
@@ -828,10 +930,11 @@ ecc_status ecc_compute(ecc_ctx* ctx, const void* image, int32_t ndim, const int6
     im.range_mode = ECC_RANGE_DEFAULT;
     im.out = out;
     Job j;
-    ecc_status st = validate(ctx, im, nbins, "ecc_compute", &j);
+    ecc_status st = validate(ctx, im, nbins, "ecc_compute", &j, 4);
     if (st != ECC_OK) return st;
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed");
+    if (j.ndim == 4) return enqueue_4d(ctx, j, nbins, (hipStream_t)hip_stream);
     return enqueue_one(ctx, j, nbins, (hipStream_t)hip_stream);
 }
 

@@ -196,9 +196,15 @@ constexpr int kMergeGroups = 32;
 // group sums (kMergeGroups x window) and per-group totals of 256-bin blocks
 constexpr size_t kLevel2Words = (size_t)kMergeGroups * (kMaxLdsBins + kMaxLdsBins / 256);
 constexpr int kCounterWords = 256;
-// accumulate: add to out instead of writing it (slabs of a streamed volume).
+// accumulate: add to out instead of writing it (slabs of a streamed volume, the
+// 3D passes of a 4D image); sign -1: subtract the sums.
 hipError_t launch_merge(const int32_t* partials, int rows, int32_t width, int32_t bin_lo, int64_t* level2,
-                        int64_t* out, int32_t nbins, uint32_t* counters, bool accumulate, bool scan, hipStream_t s);
+                        int64_t* out, int32_t nbins, uint32_t* counters, bool accumulate, bool scan, int sign,
+                        hipStream_t s);
+// out[i] = max (take_max) or min of a[i] and b[i] for i < n, in the order of their
+// bins (NaN above every number).
+hipError_t launch_pair_combine(const void* a, const void* b, void* out, int dtype, int64_t n, bool take_max,
+                               hipStream_t s);
 // Folds `blocks` min/max key pairs into the running pair acc (first: start it).
 hipError_t launch_mm_fold(const uint32_t* mm, int blocks, uint32_t* acc, bool first, hipStream_t s);
 

@@ -64,7 +64,8 @@ __global__ __launch_bounds__(kThreads) void k_params(const uint32_t* mm, int blo
 //   k_merge_groups: block (bx, g) sums rows [r0, r1) of group g for bins
 //                   bx*256 .. +255 into level2[g] (int64), and with `btot` also
 //                   the total of those 256 sums into btot[g][bx];
-//   k_merge_final:  block bx adds the groups of its bins.  When the window is
+//   k_merge_final:  block bx adds the groups of its bins (negated with sign
+//                   -1: the 4D path subtracts some 3D passes).  When the window is
 //                   the whole histogram and `scan` is set, every block scans its
 //                   own bins, offset by the totals of the blocks before it (from
 //                   btot), so the ECC needs no last-block pass.  Otherwise the
@@ -128,7 +129,7 @@ __global__ __launch_bounds__(kThreads) void k_merge_final(const int64_t* __restr
                                                           const int64_t* __restrict__ btot, int groups,
                                                           int32_t width, int32_t bin_lo, int64_t* out,
                                                           int32_t nbins, uint32_t* counter, int accumulate,
-                                                          int scan)
+                                                          int scan, int sign)
 {
     const int j = blockIdx.x * kThreads + threadIdx.x;
     int64_t t = 0;
@@ -153,7 +154,7 @@ __global__ __launch_bounds__(kThreads) void k_merge_final(const int64_t* __restr
         if (j < width) out[bin_lo + j] = offset + inc;
         return;
     }
-    if (j < width) out[bin_lo + j] = (accumulate ? out[bin_lo + j] : 0) + t;
+    if (j < width) out[bin_lo + j] = (accumulate ? out[bin_lo + j] : 0) + (sign < 0 ? -t : t);
     if (!scan) return;
     if (!last_to_arrive(counter, gridDim.x)) return;
     block_scan_inplace(out, nbins);
@@ -176,6 +177,33 @@ __global__ __launch_bounds__(kThreads) void k_mm_fold(const uint32_t* mm, int bl
     }
 }
 
+// ------------------------------------------------------ hyperplane pairs
+
+// out = elementwise max (MAX) or min of two arrays, ordered as their bins are:
+// NaN has the last bin, so it wins every max and loses every min (the min of two
+// NaNs is NaN).  Binning is monotone, so the bin of the result is the max (min)
+// of the two bins.
+template <int DT, bool MAX>
+__global__ __launch_bounds__(kThreads) void k_pair_combine(const void* a_, const void* b_, void* out_, int64_t n)
+{
+    using T = typename ValT<DT>::T;
+    const T* __restrict__ a = (const T*)a_;
+    const T* __restrict__ b = (const T*)b_;
+    T* __restrict__ out = (T*)out_;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
+        const T x = a[i], y = b[i];
+        T r;
+        if constexpr (DT == DT_F32) {
+            if constexpr (MAX) r = (x != x || y != y) ? (x != x ? x : y) : (x > y ? x : y);
+            else r = (x != x) ? y : ((y != y) ? x : (x < y ? x : y));
+        } else {
+            r = MAX ? (x > y ? x : y) : (x < y ? x : y);
+        }
+        out[i] = r;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_mm_fold(const uint32_t* mm, int blocks, uint32_t* acc, bool first, hipStream_t s)
@@ -185,20 +213,21 @@ hipError_t launch_mm_fold(const uint32_t* mm, int blocks, uint32_t* acc, bool fi
 }
 
 hipError_t launch_merge(const int32_t* partials, int rows, int32_t width, int32_t bin_lo, int64_t* level2,
-                        int64_t* out, int32_t nbins, uint32_t* counters, bool accumulate, bool scan, hipStream_t s)
+                        int64_t* out, int32_t nbins, uint32_t* counters, bool accumulate, bool scan, int sign,
+                        hipStream_t s)
 {
     const unsigned bx = (unsigned)((width + kThreads - 1) / kThreads);
     const int groups = rows < kMergeGroups ? rows : kMergeGroups;
     // one window holding every bin, written afresh: blocks scan their own bins
     // (see k_merge_final)
-    int64_t* btot = (scan && !accumulate && bin_lo == 0 && width == nbins)
+    int64_t* btot = (scan && !accumulate && sign > 0 && bin_lo == 0 && width == nbins)
                         ? level2 + (size_t)kMergeGroups * width : nullptr;
     hipLaunchKernelGGL(k_merge_groups, dim3(bx, (unsigned)groups), dim3(kThreads), 0, s, partials, rows, width,
                        level2, btot);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_merge_final, dim3(bx), dim3(kThreads), 0, s, level2, btot, groups, width, bin_lo, out,
-                       nbins, counters, accumulate ? 1 : 0, scan ? 1 : 0);
+                       nbins, counters, accumulate ? 1 : 0, scan ? 1 : 0, sign < 0 ? -1 : 1);
     return hipGetLastError();
 }
 
@@ -217,6 +246,28 @@ hipError_t launch_params_from_minmax(const uint32_t* mm, int blocks, int dtype, 
                                      BinParams* out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_params, dim3(1), dim3(kThreads), 0, s, mm, blocks, dtype, nbins, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_combine(const void* a, const void* b, void* out, int dtype, int64_t n, bool take_max,
+                               hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int blocks = (int)std::min<int64_t>((n + kThreads - 1) / kThreads, 4096);
+    switch (dtype) {
+    case DT_U8:
+        if (take_max) hipLaunchKernelGGL((k_pair_combine<DT_U8, true>), dim3(blocks), dim3(kThreads), 0, s, a, b, out, n);
+        else hipLaunchKernelGGL((k_pair_combine<DT_U8, false>), dim3(blocks), dim3(kThreads), 0, s, a, b, out, n);
+        break;
+    case DT_U16:
+        if (take_max) hipLaunchKernelGGL((k_pair_combine<DT_U16, true>), dim3(blocks), dim3(kThreads), 0, s, a, b, out, n);
+        else hipLaunchKernelGGL((k_pair_combine<DT_U16, false>), dim3(blocks), dim3(kThreads), 0, s, a, b, out, n);
+        break;
+    default:
+        if (take_max) hipLaunchKernelGGL((k_pair_combine<DT_F32, true>), dim3(blocks), dim3(kThreads), 0, s, a, b, out, n);
+        else hipLaunchKernelGGL((k_pair_combine<DT_F32, false>), dim3(blocks), dim3(kThreads), 0, s, a, b, out, n);
+        break;
+    }
     return hipGetLastError();
 }
 

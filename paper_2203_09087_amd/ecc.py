@@ -42,7 +42,7 @@ class ecc_image(ctypes.Structure):
         ("data", ctypes.c_void_p),
         ("ndim", ctypes.c_int32),
         ("dtype", ctypes.c_int32),
-        ("dims", ctypes.c_int64 * 3),
+        ("dims", ctypes.c_int64 * 4),
         ("range_mode", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
         ("lo", ctypes.c_double),
@@ -213,7 +213,7 @@ def make_image(t, out, value_range=None) -> ecc_image:
     im.data = t.data_ptr()
     im.ndim = t.dim()
     im.dtype = _dtype_code(t)
-    for i, s in enumerate(t.shape[:3]):
+    for i, s in enumerate(t.shape[:4]):
         im.dims[i] = int(s)
     if value_range is None:
         im.range_mode = ECC_RANGE_DEFAULT

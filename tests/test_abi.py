@@ -46,10 +46,10 @@ def test_library_exports_every_declared_symbol():
 def test_descriptor_layout():
     from paper_2203_09087_amd import ecc
     im = ecc.ecc_image
-    assert ctypes.sizeof(im) == 72
+    assert ctypes.sizeof(im) == 80
     assert im.data.offset == 0 and im.ndim.offset == 8 and im.dtype.offset == 12
-    assert im.dims.offset == 16 and im.range_mode.offset == 40 and im.reserved.offset == 44
-    assert im.lo.offset == 48 and im.hi.offset == 56 and im.out.offset == 64
+    assert im.dims.offset == 16 and im.range_mode.offset == 48 and im.reserved.offset == 52
+    assert im.lo.offset == 56 and im.hi.offset == 64 and im.out.offset == 72
 
 
 def test_create_without_device_reports_error():
