@@ -319,6 +319,26 @@ def pipeline_leg(ctx, stream, iters=1000):
             "smooth_ms": round(float(np.mean(ms_s)), 4), "wall_s": round(wall, 3)}
 
 
+def fourd_leg(ctx, stream, nbins=4096):
+    """A 4D image: an 8 x 256^3 float32 Gaussian random field (P(k) ~ k^-3 in four
+    dimensions, seed 9), 4096 bins over its [min, max], vertex filtration."""
+    import torch
+    from paper_2203_09087_amd import synth
+    shape = (8, 256, 256, 256)
+    vol = synth.grf(shape, seed=9)
+    lo, hi = float(vol.min()), float(vol.max())
+    d = torch.from_numpy(vol).cuda()
+    del vol
+    out = torch.empty(nbins, dtype=torch.int64, device=d.device)
+    ms, _ = timed_calls(lambda: ctx.compute(d, nbins, value_range=(lo, hi), out=out, stream=stream), stream, 20, 3)
+    m = float(np.mean(ms))
+    nv = int(np.prod(shape))
+    gbs = nv * 4 / (m * 1e-3) / 1e9
+    return {"shape": list(shape), "nbins": nbins, "ms": round(m, 3), "gvox_s": round(nv / (m * 1e-3) / 1e9, 2),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "passes": 2 * shape[0] - 1}
+
+
 def serving_leg(dev, rates=(100, 200, 500, 1000, 2000, 5000), seconds=2.0, max_requests=4000):
     """Open-loop Poisson request streams over crops of two GRF pools (uint16,
     4096 levels), 4096 bins, HBM-footprint admission; p50/p99 per rate."""
@@ -522,6 +542,8 @@ def main():
 
     if not args.no_side:
         result["pipeline"] = pipeline_leg(ctx, stream)
+        log("4D image ...")
+        result["fourd"] = fourd_leg(ctx, stream)
 
     if not args.no_side and not args.no_serve:
         result["serving"] = serving_leg(dev)

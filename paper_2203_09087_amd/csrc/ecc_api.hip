@@ -349,14 +349,17 @@ Sizes plan_sizes(const ecc_ctx* ctx, const Job& j, int32_t nbins, const ecc_laun
     return s;
 }
 
-// The histogram launches (and merges) of one image or slab.  pdev: binning
+// The histogram launches (and merges) of one image or slab.  With pass_only
+// (one LDS window only) just the histogram kernel runs, writing (or with
+// pass_add adding) its workgroup histograms times `sign` into the partial rows,
+// which a later merge sums.  pdev: binning
 // parameters on the device (AUTO), else the host parameters of j.  Planes
 // [0, z_own) of j's planes are counted; they are planes z_base.. of a volume
 // of n0_global planes.  accumulate: add the VCEC to out instead of writing it;
 // scan: prefix-sum out after the last window.
 ecc_status enqueue_hist(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t stream, const Sizes& sz,
                         const ecc::BinParams* pdev, int64_t z_own, int64_t z_base, int64_t n0_global,
-                        bool accumulate, bool scan, int sign = 1)
+                        bool accumulate, bool scan, int sign = 1, bool pass_only = false, bool pass_add = false)
 {
     char* base = (char*)ctx->ws;
     uint32_t* counters = (uint32_t*)(base + sz.off_counters);
@@ -376,9 +379,21 @@ ecc_status enqueue_hist(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t s
     L.z_base = z_base;
     L.n0_global = n0_global;
     L.partials = (int32_t*)(base + sz.off_partials);
+    L.flush_add = pass_add ? 1 : 0;
+    L.flush_sign = sign;
     L.out = j.out;
     L.counter = counters;
     hipError_t e;
+    if (pass_only) {
+        // one window, histogram kernel only: its rows are merged by a later call
+        L.bin_lo = 0;
+        L.width = sz.window;
+        if ((e = timed_launch(ctx, stream, [&] { return ecc::launch_ecc(L, stream); })) != hipSuccess)
+            return hip_fail(ctx, e, "ecc launch");
+        return ECC_OK;
+    }
+    L.flush_add = 0;
+    L.flush_sign = 1;
     for (int32_t b0 = 0; b0 < nbins; b0 += sz.window) {
         L.bin_lo = b0;
         L.width = std::min<int32_t>(sz.window, nbins - b0);
@@ -475,6 +490,13 @@ ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t st
         if (c != 0) passes.push_back({img + (size_t)w * (size_t)hv * esize, c, -1});
         if (w + 1 < nw) passes.push_back({nullptr, vertex ? -1 : 1, w});
     }
+    // With one LDS window the passes add into the same workgroup rows and one
+    // merge follows, when the int32 rows cannot overflow: a workgroup sees at
+    // most ceil(bricks / grid) bricks of chunk x rows x depth voxels per pass, and
+    // a voxel adds at most 7 in absolute value.
+    const int64_t bricks = ecc::wg_bricks(3, h.g, sz.waves, sz.depth);
+    const int64_t per_wg = (bricks + sz.grid - 1) / sz.grid * 62 * sz.waves * ecc::kRows3 * sz.depth;
+    const bool one_merge = sz.window >= nbins && (int64_t)passes.size() * per_wg < (int64_t(1) << 28);
     for (size_t k = 0; k < passes.size(); ++k) {
         const Pass& p = passes[k];
         h.data = p.src;
@@ -486,8 +508,15 @@ ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t st
             h.data = ctx->pair_buf;
         }
         if ((st = enqueue_hist(ctx, h, nbins, stream, sz, pdev, h.g.n0, 0, h.g.n0, k > 0, k + 1 == passes.size(),
-                               p.sign)) != ECC_OK)
+                               p.sign, one_merge, k > 0)) != ECC_OK)
             return st;
+    }
+    if (one_merge) {
+        uint32_t* counters = (uint32_t*)(base + sz.off_counters);
+        if ((e = ecc::launch_merge((int32_t*)(base + sz.off_partials), sz.grid, nbins, 0,
+                                   (int64_t*)(base + sz.off_level2), j4.out, nbins, counters, false, true, 1,
+                                   stream)) != hipSuccess)
+            return hip_fail(ctx, e, "merge launch");
     }
     return ECC_OK;
 }

@@ -365,15 +365,18 @@ __device__ __forceinline__ void zero_hist(int32_t* hist, int width)
     __syncthreads();
 }
 
-// Writes the workgroup histogram (copies summed) to dst[0..width).
-__device__ __forceinline__ void flush_hist(const int32_t* hist, int32_t* dst, int width)
+// Writes the workgroup histogram (copies summed, negated with sign -1) to
+// dst[0..width), or adds it to what dst holds (add).
+__device__ __forceinline__ void flush_hist(const int32_t* hist, int32_t* dst, int width, bool add = false,
+                                           int sign = 1)
 {
     __syncthreads();
     for (int j = threadIdx.x; j < width; j += blockDim.x) {
         int32_t t = 0;
 #pragma unroll
         for (int r = 0; r < kReplicas; ++r) t += hist[j * kReplicas + r];
-        dst[j] = t;
+        if (sign < 0) t = -t;
+        dst[j] = add ? dst[j] + t : t;
     }
 }
 

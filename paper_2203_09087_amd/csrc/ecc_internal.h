@@ -106,6 +106,8 @@ struct EccLaunch {
     // has z_own = g.n0, z_base = 0, n0_global = g.n0.
     int64_t z_own, z_base, n0_global;
     int32_t* partials;             // [grid][width] workgroup histograms
+    int32_t flush_add;             // add the workgroup histogram to its partial row (else write it)
+    int32_t flush_sign;            // +1, or -1: the histogram enters its row negated
     int64_t* out;                  // the caller's output (VCEC window, zeroed by block 0)
     uint32_t* counter;             // the merge's counter (unused by the main kernels)
 };

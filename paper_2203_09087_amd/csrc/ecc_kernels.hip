@@ -28,7 +28,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
     const uint32_t nbricks = nxc * nyb * nzb;
     for (uint32_t brick = blockIdx.x; brick < nbricks; brick += gridDim.x)
         run_brick_3d<DT, CONS, WIN>(L, P, H, chunk, brick % nxc, (brick / nxc) % nyb, brick / (nxc * nyb), wave_id());
-    flush_hist(hist, L.partials + (size_t)blockIdx.x * (size_t)L.width, L.width);
+    flush_hist(hist, L.partials + (size_t)blockIdx.x * (size_t)L.width, L.width, L.flush_add != 0, L.flush_sign);
 }
 
 // 2D images.  A workgroup brick is a contiguous x-chunk x L.depth rows.
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
     const uint32_t nbricks = nxc * nyb;
     for (uint32_t brick = blockIdx.x; brick < nbricks; brick += gridDim.x)
         run_brick_2d<DT, CONS, WIN>(L, P, H, chunk, brick % nxc, brick / nxc, wave_id());
-    flush_hist(hist, L.partials + (size_t)blockIdx.x * (size_t)L.width, L.width);
+    flush_hist(hist, L.partials + (size_t)blockIdx.x * (size_t)L.width, L.width, L.flush_add != 0, L.flush_sign);
 }
 
 }  // namespace
