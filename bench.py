@@ -351,6 +351,17 @@ def serving_leg(dev, rates=(100, 200, 500, 1000, 2000, 5000), seconds=2.0, max_r
     budget = 8 << 30
     out = {"budget_bytes": budget, "max_batch": 64, "lanes": 2, "nbins": 4096, "rates": {}}
     srv = serve.Server(budget_bytes=budget, max_batch=64, lanes=2)
+    # untimed warm-up: first-use allocations and kernel loading, every lane, 2D and 3D
+    warm = synth.serving_requests(float(max(rates)), 256, seed=7)
+    wviews = [p2[q["offset"][0]:q["offset"][0] + q["shape"][0], q["offset"][1]:q["offset"][1] + q["shape"][1]]
+              if len(q["shape"]) == 2 else
+              p3[q["offset"][0]:q["offset"][0] + q["shape"][0], q["offset"][1]:q["offset"][1] + q["shape"][1],
+                 q["offset"][2]:q["offset"][2] + q["shape"][2]] for q in warm]
+    srv.run_open_loop([0.0] * len(wviews), lambda i: serve.Request(source=wviews[i], nbins=4096,
+                                                                    value_range=(0, 4095)))
+    srv.peak_held = 0
+    srv.batches = 0
+    del wviews
     for rate in rates:
         n = int(min(max_requests, max(200, rate * seconds)))
         reqs = synth.serving_requests(float(rate), n, seed=6)

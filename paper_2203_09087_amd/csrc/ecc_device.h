@@ -44,8 +44,9 @@
 // the ones with its left and upper neighbours are the complements of the
 // neighbours' results, shifted by one lane.  The per-voxel signed count is
 // assembled with carry-in adds (v_addc/v_subb with the mask as carry) and added
-// to a workgroup histogram in LDS only where it is non-zero.  Workgroup
-// histograms are merged and prefix-scanned by a second kernel.
+// to a workgroup histogram in LDS by one ds_add per row (lanes that own no voxel
+// add into a spare word of their own, which is cheaper than masking the add).
+// Workgroup histograms are merged and prefix-scanned by a second kernel.
 #pragma once
 
 #include "ecc_internal.h"
@@ -70,9 +71,7 @@ template <> struct ValT<DT_U16> { using T = uint16_t; };
 template <> struct ValT<DT_F32> { using T = float; };
 
 // Key (bin << kKeyShift, its LDS byte address) of one value, OR-ed with `oob`:
-// the lane's histogram copy (copy << 2), or ~0 for lanes outside the image,
-// which makes the key the sentinel.  Keys of one bin in different copies order
-// by copy; that refines the order of values without changing any cell's bin.
+// 0, or ~0 for lanes outside the image, which makes the key the sentinel.
 // IDENT: integer data with nbins == hi - lo + 1, where the bin is the level.
 template <int DT, bool IDENT>
 __device__ __forceinline__ uint32_t key_of(typename ValT<DT>::T v, const BinParams& p, uint32_t oob)
@@ -279,13 +278,13 @@ __device__ __forceinline__ void row_start(RowState& s, uint32_t above, uint32_t 
 }
 
 struct HistRef {
-    int32_t* hist;     // LDS: kReplicas * kMaxLdsBins counters, then one spare word per lane
-    uint32_t key_lo;   // key of the first bin of the window (copy 0)
+    int32_t* hist;     // LDS: kMaxLdsBins counters, then one spare word per lane
+    uint32_t key_lo;   // key of the first bin of the window
     uint32_t key_span; // keys in the window
     uint32_t spare;    // byte offset of this lane's spare word (absorbs adds that do not count)
 };
 
-__device__ __forceinline__ uint32_t spare_offset() { return (uint32_t)(kReplicas * kMaxLdsBins + lane_id()) * 4u; }
+__device__ __forceinline__ uint32_t spare_offset() { return (uint32_t)(kMaxLdsBins + lane_id()) * 4u; }
 
 __device__ __forceinline__ HistRef hist_ref(int32_t* hist, int32_t bin_lo, int32_t width)
 {
@@ -327,28 +326,14 @@ __device__ __forceinline__ void row_step(RowState& s, uint32_t below, uint64_t o
         int32_t v;
         if constexpr (SIGN > 0) v = sub_bit(sub_bit(sub_bit(sub_bit(1, tt), tr), tb), tl);
         else v = add_bit(add_bit(add_bit(add_bit(-1, tt), tr), tb), tl);
-        uint32_t key = c;
-#if ECC_ATOMIC_MODE == 0
-        // only lanes that own the voxel and carry a non-zero count
-        bool hit = lane_bit(own) && v != 0;
-        if constexpr (WIN) {
-            key -= H.key_lo;
-            hit = hit && key < H.key_span;
-        }
-        if (hit) hist_add(H, key, v);
-#else
         // every lane adds; lanes that do not count add into their spare word
-  #if ECC_ATOMIC_MODE == 1
+        uint32_t key = c;
         bool hit = lane_bit(own);
-  #else
-        bool hit = lane_bit(own) && v != 0;
-  #endif
         if constexpr (WIN) {
             key -= H.key_lo;
             hit = hit && key < H.key_span;
         }
         hist_add(H, hit ? key : H.spare, v);
-#endif
     }
     s.fb = fb;
     s.fbr = fbr;
@@ -361,20 +346,18 @@ __device__ __forceinline__ void row_step(RowState& s, uint32_t below, uint64_t o
 
 __device__ __forceinline__ void zero_hist(int32_t* hist, int width)
 {
-    for (int j = threadIdx.x; j < kReplicas * width; j += blockDim.x) hist[j] = 0;
+    for (int j = threadIdx.x; j < width; j += blockDim.x) hist[j] = 0;
     __syncthreads();
 }
 
-// Writes the workgroup histogram (copies summed, negated with sign -1) to
-// dst[0..width), or adds it to what dst holds (add).
+// Writes the workgroup histogram (negated with sign -1) to dst[0..width), or
+// adds it to what dst holds (add).
 __device__ __forceinline__ void flush_hist(const int32_t* hist, int32_t* dst, int width, bool add = false,
                                            int sign = 1)
 {
     __syncthreads();
     for (int j = threadIdx.x; j < width; j += blockDim.x) {
-        int32_t t = 0;
-#pragma unroll
-        for (int r = 0; r < kReplicas; ++r) t += hist[j * kReplicas + r];
+        int32_t t = hist[j];
         if (sign < 0) t = -t;
         dst[j] = add ? dst[j] + t : t;
     }
@@ -437,28 +420,13 @@ __device__ __forceinline__ void plane_step(const uint32_t (&Bc)[NR + 2], const u
         return (CONS == CONS_TOP) ? min(Bc[r], Bn[r]) : max(Bc[r], Bn[r]);
     };
     RowState sa, sb;
-    if constexpr (ECC_INTERLEAVE) {
-        if constexpr (SA != 0) row_start(sa, Bc[0], Bc[1]);
-        if constexpr (HASB) row_start(sb, comb(0), comb(1));
+    if constexpr (SA != 0) row_start(sa, Bc[0], Bc[1]);
+    if constexpr (HASB) row_start(sb, comb(0), comb(1));
 #pragma unroll
-        for (int r = 1; r <= NR; ++r) {
-            const uint64_t own = (FULL || r <= rows_owned) ? own_x : 0ull;
-            if constexpr (SA != 0) row_step<CONS, SA, WIN, false>(sa, Bc[r + 1], own, H);
-            if constexpr (HASB) row_step<CONS, SB, WIN, false>(sb, comb(r + 1), own, H);
-        }
-    } else {
-        if constexpr (SA != 0) {
-            row_start(sa, Bc[0], Bc[1]);
-#pragma unroll
-            for (int r = 1; r <= NR; ++r)
-                row_step<CONS, SA, WIN, false>(sa, Bc[r + 1], (FULL || r <= rows_owned) ? own_x : 0ull, H);
-        }
-        if constexpr (HASB) {
-            row_start(sb, comb(0), comb(1));
-#pragma unroll
-            for (int r = 1; r <= NR; ++r)
-                row_step<CONS, SB, WIN, false>(sb, comb(r + 1), (FULL || r <= rows_owned) ? own_x : 0ull, H);
-        }
+    for (int r = 1; r <= NR; ++r) {
+        const uint64_t own = (FULL || r <= rows_owned) ? own_x : 0ull;
+        if constexpr (SA != 0) row_step<CONS, SA, WIN, false>(sa, Bc[r + 1], own, H);
+        if constexpr (HASB) row_step<CONS, SB, WIN, false>(sb, comb(r + 1), own, H);
     }
 }
 
@@ -504,17 +472,13 @@ __device__ __forceinline__ void brick_3d(const EccLaunch& L, const BinParams& P,
     T raw[NR + 2];
     load_plane(z0, raw);
     keys(raw, Bc);
-    if (ECC_PREFETCH2 && z0 + 1 < n0) load_plane(z0 + 1, raw);
     for (uint32_t z = z0; z < zend; ++z) {
+        // the next plane's loads are waited for here; other waves' arithmetic
+        // covers their latency (a plane prefetched one step ahead measured no gain)
         const bool has1 = z + 1 < n0;
-        if constexpr (ECC_PREFETCH2) {
-            if (has1) keys(raw, Bn);
-            if (z + 1 < zend && z + 2 < n0) load_plane(z + 2, raw);
-        } else {
-            if (has1) {
-                load_plane(z + 1, raw);
-                keys(raw, Bn);
-            }
+        if (has1) {
+            load_plane(z + 1, raw);
+            keys(raw, Bn);
         }
         if constexpr (CONS == CONS_VERTEX) {
             if (has1) plane_step<CONS, WIN, FULL, +1, true, NR>(Bc, Bn, own_x, rows_owned, H);
@@ -617,7 +581,7 @@ __device__ __forceinline__ void brick_2d(const void* data, uint32_t n1, int64_t 
 // halo, lanes 1..62 own columns x0 + 62 * wave + lane - 1.
 struct WaveCols {
     bool active;       // the wave owns at least one column of the image
-    uint32_t oob;      // this lane's histogram copy << 2 if its column lies inside the image, else ~0
+    uint32_t oob;      // 0 if this lane's column lies inside the image, else ~0
     uint64_t own_x;    // owned lanes
     uint32_t xo;       // this lane's column, clamped into the image
 };
@@ -633,7 +597,7 @@ __device__ __forceinline__ WaveCols wave_cols(int64_t x0, int wave, int64_t n2)
     const int64_t x = first - 1 + (int64_t)lane_id();
     const bool x_ok = x >= 0 && x < n2;
     const uint64_t xmask = ballot(x_ok);
-    w.oob = x_ok ? (lane_id() % kReplicas) << 2 : ~0u;
+    w.oob = x_ok ? 0u : ~0u;
     w.own_x = xmask & kOwnLanes;
     w.xo = (uint32_t)(x < 0 ? 0 : (x >= n2 ? n2 - 1 : x));
     return w;

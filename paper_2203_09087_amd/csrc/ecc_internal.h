@@ -49,9 +49,6 @@ constexpr int kMaxLdsBins = 4096;
 #ifndef ECC_CHUNK2
 #define ECC_CHUNK2 16
 #endif
-#ifndef ECC_PREFETCH2
-#define ECC_PREFETCH2 0   // 3D: plane z+2 in flight while plane z is processed
-#endif
 #ifndef ECC_WAVES_PER_EU_3D
 #define ECC_WAVES_PER_EU_3D 7   // resident waves per SIMD the 3D kernels are compiled for
 #endif
@@ -67,23 +64,9 @@ constexpr int kMaxLdsBins = 4096;
 #ifndef ECC_MAX_WGS_PER_CU_2D
 #define ECC_MAX_WGS_PER_CU_2D 3   // resident workgroups per CU a single 2D image launches
 #endif
-#ifndef ECC_ATOMIC_MODE
-#define ECC_ATOMIC_MODE 1  // LDS adds: 0 exec-masked non-zero owned lanes; 1 all lanes, the rest to spare words; 2 select non-zero
-#endif
-#ifndef ECC_HIST_REPLICAS
-#define ECC_HIST_REPLICAS 1  // copies of the LDS histogram, lane x adds into copy x % replicas
-#endif
-#ifndef ECC_INTERLEAVE
-#define ECC_INTERLEAVE 1  // 3D: advance the two 2D problems of a plane row by row together
-#endif
-// Copies of the LDS histogram: neighbouring lanes add into different copies, so
-// runs of equal bins along a row collide less.  A key is
-// (bin << kKeyShift) | (copy << 2): the LDS byte address of its counter, with
-// the copies of one bin interleaved.
-constexpr int kReplicas = ECC_HIST_REPLICAS;
-constexpr int kKeyShift = kReplicas == 1 ? 2 : (kReplicas == 2 ? 3 : 4);
-static_assert(kReplicas == 1 || kReplicas == 2 || kReplicas == 4, "1, 2 or 4 histogram copies");
-constexpr int kLdsWords = kReplicas * kMaxLdsBins + 64;   // counters, then one spare word per lane
+// A key is 4 * bin: the LDS byte address of its counter.
+constexpr int kKeyShift = 2;
+constexpr int kLdsWords = kMaxLdsBins + 64;   // counters, then one spare word per lane
 constexpr int kRows3 = ECC_ROWS3;      // rows per 3D brick
 constexpr int kChunk2 = ECC_CHUNK2;    // rows loaded together in the 2D kernel
 // Waves per workgroup of the main kernels (x-chunk = waves * 62 columns).
