@@ -174,7 +174,7 @@ def write_traffic(fetch_csv, write_csv):
 
 TRACE_FILE = os.path.join(ROOT, "profiles", "k_ecc_3d_f32_512cubed_trace.md")
 SQ_FILE = os.path.join(ROOT, "profiles", "k_ecc_3d_f32_512cubed_sq.md")
-MAIN_KERNEL = "k_ecc_3d<2, 0, false>"
+MAIN_KERNEL = "k_ecc_3d<2, 0, false, false>"
 
 
 def write_trace_summary(db_path, bench_json):

@@ -115,8 +115,7 @@ const char* ecc_last_error(const ecc_ctx* ctx);
  * dtype: ecc_dtype; out: device pointer to nbins int64 (overwritten).
  * A 4D image (the cubical complex of Sec. 2.1 in four dimensions) is computed as
  * signed 3D passes over its hyperplanes dims[0] and over the elementwise max
- * (vertex) or min (top) of adjacent hyperplanes, which the context combines into
- * a buffer of one hyperplane that it allocates (and keeps) on first use.
+ * (vertex) or min (top) of adjacent hyperplanes.
  * Errors: ECC_ERR_INVALID_ARG for any bad argument (nothing enqueued),
  * ECC_ERR_OUT_OF_MEMORY, ECC_ERR_DEVICE. */
 ecc_status ecc_compute(ecc_ctx* ctx, const void* image, int32_t ndim, const int64_t* dims,

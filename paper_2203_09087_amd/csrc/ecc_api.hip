@@ -41,9 +41,6 @@ struct ecc_ctx {
     // intermediate buffer of ecc_smooth13
     void* smooth_tmp = nullptr;
     size_t smooth_cap = 0;
-    // 4D images: the max (min) of two adjacent hyperplanes
-    void* pair_buf = nullptr;
-    size_t pair_cap = 0;
     // launch shapes chosen by ecc_autotune, by image shape (see TuneKey)
     std::map<std::tuple<int, int, int, int, int64_t, int64_t, int64_t>, ecc_launch_shape> tuned;
     // kernel timing (ecc_set_kernel_timing): event pairs around histogram launches
@@ -163,6 +160,7 @@ static_assert(sizeof(ecc_image) == 80 && offsetof(ecc_image, dims) == 16 && offs
 
 struct Job {
     const void* data;
+    const void* data2;    // 4D pair passes: count the max (min) of data and data2
     int ndim, dtype, range_mode;
     ecc::Geom g;          // 2D/3D: the image; 4D: one hyperplane (dims[1..3])
     int64_t nw;           // 4D: hyperplanes (dims[0]); else 1
@@ -237,6 +235,7 @@ ecc_status validate(ecc_ctx* ctx, const ecc_image& im, int32_t nbins, const char
         }
     }
     job->data = im.data;
+    job->data2 = nullptr;
     job->ndim = im.ndim;
     job->dtype = im.dtype;
     job->range_mode = im.range_mode;
@@ -365,6 +364,7 @@ ecc_status enqueue_hist(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t s
     uint32_t* counters = (uint32_t*)(base + sz.off_counters);
     ecc::EccLaunch L;
     L.data = j.data;
+    L.data2 = j.data2;
     L.ndim = j.ndim;
     L.dtype = j.dtype;
     L.construction = ctx->construction;
@@ -429,32 +429,13 @@ ecc_status enqueue_one(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t st
 }
 
 // A 4D image as signed 3D passes (the cells of a 4D complex are 3D cells times
-// a vertex or an edge of the last axis, Sec. 2.1).  With H_w the hyperplanes:
+// a vertex or an edge of the first axis, Sec. 2.1).  With H_w the hyperplanes:
 //   vertex: VCEC = sum_w V3(H_w) - sum_{w<n-1} V3(max(H_w, H_{w+1}))
 //   top:    VCEC = sum_w c_w T3(H_w) + sum_{w<n-1} T3(min(H_w, H_{w+1})),
 //           c_w = -1 + [w == 0] + [w == n-1]
-// Each pair is combined into a context buffer, then counted like a hyperplane;
-// every pass adds into (or subtracts from) the caller's output, the last one
+// A pair pass reads both hyperplanes and counts the max (min) of their keys.
+// Every pass adds into (or subtracts from) the caller's output, the last one
 // scans it.  The binning parameters are the whole image's.
-ecc_status ensure_pair_buf(ecc_ctx* ctx, size_t bytes)
-{
-    if (bytes <= ctx->pair_cap) return ECC_OK;
-    hipError_t e;
-    if (ctx->pair_buf) {
-        // earlier calls on any stream may still read the old buffer
-        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
-        (void)hipFree(ctx->pair_buf);
-        ctx->pair_buf = nullptr;
-        ctx->pair_cap = 0;
-    }
-    if ((e = hipMalloc(&ctx->pair_buf, bytes)) != hipSuccess) {
-        ctx->pair_buf = nullptr;
-        return hip_fail(ctx, e, "hipMalloc(hyperplane pair)");
-    }
-    ctx->pair_cap = bytes;
-    return ECC_OK;
-}
-
 ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t stream)
 {
     const int64_t nw = j4.nw;
@@ -467,7 +448,6 @@ ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t st
     const Sizes sz = plan_sizes(ctx, h, nbins);
     ecc_status st = ensure_ws(ctx, sz.total);
     if (st != ECC_OK) return st;
-    if (nw > 1 && (st = ensure_pair_buf(ctx, (size_t)hv * esize)) != ECC_OK) return st;
     char* base = (char*)ctx->ws;
     ecc::BinParams* pdev = nullptr;
     hipError_t e;
@@ -482,7 +462,7 @@ ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t st
     }
     const char* img = (const char*)j4.data;
     const bool vertex = ctx->construction == ECC_VERTEX;
-    // the passes in order: (source, sign); a null source is the pair buffer
+    // the passes in order: (hyperplane, sign), or (pair w, w+1, sign)
     struct Pass { const void* src; int sign; int64_t pair; };
     std::vector<Pass> passes;
     for (int64_t w = 0; w < nw; ++w) {
@@ -500,12 +480,10 @@ ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t st
     for (size_t k = 0; k < passes.size(); ++k) {
         const Pass& p = passes[k];
         h.data = p.src;
+        h.data2 = nullptr;
         if (p.pair >= 0) {
-            const char* a = img + (size_t)p.pair * (size_t)hv * esize;
-            if ((e = ecc::launch_pair_combine(a, a + (size_t)hv * esize, ctx->pair_buf, j4.dtype, hv, vertex,
-                                              stream)) != hipSuccess)
-                return hip_fail(ctx, e, "pair launch");
-            h.data = ctx->pair_buf;
+            h.data = img + (size_t)p.pair * (size_t)hv * esize;
+            h.data2 = img + (size_t)(p.pair + 1) * (size_t)hv * esize;
         }
         if ((st = enqueue_hist(ctx, h, nbins, stream, sz, pdev, h.g.n0, 0, h.g.n0, k > 0, k + 1 == passes.size(),
                                p.sign, one_merge, k > 0)) != ECC_OK)
@@ -918,7 +896,6 @@ ecc_status ecc_destroy(ecc_ctx* ctx)
         }
         if (ctx->copy_stream) (void)hipStreamDestroy(ctx->copy_stream);
         if (ctx->smooth_tmp) (void)hipFree(ctx->smooth_tmp);
-        if (ctx->pair_buf) (void)hipFree(ctx->pair_buf);
     }
     delete ctx;
     return ECC_OK;

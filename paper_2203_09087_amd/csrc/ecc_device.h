@@ -436,7 +436,10 @@ __device__ __forceinline__ void plane_step(const uint32_t (&Bc)[NR + 2], const u
 // bounds) and take the sentinel key, and rows past the brick's owned rows count
 // nothing; both without branches, so boundary bricks cost about what inner ones
 // do.  Plane indices are 32-bit (see brick_2d).
-template <int DT, int CONS, bool WIN, bool FULL, bool IDENT>
+// PAIR: the volume is the elementwise max (vertex) or min (top) of L.data and
+// L.data2, taken on the keys (the bins' order, so exactly the bin of the max or
+// min value): the combined hyperplanes of a 4D image.
+template <int DT, int CONS, bool WIN, bool FULL, bool IDENT, bool PAIR>
 __device__ __forceinline__ void brick_3d(const EccLaunch& L, const BinParams& P, const HistRef& H, int64_t y0,
                                          uint32_t z0, uint32_t zend, uint32_t xob, uint32_t oob, uint64_t own_x,
                                          int rows_owned, int r_lo, int r_hi)
@@ -447,38 +450,48 @@ __device__ __forceinline__ void brick_3d(const EccLaunch& L, const BinParams& P,
     const int64_t n1 = L.g.n1, n2 = L.g.n2;
     const uint32_t row_bytes = (uint32_t)(n2 * (int64_t)sizeof(T));
     const char* img = (const char*)L.data;
+    const char* img2 = (const char*)L.data2;
     // first row read: y0 - 1, or the first row inside the image
     const int64_t ybase = y0 - 1 + (FULL ? 0 : r_lo);
+    constexpr int NR2 = PAIR ? NR + 2 : 1;
 
-    auto load_plane = [&](uint32_t z, T (&raw)[NR + 2]) {
-        const __amdgpu_buffer_rsrc_t rs = rsrc_at(img + ((int64_t)z * n1 + ybase) * (int64_t)row_bytes);
+    auto load_plane = [&](uint32_t z, T (&raw)[NR + 2], T (&raw2)[NR2]) {
+        const int64_t off = ((int64_t)z * n1 + ybase) * (int64_t)row_bytes;
+        const __amdgpu_buffer_rsrc_t rs = rsrc_at(img + off);
+        __amdgpu_buffer_rsrc_t rs2 = rs;
+        if constexpr (PAIR) rs2 = rsrc_at(img2 + off);
         uint32_t soff = 0;
 #pragma unroll
         for (int r = 0; r < NR + 2; ++r) {
             raw[r] = buffer_load<T>(rs, xob, soff);
+            if constexpr (PAIR) raw2[r] = buffer_load<T>(rs2, xob, soff);
             // advance while the next row still lies inside the image
             if (FULL || (r >= r_lo && r + 1 < r_hi)) soff = advance(soff, row_bytes);
         }
     };
-    auto keys = [&](const T (&raw)[NR + 2], uint32_t (&B)[NR + 2]) {
+    auto keys = [&](const T (&raw)[NR + 2], const T (&raw2)[NR2], uint32_t (&B)[NR + 2]) {
 #pragma unroll
         for (int r = 0; r < NR + 2; ++r) {
             const uint32_t outside = (FULL || (r >= r_lo && r < r_hi)) ? 0u : ~0u;
             B[r] = key_of<DT, IDENT>(raw[r], P, oob | outside);
+            if constexpr (PAIR) {
+                const uint32_t k2 = key_of<DT, IDENT>(raw2[r], P, oob | outside);
+                B[r] = CONS == CONS_VERTEX ? max(B[r], k2) : min(B[r], k2);
+            }
         }
     };
 
     uint32_t Bc[NR + 2], Bn[NR + 2];
-    T raw[NR + 2];
-    load_plane(z0, raw);
-    keys(raw, Bc);
+    T raw[NR + 2], raw2[NR2];
+    load_plane(z0, raw, raw2);
+    keys(raw, raw2, Bc);
     for (uint32_t z = z0; z < zend; ++z) {
         // the next plane's loads are waited for here; other waves' arithmetic
         // covers their latency (a plane prefetched one step ahead measured no gain)
         const bool has1 = z + 1 < n0;
         if (has1) {
-            load_plane(z + 1, raw);
-            keys(raw, Bn);
+            load_plane(z + 1, raw, raw2);
+            keys(raw, raw2, Bn);
         }
         if constexpr (CONS == CONS_VERTEX) {
             if (has1) plane_step<CONS, WIN, FULL, +1, true, NR>(Bc, Bn, own_x, rows_owned, H);
@@ -605,7 +618,7 @@ __device__ __forceinline__ WaveCols wave_cols(int64_t x0, int wave, int64_t n2)
 
 // One 3D workgroup brick (x-chunk xc, row block yb, plane block zb) for this wave.
 // `xw`: this wave's place among the waves of the brick (columns xw*62 ..).
-template <int DT, int CONS, bool WIN>
+template <int DT, int CONS, bool WIN, bool PAIR = false>
 __device__ __forceinline__ void run_brick_3d(const EccLaunch& L, const BinParams& P, const HistRef& H,
                                              int64_t chunk, uint32_t xc, uint32_t yb, uint32_t zb, int xw)
 {
@@ -628,11 +641,11 @@ __device__ __forceinline__ void run_brick_3d(const EccLaunch& L, const BinParams
     const int r_hi = (int)((n1 - (y0 - 1)) < NR + 2 ? (n1 - (y0 - 1)) : NR + 2);
     const bool full = r_lo == 0 && r_hi == NR + 2;
     if (DT != DT_F32 && uniform_flag(P.ident)) {
-        if (full) brick_3d<DT, CONS, WIN, true, true>(L, P, H, y0, z0, zend, xob, w.oob, w.own_x, rows_owned, r_lo, r_hi);
-        else brick_3d<DT, CONS, WIN, false, true>(L, P, H, y0, z0, zend, xob, w.oob, w.own_x, rows_owned, r_lo, r_hi);
+        if (full) brick_3d<DT, CONS, WIN, true, true, PAIR>(L, P, H, y0, z0, zend, xob, w.oob, w.own_x, rows_owned, r_lo, r_hi);
+        else brick_3d<DT, CONS, WIN, false, true, PAIR>(L, P, H, y0, z0, zend, xob, w.oob, w.own_x, rows_owned, r_lo, r_hi);
     } else {
-        if (full) brick_3d<DT, CONS, WIN, true, false>(L, P, H, y0, z0, zend, xob, w.oob, w.own_x, rows_owned, r_lo, r_hi);
-        else brick_3d<DT, CONS, WIN, false, false>(L, P, H, y0, z0, zend, xob, w.oob, w.own_x, rows_owned, r_lo, r_hi);
+        if (full) brick_3d<DT, CONS, WIN, true, false, PAIR>(L, P, H, y0, z0, zend, xob, w.oob, w.own_x, rows_owned, r_lo, r_hi);
+        else brick_3d<DT, CONS, WIN, false, false, PAIR>(L, P, H, y0, z0, zend, xob, w.oob, w.own_x, rows_owned, r_lo, r_hi);
     }
 }
 

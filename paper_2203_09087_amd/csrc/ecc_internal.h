@@ -74,6 +74,7 @@ constexpr int kMaxWaves = 9;
 
 struct EccLaunch {
     const void* data;
+    const void* data2;             // non-null (3D): count the elementwise max (min) of data and data2
     int ndim, dtype, construction;
     Geom g;
     const BinParams* params_dev;   // non-null: read the parameters from device memory
@@ -186,10 +187,6 @@ constexpr int kCounterWords = 256;
 hipError_t launch_merge(const int32_t* partials, int rows, int32_t width, int32_t bin_lo, int64_t* level2,
                         int64_t* out, int32_t nbins, uint32_t* counters, bool accumulate, bool scan, int sign,
                         hipStream_t s);
-// out[i] = max (take_max) or min of a[i] and b[i] for i < n, in the order of their
-// bins (NaN above every number).
-hipError_t launch_pair_combine(const void* a, const void* b, void* out, int dtype, int64_t n, bool take_max,
-                               hipStream_t s);
 // Folds `blocks` min/max key pairs into the running pair acc (first: start it).
 hipError_t launch_mm_fold(const uint32_t* mm, int blocks, uint32_t* acc, bool first, hipStream_t s);
 

@@ -14,7 +14,7 @@ using namespace dev;
 // side by side, each 64 lanes wide with 62 owned) x kRows3 rows x L.depth planes.
 // All waves of a workgroup read the same rows at about the same time, so every
 // plane step of a workgroup reads whole row segments of memory.
-template <int DT, int CONS, bool WIN>
+template <int DT, int CONS, bool WIN, bool PAIR>
 __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU_3D))) void k_ecc_3d(EccLaunch L)
 {
     __shared__ int32_t hist[kLdsWords];
@@ -27,7 +27,8 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
     const uint32_t nzb = (uint32_t)((L.z_own + L.depth - 1) / L.depth);
     const uint32_t nbricks = nxc * nyb * nzb;
     for (uint32_t brick = blockIdx.x; brick < nbricks; brick += gridDim.x)
-        run_brick_3d<DT, CONS, WIN>(L, P, H, chunk, brick % nxc, (brick / nxc) % nyb, brick / (nxc * nyb), wave_id());
+        run_brick_3d<DT, CONS, WIN, PAIR>(L, P, H, chunk, brick % nxc, (brick / nxc) % nyb, brick / (nxc * nyb),
+                                          wave_id());
     flush_hist(hist, L.partials + (size_t)blockIdx.x * (size_t)L.width, L.width, L.flush_add != 0, L.flush_sign);
 }
 
@@ -66,8 +67,10 @@ static hipError_t launch_t(const EccLaunch& L, hipStream_t s)
 {
     if constexpr (NDIM == 2)
         hipLaunchKernelGGL((k_ecc_2d<DT, CONS, WIN>), dim3(L.grid), dim3(L.waves * 64), 0, s, L);
+    else if (L.data2)
+        hipLaunchKernelGGL((k_ecc_3d<DT, CONS, WIN, true>), dim3(L.grid), dim3(L.waves * 64), 0, s, L);
     else
-        hipLaunchKernelGGL((k_ecc_3d<DT, CONS, WIN>), dim3(L.grid), dim3(L.waves * 64), 0, s, L);
+        hipLaunchKernelGGL((k_ecc_3d<DT, CONS, WIN, false>), dim3(L.grid), dim3(L.waves * 64), 0, s, L);
     return hipGetLastError();
 }
 
@@ -103,7 +106,7 @@ template <int NDIM, int DT, int CONS, bool WIN>
 static const void* kernel_of()
 {
     if constexpr (NDIM == 2) return (const void*)k_ecc_2d<DT, CONS, WIN>;
-    else return (const void*)k_ecc_3d<DT, CONS, WIN>;
+    else return (const void*)k_ecc_3d<DT, CONS, WIN, false>;
 }
 
 template <int NDIM, int DT, int CONS>

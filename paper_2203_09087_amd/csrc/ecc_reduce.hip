@@ -177,33 +177,6 @@ __global__ __launch_bounds__(kThreads) void k_mm_fold(const uint32_t* mm, int bl
     }
 }
 
-// ------------------------------------------------------ hyperplane pairs
-
-// out = elementwise max (MAX) or min of two arrays, ordered as their bins are:
-// NaN has the last bin, so it wins every max and loses every min (the min of two
-// NaNs is NaN).  Binning is monotone, so the bin of the result is the max (min)
-// of the two bins.
-template <int DT, bool MAX>
-__global__ __launch_bounds__(kThreads) void k_pair_combine(const void* a_, const void* b_, void* out_, int64_t n)
-{
-    using T = typename ValT<DT>::T;
-    const T* __restrict__ a = (const T*)a_;
-    const T* __restrict__ b = (const T*)b_;
-    T* __restrict__ out = (T*)out_;
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
-        const T x = a[i], y = b[i];
-        T r;
-        if constexpr (DT == DT_F32) {
-            if constexpr (MAX) r = (x != x || y != y) ? (x != x ? x : y) : (x > y ? x : y);
-            else r = (x != x) ? y : ((y != y) ? x : (x < y ? x : y));
-        } else {
-            r = MAX ? (x > y ? x : y) : (x < y ? x : y);
-        }
-        out[i] = r;
-    }
-}
-
 }  // namespace
 
 hipError_t launch_mm_fold(const uint32_t* mm, int blocks, uint32_t* acc, bool first, hipStream_t s)
@@ -249,26 +222,5 @@ hipError_t launch_params_from_minmax(const uint32_t* mm, int blocks, int dtype, 
     return hipGetLastError();
 }
 
-hipError_t launch_pair_combine(const void* a, const void* b, void* out, int dtype, int64_t n, bool take_max,
-                               hipStream_t s)
-{
-    if (n <= 0) return hipSuccess;
-    const int blocks = (int)std::min<int64_t>((n + kThreads - 1) / kThreads, 4096);
-    switch (dtype) {
-    case DT_U8:
-        if (take_max) hipLaunchKernelGGL((k_pair_combine<DT_U8, true>), dim3(blocks), dim3(kThreads), 0, s, a, b, out, n);
-        else hipLaunchKernelGGL((k_pair_combine<DT_U8, false>), dim3(blocks), dim3(kThreads), 0, s, a, b, out, n);
-        break;
-    case DT_U16:
-        if (take_max) hipLaunchKernelGGL((k_pair_combine<DT_U16, true>), dim3(blocks), dim3(kThreads), 0, s, a, b, out, n);
-        else hipLaunchKernelGGL((k_pair_combine<DT_U16, false>), dim3(blocks), dim3(kThreads), 0, s, a, b, out, n);
-        break;
-    default:
-        if (take_max) hipLaunchKernelGGL((k_pair_combine<DT_F32, true>), dim3(blocks), dim3(kThreads), 0, s, a, b, out, n);
-        else hipLaunchKernelGGL((k_pair_combine<DT_F32, false>), dim3(blocks), dim3(kThreads), 0, s, a, b, out, n);
-        break;
-    }
-    return hipGetLastError();
-}
 
 }  // namespace ecc
