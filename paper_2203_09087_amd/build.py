@@ -31,14 +31,33 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
-    """Compiles every HIP source into `out` (always recompiles).
+    """Compiles every HIP source into `out` (always recompiles): one object per
+    source, compiled in parallel, then one shared library.  The sources share no
+    device code, so no relocatable device code is needed.
 
     defines: extra preprocessor definitions ("NAME=VALUE"), used for tuning builds."""
-    tmp = out + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, *[f"-D{d}" for d in defines], *SOURCES, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    defs = [f"-D{d}" for d in defines]
+    with tempfile.TemporaryDirectory(prefix="ecc_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.basename(src) + ".o") for src in SOURCES]
+        cmds = [[hipcc(), *compile_flags, *defs, "-c", src, "-o", obj] for src, obj in zip(SOURCES, objs)]
+        if verbose:
+            for c in cmds:
+                print(" ".join(c), flush=True)
+        jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+        with ThreadPoolExecutor(jobs) as ex:
+            results = list(ex.map(lambda c: subprocess.run(c, capture_output=True, text=True), cmds))
+        for c, r in zip(cmds, results):
+            if r.returncode != 0:
+                print(r.stderr, flush=True)
+                raise subprocess.CalledProcessError(r.returncode, c, r.stdout, r.stderr)
+        tmp = out + ".tmp"
+        link = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+        if verbose:
+            print(" ".join(link), flush=True)
+        subprocess.run(link, check=True)
     os.replace(tmp, out)
     return out
 
