@@ -231,7 +231,7 @@ def test_invalid_arguments_enqueue_nothing(ctxs):
                 setattr(im, k, v)
         return im
 
-    bad = [variant(data=None), variant(out=None), variant(ndim=1), variant(ndim=4),
+    bad = [variant(data=None), variant(out=None), variant(ndim=1), variant(ndim=5),
            variant(dtype=7), variant(range_mode=9), variant(reserved=1), variant(dims=(0, 8)),
            variant(dims=(8, -1)), variant(range_mode=ecc.ECC_RANGE_EXPLICIT, lo=3.0, hi=2.0),
            variant(range_mode=ecc.ECC_RANGE_EXPLICIT, lo=0.5, hi=2.0),
