@@ -462,14 +462,15 @@ ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t st
     }
     const char* img = (const char*)j4.data;
     const bool vertex = ctx->construction == ECC_VERTEX;
-    // the passes in order: (hyperplane, sign), or (pair w, w+1, sign)
-    struct Pass { const void* src; int sign; int64_t pair; };
+    // the passes in order: hyperplane w, or the pair (w, w+1), with a sign
+    struct Pass { int64_t w; int sign; bool pair; };
     std::vector<Pass> passes;
     for (int64_t w = 0; w < nw; ++w) {
         const int c = vertex ? 1 : -1 + (w == 0) + (w == nw - 1);
-        if (c != 0) passes.push_back({img + (size_t)w * (size_t)hv * esize, c, -1});
-        if (w + 1 < nw) passes.push_back({nullptr, vertex ? -1 : 1, w});
+        if (c != 0) passes.push_back({w, c, false});
+        if (w + 1 < nw) passes.push_back({w, vertex ? -1 : 1, true});
     }
+    auto plane = [&](int64_t w) { return (const void*)(img + (size_t)w * (size_t)hv * esize); };
     // With one LDS window the passes add into the same workgroup rows and one
     // merge follows, when the int32 rows cannot overflow: a workgroup sees at
     // most ceil(bricks / grid) bricks of chunk x rows x depth voxels per pass, and
@@ -479,12 +480,8 @@ ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t st
     const bool one_merge = sz.window >= nbins && (int64_t)passes.size() * per_wg < (int64_t(1) << 28);
     for (size_t k = 0; k < passes.size(); ++k) {
         const Pass& p = passes[k];
-        h.data = p.src;
-        h.data2 = nullptr;
-        if (p.pair >= 0) {
-            h.data = img + (size_t)p.pair * (size_t)hv * esize;
-            h.data2 = img + (size_t)(p.pair + 1) * (size_t)hv * esize;
-        }
+        h.data = plane(p.w);
+        h.data2 = p.pair ? plane(p.w + 1) : nullptr;
         if ((st = enqueue_hist(ctx, h, nbins, stream, sz, pdev, h.g.n0, 0, h.g.n0, k > 0, k + 1 == passes.size(),
                                p.sign, one_merge, k > 0)) != ECC_OK)
             return st;
