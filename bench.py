@@ -284,10 +284,27 @@ def cpu_baseline(vol, nbins, lo, hi, target_s=12.0):
     t0 = time.perf_counter()
     oracle.ecc(sample, nbins, "vertex", value_range=(lo, hi), threads=threads)
     dt = time.perf_counter() - t0
+    # one thread on a smaller sample of the same field
+    one = vol[:8]
+    t1 = time.perf_counter()
+    oracle.ecc(one, nbins, "vertex", value_range=(lo, hi), threads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": round(sample.size / dt / 1e9, 4), "unit": "Gvoxels/s", "cores": threads,
             "kind": "oracle",
             "sample": f"first {planes} of {vol.shape[0]} planes of the 512^3 f32 field "
-                      f"({sample.size} voxels, vertex filtration, {nbins} bins), {dt:.1f} s"}
+                      f"({sample.size} voxels, vertex filtration, {nbins} bins), {dt:.1f} s",
+            "single_thread": {"value": round(one.size / dt1 / 1e9, 4), "sample": f"first 8 planes, {dt1:.2f} s"},
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def pipeline_leg(ctx, stream, iters=1000):
@@ -481,7 +498,9 @@ def main():
                      "launches": k_launches, "algorithmic_bytes": alg_bytes,
                      "step_ms_with_kernel_events": round(float(np.mean(ms_k)), 4)},
         "launch_shape": shape,
+        "p10_ms": round(float(np.percentile(ms, 10)), 4),
         "p50_ms": round(float(np.percentile(ms, 50)), 4),
+        "p90_ms": round(float(np.percentile(ms, 90)), 4),
         "p99_ms": round(float(np.percentile(ms, 99)), 4),
         "wall_s": round(wall, 3),
     }
