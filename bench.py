@@ -536,8 +536,11 @@ def main():
             for a, o in zip(dev_imgs, outs):
                 ctx.compute(a, 256, out=o, stream=stream)
         ms_p, _ = timed_calls(per_image, stream, 5, 2)
-        # the same batch planned once and replayed from a captured HIP graph
+        # the same batch planned once, its launch shape tuned, and replayed from a
+        # captured HIP graph
         plan = ctx.plan_batch(dev_imgs, 256, outs=outs)
+        plan_shape = plan.autotune(reps=3, stream=stream)
+        ms_l, _ = timed_calls(lambda: plan.launch(stream=stream), stream, 5, 2)
         gs = torch.cuda.Stream(dev)
         gs.wait_stream(stream)
         with torch.cuda.stream(gs):
@@ -554,6 +557,7 @@ def main():
                              "images_per_s": round(len(imgs) / (mb * 1e-3), 1),
                              "gvox_s": round(nv / (mb * 1e-3) / 1e9, 2),
                              "hbm_frac": round(nv / (mb * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                             "planned_ms": round(float(np.mean(ms_l)), 3), "plan_shape": plan_shape,
                              "graph_replay_ms": round(mg, 3),
                              "per_image_calls_ms": round(mp, 3),
                              "speedup_vs_per_image": round(mp / mb, 3)}

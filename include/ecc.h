@@ -206,6 +206,27 @@ ecc_status ecc_batch_plan_create(ecc_ctx* ctx, const ecc_image* imgs, int32_t co
                                  ecc_batch_plan** plan);
 /* Enqueues one run of the planned batch on hip_stream (asynchronous). */
 ecc_status ecc_batch_plan_launch(ecc_batch_plan* plan, void* hip_stream);
+
+/* Launch shape of a planned batch: bricks of depth3 planes (3D images) and
+ * depth2 rows (2D images), at most wgs_per_cu workgroups per compute unit; ms is
+ * the mean time of one run measured by ecc_batch_plan_autotune. */
+typedef struct {
+    int32_t depth3;
+    int32_t depth2;
+    int32_t wgs_per_cu;
+    int32_t reserved;
+    double ms;
+} ecc_batch_shape;
+
+/* Chooses the plan's launch shape by timing: runs the batch `reps` times (1..1000)
+ * for each candidate shape on hip_stream, keeps the fastest in the plan (every
+ * shape gives the same ECCs) and, if `chosen` is not null, writes it there.
+ * Blocking: it waits for its runs, and it writes the images' outputs, which hold
+ * the batch's ECCs when it returns.  The caller keeps the plan's images alive as
+ * for ecc_batch_plan_launch.  Errors: ECC_ERR_INVALID_ARG (null plan, reps out of
+ * range), ECC_ERR_OUT_OF_MEMORY, ECC_ERR_DEVICE; on error the plan keeps its
+ * previous shape. */
+ecc_status ecc_batch_plan_autotune(ecc_batch_plan* plan, int32_t reps, void* hip_stream, ecc_batch_shape* chosen);
 /* Releases the plan's device memory; waits for nothing (the caller must have
  * synchronized its launches).  A null plan is accepted and ignored. */
 ecc_status ecc_batch_plan_destroy(ecc_batch_plan* plan);

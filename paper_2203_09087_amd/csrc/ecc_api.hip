@@ -549,7 +549,11 @@ struct BatchTables {
     BatchLayout lay;
 };
 
-void build_batch_tables(int cu_count, const std::vector<Job>& jobs, int32_t nbins, BatchTables& T)
+// The batch's launch shape unless a plan was tuned.
+constexpr ecc_batch_shape kDefaultBatchShape = {8, 64, 2, 0, 0.0};
+
+void build_batch_tables(int cu_count, const std::vector<Job>& jobs, int32_t nbins, BatchTables& T,
+                        const ecc_batch_shape& shape = kDefaultBatchShape)
 {
     const int count = (int)jobs.size();
     const int waves = ecc::kBatchWaves;
@@ -571,7 +575,7 @@ void build_batch_tables(int cu_count, const std::vector<Job>& jobs, int32_t nbin
         im.nvox = j.nvox;
         im.params = host_params(j, nbins);
         im.out = j.out;
-        bricks[(size_t)i] = ecc::batch_bricks(im, waves);
+        bricks[(size_t)i] = ecc::batch_bricks(im, waves, shape.depth3, shape.depth2);
         // time of one brick: a team of wpb waves walks its rows (two 2D problems
         // per row in 3D); W / wpb teams of a workgroup share one pass
         const double teams = (double)(waves / im.wpb);
@@ -585,7 +589,7 @@ void build_batch_tables(int cu_count, const std::vector<Job>& jobs, int32_t nbin
         for (int i = 0; i < count; ++i)
             if (T.images[(size_t)i].dtype == dt) { total += bricks[(size_t)i] * brick_cost[(size_t)i]; nbr += bricks[(size_t)i]; }
         if (nbr == 0) continue;
-        const int G = (int)std::max<int64_t>(1, std::min<int64_t>(nbr, 2 * (int64_t)cu_count));
+        const int G = (int)std::max<int64_t>(1, std::min<int64_t>(nbr, (int64_t)shape.wgs_per_cu * cu_count));
         BatchGroup gr{dt, G, T.wg_seg.size()};
         const double per = total / G;
         int wg = 0;
@@ -846,9 +850,38 @@ ecc_status enqueue_streamed(ecc_ctx* ctx, const Job& vol, int32_t nbins, int64_t
 // the plan, written once at creation.
 struct ecc_batch_plan {
     ecc_ctx* ctx = nullptr;
+    std::vector<Job> jobs;
+    int32_t nbins = 0;
+    ecc_batch_shape shape = kDefaultBatchShape;
     BatchTables tables;
     void* dbuf = nullptr;
+    size_t dbuf_bytes = 0;
 };
+
+// Builds the plan's tables for `shape` and uploads them (synchronously: the
+// plan's earlier runs must have finished), growing its device buffer if needed.
+ecc_status plan_upload(ecc_batch_plan* p, const ecc_batch_shape& shape)
+{
+    ecc_ctx* ctx = p->ctx;
+    BatchTables T;
+    build_batch_tables(ctx->cu_count, p->jobs, p->nbins, T, shape);
+    const BatchLayout& lay = T.lay;
+    std::vector<char> host(lay.tables_end);
+    pack_batch_tables(T, host.data());
+    hipError_t e;
+    if (lay.total > p->dbuf_bytes) {
+        void* nb = nullptr;
+        if ((e = hipMalloc(&nb, lay.total)) != hipSuccess) return hip_fail(ctx, e, "hipMalloc(batch plan)");
+        if (p->dbuf) (void)hipFree(p->dbuf);
+        p->dbuf = nb;
+        p->dbuf_bytes = lay.total;
+    }
+    if ((e = hipMemcpy(p->dbuf, host.data(), lay.tables_end, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(ctx, e, "hipMemcpy(batch plan tables)");
+    p->tables = std::move(T);
+    p->shape = shape;
+    return ECC_OK;
+}
 
 extern "C" {
 
@@ -1026,19 +1059,13 @@ ecc_status ecc_batch_plan_create(ecc_ctx* ctx, const ecc_image* imgs, int32_t co
     ecc_batch_plan* p = new (std::nothrow) ecc_batch_plan;
     if (!p) return fail(ctx, ECC_ERR_OUT_OF_MEMORY, "ecc_batch_plan_create: out of host memory");
     p->ctx = ctx;
-    build_batch_tables(ctx->cu_count, jobs, nbins, p->tables);
-    const BatchLayout& lay = p->tables.lay;
-    std::vector<char> host(lay.tables_end);
-    pack_batch_tables(p->tables, host.data());
-    hipError_t e = hipMalloc(&p->dbuf, lay.total);
-    if (e != hipSuccess) {
+    p->jobs = std::move(jobs);
+    p->nbins = nbins;
+    const ecc_status st = plan_upload(p, kDefaultBatchShape);
+    if (st != ECC_OK) {
+        if (p->dbuf) (void)hipFree(p->dbuf);
         delete p;
-        return hip_fail(ctx, e, "hipMalloc(batch plan)");
-    }
-    if ((e = hipMemcpy(p->dbuf, host.data(), lay.tables_end, hipMemcpyHostToDevice)) != hipSuccess) {
-        (void)hipFree(p->dbuf);
-        delete p;
-        return hip_fail(ctx, e, "hipMemcpy(batch plan tables)");
+        return st;
     }
     *plan = p;
     return ECC_OK;
@@ -1062,6 +1089,63 @@ ecc_status ecc_batch_plan_destroy(ecc_batch_plan* plan)
         if (plan->dbuf) (void)hipFree(plan->dbuf);
     }
     delete plan;
+    return ECC_OK;
+}
+
+ecc_status ecc_batch_plan_autotune(ecc_batch_plan* plan, int32_t reps, void* hip_stream, ecc_batch_shape* chosen)
+{
+    if (!plan) return ECC_ERR_INVALID_ARG;
+    ecc_ctx* ctx = plan->ctx;
+    ctx->err.clear();
+    if (reps < 1 || reps > 1000)
+        return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_batch_plan_autotune: reps must be in [1, 1000]");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed");
+    hipStream_t stream = (hipStream_t)hip_stream;
+    hipError_t e;
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
+    // candidates: brick depths (3D planes, 2D rows) and workgroups per CU
+    std::vector<ecc_batch_shape> cand;
+    for (int wgs : {1, 2, 3, 4})
+        for (const auto& d : {std::pair<int, int>{4, 32}, {8, 64}, {16, 128}})
+            cand.push_back(ecc_batch_shape{d.first, d.second, wgs, 0, 0.0});
+    const ecc_batch_shape before = plan->shape;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if ((e = hipEventCreate(&t0)) != hipSuccess || (e = hipEventCreate(&t1)) != hipSuccess) {
+        if (t0) (void)hipEventDestroy(t0);
+        return hip_fail(ctx, e, "hipEventCreate");
+    }
+    ecc_status st = ECC_OK;
+    ecc_batch_shape best = before;
+    best.ms = -1.0;
+    for (auto& c : cand) {
+        if ((st = plan_upload(plan, c)) != ECC_OK) break;
+        // one untimed run, then `reps` timed ones
+        if ((st = launch_batch_kernels(ctx, plan->tables, (char*)plan->dbuf, true, stream)) != ECC_OK) break;
+        if ((e = hipEventRecord(t0, stream)) != hipSuccess) { st = hip_fail(ctx, e, "hipEventRecord"); break; }
+        for (int r = 0; r < reps && st == ECC_OK; ++r)
+            st = launch_batch_kernels(ctx, plan->tables, (char*)plan->dbuf, true, stream);
+        if (st != ECC_OK) break;
+        float ms = 0.f;
+        if ((e = hipEventRecord(t1, stream)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess ||
+            (e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) {
+            st = hip_fail(ctx, e, "batch timing");
+            break;
+        }
+        c.ms = ms / reps;
+        if (best.ms < 0 || c.ms < best.ms) best = c;
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (st == ECC_OK && (e = hipStreamSynchronize(stream)) != hipSuccess) st = hip_fail(ctx, e, "hipStreamSynchronize");
+    const ecc_status st2 = plan_upload(plan, st == ECC_OK ? best : before);
+    if (st != ECC_OK) return st;
+    if (st2 != ECC_OK) return st2;
+    // the outputs hold the batch's ECCs
+    if ((st = launch_batch_kernels(ctx, plan->tables, (char*)plan->dbuf, true, stream)) != ECC_OK) return st;
+    if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+    plan->shape = best;
+    if (chosen) *chosen = best;
     return ECC_OK;
 }
 

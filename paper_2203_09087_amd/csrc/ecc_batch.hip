@@ -134,18 +134,18 @@ hipError_t launch_batch_d(const BatchLaunch& B, hipStream_t s)
 
 }  // namespace
 
-int64_t batch_bricks(BatchImage& im, int waves)
+int64_t batch_bricks(BatchImage& im, int waves, int depth3, int depth2)
 {
     const int64_t cols = (im.g.n2 + 61) / 62;
     im.wpb = (int32_t)(cols < waves ? cols : waves);
     const int64_t chunk = 62 * (int64_t)im.wpb;
     im.nxc = (int32_t)((im.g.n2 + chunk - 1) / chunk);
     if (im.ndim == 3) {
-        im.depth = 8;
+        im.depth = depth3;
         im.nyb = (int32_t)((im.g.n1 + kRows3 - 1) / kRows3);
         return (int64_t)im.nxc * im.nyb * ((im.g.n0 + im.depth - 1) / im.depth);
     }
-    im.depth = 64;
+    im.depth = depth2;
     im.nyb = (int32_t)((im.g.n1 + im.depth - 1) / im.depth);
     return (int64_t)im.nxc * im.nyb;
 }

@@ -152,8 +152,9 @@ hipError_t launch_mm_init(uint32_t* mm, int count, hipStream_t s);
 // Sums every image's partial rows into its out[bin_lo .. bin_lo+width) and, with
 // `scan`, prefix-sums its out[0 .. nbins).
 hipError_t launch_merge_batch(const BatchLaunch& B, bool scan, hipStream_t s);
-// Bricks of one batch image for the batched launch shape (sets nxc, nyb, depth).
-int64_t batch_bricks(BatchImage& im, int waves);
+// Bricks of one batch image for the batched launch shape (sets nxc, nyb, depth):
+// 3D bricks of depth3 planes, 2D bricks of depth2 rows.
+int64_t batch_bricks(BatchImage& im, int waves, int depth3, int depth2);
 #ifndef ECC_BATCH_WAVES
 #define ECC_BATCH_WAVES 9
 #endif

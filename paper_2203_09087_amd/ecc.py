@@ -32,7 +32,8 @@ CONSTRUCTIONS = {"vertex": ECC_VERTEX, "top": ECC_TOP}
 # Symbols declared in include/ecc.h.
 EXPORTED = ("ecc_create", "ecc_destroy", "ecc_last_error", "ecc_compute", "ecc_compute_ex",
             "ecc_compute_batch", "ecc_set_kernel_timing", "ecc_kernel_time", "ecc_batch_plan_create",
-            "ecc_batch_plan_launch", "ecc_batch_plan_destroy", "ecc_autotune", "ecc_compute_streamed",
+            "ecc_batch_plan_launch", "ecc_batch_plan_destroy", "ecc_batch_plan_autotune", "ecc_autotune",
+            "ecc_compute_streamed",
             "ecc_smooth13")
 
 
@@ -48,6 +49,17 @@ class ecc_image(ctypes.Structure):
         ("lo", ctypes.c_double),
         ("hi", ctypes.c_double),
         ("out", ctypes.c_void_p),
+    ]
+
+
+class ecc_batch_shape(ctypes.Structure):
+    """Mirror of ``ecc_batch_shape`` in include/ecc.h."""
+    _fields_ = [
+        ("depth3", ctypes.c_int32),
+        ("depth2", ctypes.c_int32),
+        ("wgs_per_cu", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("ms", ctypes.c_double),
     ]
 
 
@@ -101,6 +113,8 @@ def load_library(path: str = LIB_PATH):
     lib.ecc_batch_plan_launch.argtypes = [vp, vp]
     lib.ecc_batch_plan_launch.restype = ctypes.c_int
     lib.ecc_batch_plan_destroy.argtypes = [vp]
+    lib.ecc_batch_plan_autotune.argtypes = [vp, i32, vp, ctypes.POINTER(ecc_batch_shape)]
+    lib.ecc_batch_plan_autotune.restype = ctypes.c_int
     lib.ecc_batch_plan_destroy.restype = ctypes.c_int
     lib.ecc_autotune.argtypes = [vp, ctypes.POINTER(ecc_image), i32, i32, vp, ctypes.POINTER(ecc_launch_shape)]
     lib.ecc_autotune.restype = ctypes.c_int
@@ -169,6 +183,10 @@ def ecc_batch_plan_create(ctx: int, imgs, nbins: int):
 
 def ecc_batch_plan_launch(plan: int, stream: int = 0) -> int:
     return load_library().ecc_batch_plan_launch(plan, stream)
+
+
+def ecc_batch_plan_autotune(plan: int, reps: int, stream: int, shape: ecc_batch_shape) -> int:
+    return load_library().ecc_batch_plan_autotune(plan, int(reps), stream, ctypes.byref(shape))
 
 
 def ecc_batch_plan_destroy(plan: int) -> int:
@@ -350,6 +368,13 @@ class BatchPlan:
     def launch(self, stream=None):
         self.ctx._check(ecc_batch_plan_launch(self.handle, self.ctx._stream(stream)))
         return self.outs
+
+    def autotune(self, reps: int = 3, stream=None) -> dict:
+        """Times the candidate launch shapes and keeps the fastest (blocking; the
+        outputs hold the batch's ECCs afterwards)."""
+        sh = ecc_batch_shape()
+        self.ctx._check(ecc_batch_plan_autotune(self.handle, reps, self.ctx._stream(stream), sh))
+        return {"depth3": sh.depth3, "depth2": sh.depth2, "wgs_per_cu": sh.wgs_per_cu, "ms": sh.ms}
 
     def close(self):
         if self.handle:

@@ -326,6 +326,32 @@ def test_batch_plan_matches_batch_and_oracle(ctxs, oracle_mod, cons):
         plan.close()
 
 
+@pytest.mark.parametrize("cons", CONS)
+def test_batch_plan_autotune_keeps_results(ctxs, oracle_mod, cons):
+    """The plan's tuner picks one of its candidate shapes; the outputs after tuning
+    and every later launch with the chosen shape equal the oracle."""
+    ctx = ctxs[cons]
+    imgs, ranges = _plan_inputs(42)
+    say(f"case: batch plan autotune, {cons}, {len(imgs)} mixed images, 300 bins")
+    dev = [to_dev(a) for a in imgs]
+    plan = ctx.plan_batch(dev, 300, value_ranges=ranges)
+    try:
+        shape = plan.autotune(reps=1)
+        assert shape["depth3"] in (4, 8, 16) and shape["depth2"] in (32, 64, 128)
+        assert 1 <= shape["wgs_per_cu"] <= 4 and shape["ms"] > 0
+        want = [oracle_mod.ecc(a, 300, cons, value_range=r) for a, r in zip(imgs, ranges)]
+        for g, w in zip(plan.outs, want):
+            assert np.array_equal(g.cpu().numpy(), w)
+        for o in plan.outs:
+            o.fill_(-5)
+        got = [o.cpu().numpy() for o in plan.launch()]
+        torch.cuda.synchronize()
+        for g, w in zip(got, want):
+            assert np.array_equal(g, w)
+    finally:
+        plan.close()
+
+
 def test_batch_plan_graph_replay(ctxs, oracle_mod):
     """A planned batch captured into a HIP graph: every replay, with eager work
     and synchronisation between replays, equals the eager result."""
