@@ -66,3 +66,49 @@ def test_mix_equals_alone(pools, oracle_mod, budget):
     alone.close()
     srv.close()
     assert srv.batches < len(views)   # requests were batched together
+
+
+@pytest.mark.timeout(600)
+def test_full_size_mix_equals_alone(oracle_mod):
+    """The serving configuration the benchmark times: crops of a 4096^2 and a
+    384^3 uint16 GRF pool (2D sides 128..4096, 3D sides 32..384, log-uniform),
+    4096 bins, an 8 GiB admission budget, batches of up to 64 on two lanes, at
+    5000 requests/s.  Every result equals the request computed alone; every
+    25th equals the oracle."""
+    from paper_2203_09087_amd import ecc, serve, synth
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    say("case: full-size serving pools (seeds 61, 62)")
+    p2 = synth.quantize_u16(synth.grf((4096, 4096), seed=61), 4096)
+    p3 = synth.quantize_u16(synth.grf((384, 384, 384), seed=62), 4096)
+    d2, d3 = torch.from_numpy(p2.view(np.int16)).cuda(), torch.from_numpy(p3.view(np.int16)).cuda()
+    reqs = synth.serving_requests(5000.0, 400, seed=6)
+    views = []
+    for q in reqs:
+        o, s = q["offset"], q["shape"]
+        sl = tuple(slice(a, a + b) for a, b in zip(o, s))
+        views.append((d2[sl], p2[sl]) if len(s) == 2 else (d3[sl], p3[sl]))
+    budget = 8 << 30
+    say(f"case: serving {len(views)} full-size requests at 5000/s, budget {budget}")
+    srv = serve.Server(budget_bytes=budget, max_batch=64, lanes=2)
+    alone = ecc.Context(0, "vertex")
+    try:
+        done = srv.run_open_loop([q["t"] for q in reqs],
+                                 lambda i: serve.Request(source=views[i][0], nbins=4096, value_range=(0, 4095)))
+        torch.cuda.synchronize()
+        assert len(done) == len(views)
+        assert srv.peak_held <= budget
+        by_source = {id(v[0]): v for v in views}
+        for k, r in enumerate(done):
+            dev, host = by_source[id(r.source)]
+            got = r.out.cpu().numpy()
+            ref = alone.compute(dev.contiguous(), 4096, value_range=(0, 4095))
+            torch.cuda.synchronize()
+            assert np.array_equal(got, ref.cpu().numpy()), (k, host.shape)
+            if k % 25 == 0:
+                want = oracle_mod.ecc(np.ascontiguousarray(host), 4096, "vertex", value_range=(0, 4095),
+                                      threads=16)
+                assert np.array_equal(got, want), (k, host.shape)
+    finally:
+        alone.close()
+        srv.close()
