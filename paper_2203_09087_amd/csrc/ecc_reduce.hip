@@ -85,25 +85,66 @@ __device__ __forceinline__ bool last_to_arrive(uint32_t* counter, uint32_t total
     return last;
 }
 
-// Inclusive scan of one value per thread across the block; returns the
-// thread's scanned value, and the block total in *total.
-__device__ __forceinline__ int64_t block_scan_values(int64_t v, int64_t* total)
+// Inclusive scan of one value per thread across the wave (lanes shift by 1, 2,
+// 4, ... 32).
+__device__ __forceinline__ int64_t wave_scan(int64_t v)
 {
-    __shared__ int64_t buf[kThreads];
-    const int t = threadIdx.x;
-    buf[t] = v;
-    __syncthreads();
-    for (int off = 1; off < kThreads; off <<= 1) {
-        const int64_t add = t >= off ? buf[t - off] : 0;
-        __syncthreads();
-        buf[t] += add;
-        __syncthreads();
+    const int lane = (int)(threadIdx.x & 63);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t u = __shfl_up(v, off, 64);
+        if (lane >= off) v += u;
     }
-    const int64_t r = buf[t];
-    *total = buf[kThreads - 1];
-    __syncthreads();
-    return r;
+    return v;
 }
+
+// Sum of one value per thread across the wave, in every lane.
+__device__ __forceinline__ int64_t wave_sum(int64_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Inclusive scan of `v` across the block plus the block-wide sum of `add`, in
+// one LDS exchange of the wave totals (one barrier for the exchange, one before
+// the buffer is used again).
+__device__ __forceinline__ int64_t block_scan_plus(int64_t v, int64_t add)
+{
+    constexpr int W = kThreads / 64;
+    __shared__ int64_t wscan[W], wadd[W];
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+    const int64_t inc = wave_scan(v);
+    const int64_t a = wave_sum(add);
+    if (lane == 63) wscan[w] = inc;
+    if (lane == 0) wadd[w] = a;
+    __syncthreads();
+    int64_t before = 0, offset = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        before += k < w ? wscan[k] : 0;
+        offset += wadd[k];
+    }
+    __syncthreads();
+    return inc + before + offset;
+}
+
+// Sum of one value per thread across the block, in every thread.
+__device__ __forceinline__ int64_t block_sum(int64_t v)
+{
+    constexpr int W = kThreads / 64;
+    __shared__ int64_t ws[W];
+    const int64_t a = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = a;
+    __syncthreads();
+    int64_t t = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) t += ws[k];
+    __syncthreads();
+    return t;
+}
+
+static_assert(kMaxLdsBins / kThreads <= kThreads, "k_merge_final gives each earlier block one thread");
 
 __global__ __launch_bounds__(kThreads) void k_merge_groups(const int32_t* __restrict__ partials, int rows,
                                                            int32_t width, int64_t* __restrict__ level2,
@@ -119,8 +160,7 @@ __global__ __launch_bounds__(kThreads) void k_merge_groups(const int32_t* __rest
         level2[(size_t)g * width + j] = s;
     }
     if (btot) {
-        int64_t total;
-        block_scan_values(s, &total);
+        const int64_t total = block_sum(s);
         if (threadIdx.x == 0) btot[(size_t)g * gridDim.x + blockIdx.x] = total;
     }
 }
@@ -132,26 +172,31 @@ __global__ __launch_bounds__(kThreads) void k_merge_final(const int64_t* __restr
                                                           int scan, int sign)
 {
     const int j = blockIdx.x * kThreads + threadIdx.x;
+    // Every row of level2 is loaded, those past `groups` too (they lie in the
+    // buffer, and their values are dropped): a load under a condition becomes a
+    // branch with a wait for each, and the latencies would add up.
     int64_t t = 0;
     if (j < width) {
-        // all group sums in flight at once (one memory latency, not four)
+        int64_t x[kMergeGroups];
 #pragma unroll
-        for (int g = 0; g < kMergeGroups; ++g)
-            if (g < groups) t += level2[(size_t)g * width + j];
+        for (int g = 0; g < kMergeGroups; ++g) x[g] = level2[(size_t)g * width + j];
+#pragma unroll
+        for (int g = 0; g < kMergeGroups; ++g) t += g < groups ? x[g] : 0;
     }
     if (btot) {
-        // offset = sum of the bins of the blocks before this one
+        // offset = sum of the bins of the blocks before this one: thread b < this
+        // block's index adds block b's group totals (blocks <= kThreads, since a
+        // window holds at most kMaxLdsBins bins)
         int64_t part = 0;
-        const int n = groups * (int)blockIdx.x;
-        for (int i = threadIdx.x; i < n; i += kThreads) {
-            const int g = i / (int)blockIdx.x, b = i - g * (int)blockIdx.x;
-            part += btot[(size_t)g * gridDim.x + b];
+        if ((int)threadIdx.x < (int)blockIdx.x) {
+            int64_t x[kMergeGroups];
+#pragma unroll
+            for (int g = 0; g < kMergeGroups; ++g) x[g] = btot[(size_t)g * gridDim.x + threadIdx.x];
+#pragma unroll
+            for (int g = 0; g < kMergeGroups; ++g) part += g < groups ? x[g] : 0;
         }
-        int64_t offset;
-        block_scan_values(part, &offset);
-        int64_t dummy;
-        const int64_t inc = block_scan_values(t, &dummy);
-        if (j < width) out[bin_lo + j] = offset + inc;
+        const int64_t v = block_scan_plus(t, part);
+        if (j < width) out[bin_lo + j] = v;
         return;
     }
     if (j < width) out[bin_lo + j] = (accumulate ? out[bin_lo + j] : 0) + (sign < 0 ? -t : t);
