@@ -5,7 +5,7 @@
 // workgroup, balanced by work, and lists each run as segments of single images.
 // A workgroup processes its segments in order with the same brick bodies as the
 // single-image kernels, and writes one partial histogram row per segment.  The
-// merge kernel then gives every image the sum of its rows (and its prefix scan)
+// merge kernels then give every image the sum of its rows (and its prefix scan)
 // without any atomic operation on the histogram bins, so the result of an image
 // does not depend on the batch it is in.
 #include "ecc_device.h"
@@ -95,21 +95,33 @@ void k_ecc_batch(BatchLaunch B)
     }
 }
 
-// One block per image: out[bin_lo + j] = sum of the image's partial rows; with
-// `scan`, the image's out[0 .. nbins) is then prefix-summed in place.
-__global__ __launch_bounds__(kThreads) void k_merge_batch(BatchLaunch B, int scan)
+// Block (image i, bins y * 256 ..): out[bin_lo + j] = the sum of the image's
+// partial rows.  16 rows are loaded before they are added (rows past the last
+// re-read it and are dropped), so a wide image spread over many workgroups costs
+// a few memory latencies, not one per row.
+__global__ __launch_bounds__(kThreads) void k_merge_batch(BatchLaunch B)
 {
+    constexpr int K = 16;
     const int i = blockIdx.x;
-    const BatchImage& I = B.images[i];
+    const int j = blockIdx.y * kThreads + threadIdx.x;
+    if (j >= B.width) return;
     const int r0 = B.slot_off[i], r1 = B.slot_off[i + 1];
-    for (int j = threadIdx.x; j < B.width; j += kThreads) {
-        int64_t s = 0;
-        for (int r = r0; r < r1; ++r) s += B.partials[(size_t)B.slots[r] * (size_t)B.width + j];
-        I.out[B.bin_lo + j] = s;
+    int64_t s = 0;
+    for (int base = r0; base < r1; base += K) {
+        int32_t x[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            x[k] = B.partials[(size_t)B.slots[min(base + k, r1 - 1)] * (size_t)B.width + j];
+#pragma unroll
+        for (int k = 0; k < K; ++k) s += base + k < r1 ? x[k] : 0;
     }
-    if (!scan) return;
-    __syncthreads();
-    block_scan_inplace(I.out, B.nbins);
+    B.images[i].out[B.bin_lo + j] = s;
+}
+
+// One block per image: out[0 .. nbins) prefix-summed in place.
+__global__ __launch_bounds__(kThreads) void k_scan_batch(BatchLaunch B)
+{
+    block_scan_inplace(B.images[blockIdx.x].out, B.nbins);
 }
 
 template <int DT, int CONS>
@@ -173,7 +185,11 @@ hipError_t launch_ecc_batch(const BatchLaunch& B, int construction, hipStream_t 
 hipError_t launch_merge_batch(const BatchLaunch& B, bool scan, hipStream_t s)
 {
     if (B.count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_merge_batch, dim3(B.count), dim3(kThreads), 0, s, B, scan ? 1 : 0);
+    const unsigned by = (unsigned)((B.width + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_merge_batch, dim3((unsigned)B.count, by), dim3(kThreads), 0, s, B);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !scan) return e;
+    hipLaunchKernelGGL(k_scan_batch, dim3((unsigned)B.count), dim3(kThreads), 0, s, B);
     return hipGetLastError();
 }
 
