@@ -191,6 +191,27 @@ def test_batch_matches_single_and_oracle(ctxs, oracle_mod, cons):
     assert ctxs[cons].compute_batch([], 512) == []
 
 
+@pytest.mark.parametrize("nbins", [4097, 20000])
+def test_batch_wide_histograms(ctxs, oracle_mod, nbins):
+    """Batches whose histograms need several LDS windows (merge per window, the
+    scan after the last), with an image spread over many workgroups (more
+    partial rows than the merge loads at once, and a ragged last round)."""
+    rng = np.random.default_rng(410 + nbins)
+    imgs = [rng.integers(0, 65536, size=(700, 900)).astype(np.uint16),
+            rng.integers(0, 65536, size=(9, 30, 77)).astype(np.uint16),
+            rng.standard_normal((3, 200)).astype(np.float32),
+            rng.integers(0, 256, size=(1, 1)).astype(np.uint8)]
+    ranges = [(0, 65535), "auto", "auto", None]
+    for cons in CONS:
+        say(f"case: batch with {nbins} bins ({cons})")
+        dev = [to_dev(a) for a in imgs]
+        outs = ctxs[cons].compute_batch(dev, nbins, value_ranges=ranges)
+        torch.cuda.synchronize()
+        for a, r, o in zip(imgs, ranges, outs):
+            want = oracle_mod.ecc(a, nbins, cons, value_range=r, threads=8)
+            assert np.array_equal(o.cpu().numpy(), want), (cons, a.shape, a.dtype, r)
+
+
 def test_repeat_runs_are_identical(ctxs):
     from paper_2203_09087_amd import synth
     img = to_dev(synth.grf((64, 80, 96), seed=9))
