@@ -189,10 +189,15 @@ __device__ __forceinline__ void block_scan_inplace(int64_t* v, int32_t n)
     int64_t carry = 0;
     for (int32_t base = 0; base < n; base += kScanChunk) {
         const int m = min(kScanChunk, n - base);
+        // every load is issued before any is used (indices past the chunk
+        // re-read its last value, which is dropped)
+        int64_t x[kScanPer];
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) x[k] = v[base + min(k * kThreads + t, m - 1)];
 #pragma unroll
         for (int k = 0; k < kScanPer; ++k) {
             const int i = k * kThreads + t;
-            buf[i] = i < m ? v[base + i] : 0;
+            buf[i] = i < m ? x[k] : 0;
         }
         __syncthreads();
         int64_t run = 0;
