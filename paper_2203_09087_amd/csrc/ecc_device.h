@@ -361,10 +361,29 @@ __device__ __forceinline__ void flush_hist(const int32_t* hist, int32_t* dst, in
                                            int sign = 1)
 {
     __syncthreads();
-    for (int j = threadIdx.x; j < width; j += blockDim.x) {
-        int32_t t = hist[j];
-        if (sign < 0) t = -t;
-        dst[j] = add ? dst[j] + t : t;
+    if (!add) {
+        for (int j = threadIdx.x; j < width; j += blockDim.x) {
+            const int32_t t = hist[j];
+            dst[j] = sign < 0 ? -t : t;
+        }
+        return;
+    }
+    // adding: a round of the row's old values is loaded before any is written
+    // (indices past the row re-read its last word, which is dropped)
+    constexpr int R = 8;
+    const int step = (int)blockDim.x;
+    for (int j0 = (int)threadIdx.x; j0 < width; j0 += R * step) {
+        int32_t old[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) old[k] = dst[min(j0 + k * step, width - 1)];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int j = j0 + k * step;
+            if (j < width) {
+                const int32_t t = hist[j];
+                dst[j] = old[k] + (sign < 0 ? -t : t);
+            }
+        }
     }
 }
 
