@@ -187,6 +187,17 @@ typedef struct {
 ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32_t reps, void* hip_stream,
                         ecc_launch_shape* chosen);
 
+/* Makes `ctx` use `shape` (HOST pointer) for every later call on an image with
+ * the same key as ecc_autotune's (ndim, dims, dtype, filtration, nbins on the
+ * same side of 4096), as if ecc_autotune had chosen it: for reusing a shape
+ * tuned in another process, e.g. in a run under a profiler, whose timings the
+ * profiler distorts.  A field <= 0 keeps the default for that field; `ms` is
+ * ignored.  The result of a call does not depend on the shape.  Enqueues
+ * nothing.  img->data and img->out are not read; img->ndim is 2 or 3.
+ * Errors: ECC_ERR_INVALID_ARG (null pointer, an invalid descriptor as for
+ * ecc_compute_ex, waves above 9, wgs_per_cu above 16, depth above 4096). */
+ecc_status ecc_set_launch_shape(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, const ecc_launch_shape* shape);
+
 /* A planned batch (Sec. 5's many-files workload, kept on the device): the
  * tables of ecc_compute_batch built once and copied to device memory owned by
  * the plan, so that each launch enqueues kernels only -- no allocation, no host

@@ -1149,6 +1149,23 @@ ecc_status ecc_batch_plan_autotune(ecc_batch_plan* plan, int32_t reps, void* hip
     return ECC_OK;
 }
 
+ecc_status ecc_set_launch_shape(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, const ecc_launch_shape* shape)
+{
+    if (!ctx) return ECC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (!img || !shape) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_set_launch_shape: null pointer");
+    if (shape->waves > ecc::kMaxWaves || shape->wgs_per_cu > 16 || shape->depth > 4096)
+        return fail(ctx, ECC_ERR_INVALID_ARG,
+                    "ecc_set_launch_shape: waves must be at most 9, wgs_per_cu at most 16, depth at most 4096");
+    Job j;
+    ecc_status st = validate(ctx, *img, nbins, "ecc_set_launch_shape", &j);
+    if (st != ECC_OK) return st;
+    ecc_launch_shape c = *shape;
+    c.ms = 0.0;
+    ctx->tuned[tune_key(ctx, j, nbins)] = c;
+    return ECC_OK;
+}
+
 ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32_t reps, void* hip_stream,
                         ecc_launch_shape* chosen)
 {

@@ -33,7 +33,7 @@ CONSTRUCTIONS = {"vertex": ECC_VERTEX, "top": ECC_TOP}
 EXPORTED = ("ecc_create", "ecc_destroy", "ecc_last_error", "ecc_compute", "ecc_compute_ex",
             "ecc_compute_batch", "ecc_set_kernel_timing", "ecc_kernel_time", "ecc_batch_plan_create",
             "ecc_batch_plan_launch", "ecc_batch_plan_destroy", "ecc_batch_plan_autotune", "ecc_autotune",
-            "ecc_compute_streamed",
+            "ecc_set_launch_shape", "ecc_compute_streamed",
             "ecc_smooth13")
 
 
@@ -118,6 +118,8 @@ def load_library(path: str = LIB_PATH):
     lib.ecc_batch_plan_destroy.restype = ctypes.c_int
     lib.ecc_autotune.argtypes = [vp, ctypes.POINTER(ecc_image), i32, i32, vp, ctypes.POINTER(ecc_launch_shape)]
     lib.ecc_autotune.restype = ctypes.c_int
+    lib.ecc_set_launch_shape.argtypes = [vp, ctypes.POINTER(ecc_image), i32, ctypes.POINTER(ecc_launch_shape)]
+    lib.ecc_set_launch_shape.restype = ctypes.c_int
     lib.ecc_compute_streamed.argtypes = [vp, ctypes.POINTER(ecc_image), i32, ctypes.c_int64, vp]
     lib.ecc_compute_streamed.restype = ctypes.c_int
     fltp = ctypes.POINTER(ctypes.c_float)
@@ -198,6 +200,11 @@ def ecc_autotune(ctx: int, img: ecc_image, nbins: int, reps: int, stream: int = 
     shape = ecc_launch_shape()
     st = load_library().ecc_autotune(ctx, ctypes.byref(img), int(nbins), int(reps), stream, ctypes.byref(shape))
     return st, shape
+
+
+def ecc_set_launch_shape(ctx: int, img: ecc_image, nbins: int, waves: int, wgs_per_cu: int, depth: int) -> int:
+    shape = ecc_launch_shape(int(waves), int(wgs_per_cu), int(depth), 0.0)
+    return load_library().ecc_set_launch_shape(ctx, ctypes.byref(img), int(nbins), ctypes.byref(shape))
 
 
 def ecc_compute_streamed(ctx: int, img: ecc_image, nbins: int, slab_planes: int = 0, stream: int = 0) -> int:
@@ -342,6 +349,14 @@ class Context:
                                  self._stream(stream))
         self._check(st)
         return {"waves": shape.waves, "wgs_per_cu": shape.wgs_per_cu, "depth": shape.depth, "ms": shape.ms}
+
+    def set_launch_shape(self, image, nbins: int, waves: int = 0, wgs_per_cu: int = 0, depth: int = 0):
+        """Uses the given launch shape (0: default for that field) for later calls
+        on images shaped like `image` (a tuned shape from another run)."""
+        import torch
+        out = torch.empty(1, dtype=torch.int64, device=image.device)
+        self._check(ecc_set_launch_shape(self.handle, make_image(image, out, None), nbins, waves, wgs_per_cu,
+                                         depth))
 
     def plan_batch(self, images, nbins: int, value_ranges=None, outs=None):
         """A BatchPlan over device tensors (kept alive by the plan object)."""

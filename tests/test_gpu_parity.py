@@ -406,6 +406,32 @@ def test_batch_plan_graph_replay(ctxs, oracle_mod):
         plan.close()
 
 
+def test_set_launch_shape(oracle_mod):
+    """A pinned launch shape (as a profiled run uses) gives the oracle's ECC;
+    out-of-range fields are rejected without changing later calls."""
+    from paper_2203_09087_amd import ecc
+    rng = np.random.default_rng(51)
+    img = rng.standard_normal((20, 70, 300)).astype(np.float32)
+    want = oracle_mod.ecc(img, 4096, "vertex", value_range=(-2.0, 2.0))
+    ctx = ecc.Context(0, "vertex")
+    try:
+        d = to_dev(img)
+        for waves, wgs, depth in ((9, 4, 64), (2, 1, 3), (5, 3, 0), (0, 0, 0)):
+            say(f"case: launch shape waves={waves} wgs_per_cu={wgs} depth={depth}")
+            ctx.set_launch_shape(d, 4096, waves=waves, wgs_per_cu=wgs, depth=depth)
+            got = ctx.compute(d, 4096, value_range=(-2.0, 2.0))
+            torch.cuda.synchronize()
+            assert np.array_equal(got.cpu().numpy(), want), (waves, wgs, depth)
+        for bad in ({"waves": 10}, {"wgs_per_cu": 17}, {"depth": 4097}):
+            with pytest.raises(ecc.EccError):
+                ctx.set_launch_shape(d, 4096, **bad)
+        got = ctx.compute(d, 4096, value_range=(-2.0, 2.0))
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy(), want)
+    finally:
+        ctx.close()
+
+
 @pytest.mark.parametrize("shape,dtype", [((40, 70, 300), np.float32), ((300, 2000), np.uint16)])
 def test_autotune_keeps_results(oracle_mod, shape, dtype):
     """ecc_autotune picks a launch shape for the image shape; every later call
