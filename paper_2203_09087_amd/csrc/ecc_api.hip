@@ -550,7 +550,7 @@ struct BatchTables {
 };
 
 // The batch's launch shape unless a plan was tuned.
-constexpr ecc_batch_shape kDefaultBatchShape = {8, 64, 2, 0, 0.0};
+constexpr ecc_batch_shape kDefaultBatchShape = {8, 128, 2, 0, 0.0};
 
 void build_batch_tables(int cu_count, const std::vector<Job>& jobs, int32_t nbins, BatchTables& T,
                         const ecc_batch_shape& shape = kDefaultBatchShape)
