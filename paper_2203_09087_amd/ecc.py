@@ -160,8 +160,9 @@ def ecc_compute_ex(ctx: int, img: ecc_image, nbins: int, stream: int = 0) -> int
 
 
 def ecc_compute_batch(ctx: int, imgs, nbins: int, stream: int = 0) -> int:
-    arr = (ecc_image * max(1, len(imgs)))(*imgs)
-    return load_library().ecc_compute_batch(ctx, arr, len(imgs), int(nbins), stream)
+    """imgs: a list of ecc_image structures or a make_images() array."""
+    ptr, keep, n = _descriptor_array(imgs)
+    return load_library().ecc_compute_batch(ctx, ptr, n, int(nbins), stream)
 
 
 def ecc_set_kernel_timing(ctx: int, enable: int) -> int:
@@ -177,9 +178,9 @@ def ecc_kernel_time(ctx: int):
 
 def ecc_batch_plan_create(ctx: int, imgs, nbins: int):
     """(status, plan handle or None)."""
-    arr = (ecc_image * max(1, len(imgs)))(*imgs)
+    ptr, keep, n = _descriptor_array(imgs)
     h = ctypes.c_void_p()
-    st = load_library().ecc_batch_plan_create(ctx, arr, len(imgs), int(nbins), ctypes.byref(h))
+    st = load_library().ecc_batch_plan_create(ctx, ptr, n, int(nbins), ctypes.byref(h))
     return st, h.value
 
 
@@ -240,17 +241,72 @@ def make_image(t, out, value_range=None) -> ecc_image:
     im.dtype = _dtype_code(t)
     for i, s in enumerate(t.shape[:4]):
         im.dims[i] = int(s)
-    if value_range is None:
-        im.range_mode = ECC_RANGE_DEFAULT
-    elif isinstance(value_range, str):
-        if value_range != "auto":
-            raise ValueError(f"unknown range {value_range!r}")
-        im.range_mode = ECC_RANGE_AUTO
-    else:
-        im.range_mode = ECC_RANGE_EXPLICIT
-        im.lo, im.hi = float(value_range[0]), float(value_range[1])
+    im.range_mode, im.lo, im.hi = _range_fields(value_range)
     im.out = out.data_ptr()
     return im
+
+
+def _range_fields(value_range):
+    if value_range is None:
+        return ECC_RANGE_DEFAULT, 0.0, 0.0
+    if isinstance(value_range, str):
+        if value_range != "auto":
+            raise ValueError(f"unknown range {value_range!r}")
+        return ECC_RANGE_AUTO, 0.0, 0.0
+    return ECC_RANGE_EXPLICIT, float(value_range[0]), float(value_range[1])
+
+
+_RECORD = []
+
+
+def _image_record():
+    """numpy record type with the byte layout of ``ecc_image`` (built once)."""
+    if _RECORD:
+        return _RECORD[0]
+    import numpy as np
+    f = {n: getattr(ecc_image, n) for n, _ in ecc_image._fields_}
+    _RECORD.append(np.dtype({"names": [n for n, _ in ecc_image._fields_],
+                     "formats": [np.uint64, np.int32, np.int32, (np.int64, 4), np.int32, np.int32, np.float64,
+                                 np.float64, np.uint64],
+                     "offsets": [f[n].offset for n, _ in ecc_image._fields_],
+                     "itemsize": ctypes.sizeof(ecc_image)}))
+    return _RECORD[0]
+
+
+def make_images(tensors, outs, value_ranges=None):
+    """Descriptors of many images at once (as make_image, one record each), as a
+    numpy array with the layout of an ``ecc_image`` array; much cheaper than one
+    ctypes structure per image for large batches."""
+    import numpy as np
+    import torch
+    codes = {torch.uint8: ECC_U8, torch.uint16: ECC_U16, torch.int16: ECC_U16, torch.float32: ECC_F32}
+    if value_ranges is None:
+        value_ranges = [None] * len(tensors)
+    rows = []
+    for t, o, r in zip(tensors, outs, value_ranges):
+        if not t.is_contiguous():
+            raise ValueError("image tensor must be contiguous")
+        code = codes.get(t.dtype)
+        if code is None:
+            raise TypeError(f"unsupported dtype {t.dtype}")
+        sh = tuple(t.shape)[:4]
+        mode, lo, hi = (ECC_RANGE_DEFAULT, 0.0, 0.0) if r is None else _range_fields(r)
+        rows.append((t.data_ptr(), len(t.shape), code, sh + (0,) * (4 - len(sh)), mode, 0, lo, hi, o.data_ptr()))
+    return np.array(rows, dtype=_image_record())
+
+
+def _descriptor_array(imgs):
+    """(pointer to ecc_image[], keep-alive object, count) for a list of
+    ecc_image structures or a make_images array."""
+    if hasattr(imgs, "ctypes") and hasattr(imgs, "dtype"):
+        if imgs.dtype.itemsize != ctypes.sizeof(ecc_image) or not imgs.flags["C_CONTIGUOUS"]:
+            raise ValueError("descriptor array must be a contiguous make_images() array")
+        if len(imgs) == 0:
+            keep = (ecc_image * 1)()
+            return keep, keep, 0
+        return imgs.ctypes.data_as(ctypes.POINTER(ecc_image)), imgs, len(imgs)
+    arr = (ecc_image * max(1, len(imgs)))(*imgs)
+    return arr, arr, len(imgs)
 
 
 class Context:
@@ -298,8 +354,8 @@ class Context:
             outs = [torch.empty(int(nbins), dtype=torch.int64, device=t.device) for t in images]
         if value_ranges is None:
             value_ranges = [None] * len(images)
-        descs = [make_image(t, o, r) for t, o, r in zip(images, outs, value_ranges)]
-        self._check(ecc_compute_batch(self.handle, descs, nbins, self._stream(stream)))
+        self._check(ecc_compute_batch(self.handle, make_images(images, outs, value_ranges), nbins,
+                                      self._stream(stream)))
         return outs
 
     def set_kernel_timing(self, enable: bool = True):
@@ -375,8 +431,7 @@ class BatchPlan:
             torch.empty(int(nbins), dtype=torch.int64, device=t.device) for t in self.images]
         if value_ranges is None:
             value_ranges = [None] * len(self.images)
-        descs = [make_image(t, o, r) for t, o, r in zip(self.images, self.outs, value_ranges)]
-        st, h = ecc_batch_plan_create(ctx.handle, descs, nbins)
+        st, h = ecc_batch_plan_create(ctx.handle, make_images(self.images, self.outs, value_ranges), nbins)
         ctx._check(st)
         self.handle = h
 

@@ -16,6 +16,7 @@ All computation is in the library; this module only schedules calls.
 from __future__ import annotations
 
 import collections
+import gc
 import time
 from dataclasses import dataclass, field
 
@@ -151,17 +152,27 @@ class Server:
 
     def run_open_loop(self, arrivals, make_request):
         """Replays an arrival schedule (seconds from start, ascending): request i is
-        submitted once its time has come; returns the completed requests in order."""
-        t0 = time.perf_counter()
-        i, n = 0, len(arrivals)
-        while i < n or self.busy():
-            now = time.perf_counter()
-            while i < n and t0 + arrivals[i] <= now:
-                req = make_request(i)
-                req.t_arrival = t0 + arrivals[i]
-                self.submit(req)
-                i += 1
-            self.step()
+        submitted once its time has come; returns the completed requests in order.
+
+        Python's cyclic garbage collector is paused while the loop runs (objects
+        are still freed by reference counting): a full collection over the
+        process's objects stalled the loop for about 56 ms."""
+        was_enabled = gc.isenabled()
+        gc.disable()
+        try:
+            t0 = time.perf_counter()
+            i, n = 0, len(arrivals)
+            while i < n or self.busy():
+                now = time.perf_counter()
+                while i < n and t0 + arrivals[i] <= now:
+                    req = make_request(i)
+                    req.t_arrival = t0 + arrivals[i]
+                    self.submit(req)
+                    i += 1
+                self.step()
+        finally:
+            if was_enabled:
+                gc.enable()
         done = sorted(self.completed, key=lambda r: r.t_arrival)
         self.completed = []
         return done

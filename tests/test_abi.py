@@ -74,3 +74,22 @@ def test_product_package_does_not_use_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "ecc_oracle" not in text, f
+
+
+def test_batch_descriptor_array_matches_structures():
+    """make_images() writes the same bytes as one ecc_image structure per image
+    (the batch calls pass its buffer as the ecc_image array)."""
+    torch = pytest.importorskip("torch")
+    from paper_2203_09087_amd import ecc
+    imgs = [torch.zeros((5, 7), dtype=torch.uint8), torch.zeros((2, 3, 4), dtype=torch.int16),
+            torch.zeros((3, 1, 2, 9), dtype=torch.float32), torch.zeros((1, 1), dtype=torch.float32)]
+    outs = [torch.zeros(16, dtype=torch.int64) for _ in imgs]
+    ranges = [None, "auto", (-1.5, 2.25), (0.0, float("inf"))]
+    arr = ecc.make_images(imgs, outs, ranges)
+    structs = (ecc.ecc_image * len(imgs))(*[ecc.make_image(t, o, r) for t, o, r in zip(imgs, outs, ranges)])
+    assert arr.tobytes() == bytes(structs)
+    assert len(ecc.make_images([], [])) == 0
+    with pytest.raises(ValueError):
+        ecc.make_images(imgs[:1], outs[:1], ["nearest"])
+    with pytest.raises(ValueError):
+        ecc.make_images([torch.zeros((4, 6), dtype=torch.uint8)[:, ::2]], outs[:1])

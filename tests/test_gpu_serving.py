@@ -50,6 +50,8 @@ def test_mix_equals_alone(pools, oracle_mod, budget):
     done = srv.run_open_loop(arrivals, lambda i: serve.Request(source=views[i][0], nbins=4096,
                                                                value_range=(0, 4095)))
     torch.cuda.synchronize()
+    import gc
+    assert gc.isenabled()             # the loop pauses the collector and restores it
     assert len(done) == len(views)
     assert srv.peak_held <= budget
     alone = ecc.Context(0, "vertex")
