@@ -212,6 +212,31 @@ def test_batch_wide_histograms(ctxs, oracle_mod, nbins):
             assert np.array_equal(o.cpu().numpy(), want), (cons, a.shape, a.dtype, r)
 
 
+@pytest.mark.parametrize("cons", CONS)
+def test_unaligned_base_pointers(ctxs, oracle_mod, cons):
+    """Images whose first element is not 16-byte aligned (a view into a larger
+    buffer at an element offset): every dtype, AUTO and explicit ranges, alone
+    and as a batch of one."""
+    rng = np.random.default_rng(430)
+    for dtype, shape, nb, rg in ((np.uint8, (37, 91), 256, None), (np.uint16, (9, 13, 70), 4096, "auto"),
+                                 (np.float32, (5, 29, 33), 1000, "auto"), (np.float32, (61, 47), 300, (-1.0, 1.0))):
+        n = int(np.prod(shape))
+        for off in (1, 2, 3):
+            full = (rng.standard_normal(n + 4).astype(np.float32) if dtype == np.float32
+                    else rng.integers(0, 256 if dtype == np.uint8 else 65536, size=n + 4).astype(dtype))
+            base = to_dev(full)
+            view = base[off:off + n].view(shape)
+            assert view.data_ptr() % 16 != 0
+            host = full[off:off + n].reshape(shape)
+            say(f"case: unaligned {np.dtype(dtype).name} {shape} offset {off} elements ({cons})")
+            want = oracle_mod.ecc(host, nb, cons, value_range=rg)
+            got = ctxs[cons].compute(view, nb, value_range=rg)
+            one = ctxs[cons].compute_batch([view], nb, value_ranges=[rg])
+            torch.cuda.synchronize()
+            assert np.array_equal(got.cpu().numpy(), want), (dtype, shape, off)
+            assert np.array_equal(one[0].cpu().numpy(), want), (dtype, shape, off)
+
+
 def test_repeat_runs_are_identical(ctxs):
     from paper_2203_09087_amd import synth
     img = to_dev(synth.grf((64, 80, 96), seed=9))
