@@ -127,7 +127,8 @@ ecc_status ecc_compute(ecc_ctx* ctx, const void* image, int32_t ndim, const int6
  * 4D image is the min/max of all its hyperplanes. */
 ecc_status ecc_compute_ex(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, void* hip_stream);
 
-/* ECC of `count` images in one persistent launch.  imgs: HOST array of `count`
+/* ECC of `count` images in one persistent histogram launch per dtype present
+ * (then one merge and one scan launch for all images).  imgs: HOST array of `count`
  * descriptors; images may differ in ndim, dtype, size and range mode but share
  * nbins and the context's filtration; each writes its own `out`.  The result of
  * every image is identical to what ecc_compute_ex returns for it alone.
