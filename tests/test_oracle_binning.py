@@ -97,3 +97,77 @@ def test_bad_arguments_are_rejected(oracle_mod, args):
     a = np.zeros(4, dtype=args.get("dtype", np.uint8))
     with pytest.raises(ValueError):
         oracle_mod.bins(a, args.get("nbins", 8), args.get("rng"))
+
+
+# ---------------------------------------------------------------------------
+# Float binning near bin boundaries, against exact rational arithmetic.
+#
+# The reading of the gray-level histogram index for float data (Sec. 4 and
+# Algorithm 2 use 0..255 levels) is t = ((double)x - lo) * (nbins / (hi - lo))
+# with every operation rounded once in IEEE double, bin = clamp(floor(t)).  Those
+# three roundings move t by at most about 4 * 2^-53 * t <= 3e-11 for nbins <= 65535,
+# so wherever the exact rational value of (x - lo) * nbins / (hi - lo) lies at least
+# 1e-9 away from an integer, the bin is the exact floor.  The cases below take
+# float32 values adjacent to exact bin boundaries, where the exact value lies within
+# about one float32 ulp of an integer: a computation carried out in float32 (or with
+# a coarser scale) lands on the wrong side of the boundary for many of them.
+from fractions import Fraction  # noqa: E402
+
+
+def _boundary_cases(seed, groups=40, per_group=48):
+    """(x float32 array, lo, hi, nbins, expected bins) groups whose expected bins
+    come from fractions.Fraction alone."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for g in range(groups):
+        nbins = int(rng.choice([7, 97, 256, 1000, 4096, 4095, 65535]))
+        if g % 3 == 0:
+            # float32 range ends, as an AUTO range over float32 data produces them
+            lo = float(np.float32(rng.uniform(-500.0, 500.0)))
+            hi = float(np.float32(lo + 10.0 ** rng.uniform(-2, 4)))
+        else:
+            # arbitrary double range ends (an explicit range)
+            lo = float(rng.uniform(-50.0, 50.0))
+            hi = lo + float(10.0 ** rng.uniform(-1, 3))
+        if not hi > lo:
+            continue
+        flo, fhi = Fraction(lo), Fraction(hi)
+        xs, want = [], []
+        for j in rng.integers(1, nbins, size=per_group):
+            edge = flo + (fhi - flo) * int(j) / nbins          # exact boundary of bin j
+            x0 = np.float32(float(edge))
+            for x in (np.nextafter(x0, np.float32(-np.inf)), x0, np.nextafter(x0, np.float32(np.inf))):
+                t = (Fraction(float(x)) - flo) * nbins / (fhi - flo)
+                dist = abs(t - round(t))
+                if dist < Fraction(1, 10 ** 9) or dist > Fraction(1, 10 ** 3):
+                    continue
+                b = t.numerator // t.denominator                # floor of the exact value
+                xs.append(x)
+                want.append(min(max(b, 0), nbins - 1))
+        if xs:
+            out.append((np.array(xs, dtype=np.float32), lo, hi, nbins, np.array(want)))
+    return out
+
+
+def test_f32_bins_near_boundaries_are_the_exact_floor(oracle_mod):
+    total = 0
+    for xs, lo, hi, nbins, want in _boundary_cases(11):
+        got, used = oracle_mod.bins(xs, nbins, (lo, hi))
+        assert used == (lo, hi)
+        bad = np.nonzero(got != want)[0]
+        assert bad.size == 0, (f"nbins={nbins} range=({lo!r}, {hi!r}): x={xs[bad[0]]!r} "
+                               f"bin {got[bad[0]]} != exact {want[bad[0]]}")
+        total += xs.size
+    assert total > 3000
+
+
+def test_boundary_cases_separate_double_from_float32_arithmetic():
+    """The cases above have teeth: the same formula evaluated in float32
+    (subtraction and product rounded to float32) misplaces some of them."""
+    wrong = 0
+    for xs, lo, hi, nbins, want in _boundary_cases(11):
+        d = xs - np.float32(lo)
+        t = d * np.float32(nbins / (hi - lo))
+        b = np.clip(np.floor(t.astype(np.float64)), 0, nbins - 1).astype(np.int64)
+        wrong += int(np.count_nonzero(b != want))
+    assert wrong > 50

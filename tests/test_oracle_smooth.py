@@ -56,3 +56,42 @@ def test_asymmetric_taps_select_the_right_neighbours(oracle_mod):
     ys = np.minimum(np.arange(20) + 6, 19)
     xs = np.minimum(np.arange(25) + 6, 24)
     assert np.array_equal(out, img[np.ix_(ys, xs)])
+
+
+def test_taps_are_summed_in_order_with_one_rounding_each(oracle_mod):
+    """Each output starts at 0, adds tap k times its neighbour for k = 0..12 in that
+    order, and rounds every sum to float32.  Taps (1, 2^-25 x 12) on a constant
+    image of ones: after the first term the running sum is 1.0, and each further
+    term 2^-25 is below half an ulp of 1.0 (2^-24), so it rounds away; the output
+    is exactly 1.0 in both passes.  Adding the small taps first (any other order)
+    gives 12 * 2^-25 + 1 = 1 + 3 * 2^-23 instead."""
+    taps = np.array([1.0] + [2.0 ** -25] * 12, dtype=np.float32)
+    img = np.ones((9, 14), dtype=np.float32)
+    out = oracle_mod.smooth13(img, taps)
+    assert np.array_equal(out, img)
+
+
+def test_products_are_rounded_before_they_are_added(oracle_mod):
+    """Tap 1 is w = 2^-24 (1 + 2^-12) and the pixel it meets is
+    b = 1 - 2^-12 + 2^-24, so w * b = 2^-24 (1 + 2^-36) exactly, which rounds to
+    2^-24 in float32.  Added to the running sum 1.0 that is an exact tie between
+    1.0 and 1 + 2^-23, which rounds to the even 1.0.  A fused multiply-add keeps
+    the 2^-60 and rounds up to 1 + 2^-23.
+
+    Image: columns alternate 1.0 (even) and b (odd); odd rows are zero.  For an
+    even row y >= 6 the column pass reads tmp[y-6] (tap 0) and a zero row (tap 1),
+    so out[y] = tmp[y-6]; for even x >= 6 the row pass gives 1 * 1.0 + w * b -> 1.0,
+    and for odd x >= 6 it gives 1 * b + w * 1.0 = b + 2^-24 + 2^-36 -> b + 2^-24."""
+    w1 = np.float32(2.0 ** -24 * (1.0 + 2.0 ** -12))
+    b = np.float32(1.0 - 2.0 ** -12 + 2.0 ** -24)
+    assert float(w1) == 2.0 ** -24 * (1.0 + 2.0 ** -12) and float(b) == 1.0 - 2.0 ** -12 + 2.0 ** -24
+    taps = np.zeros(13, dtype=np.float32)
+    taps[0], taps[1] = 1.0, w1
+    n1, n2 = 20, 24
+    img = np.zeros((n1, n2), dtype=np.float32)
+    img[0::2, 0::2] = 1.0
+    img[0::2, 1::2] = b
+    out = oracle_mod.smooth13(img, taps)
+    inner = out[6::2, 6:]
+    assert np.all(inner[:, 0::2] == np.float32(1.0))
+    assert np.all(inner[:, 1::2] == np.float32(float(b) + 2.0 ** -24))
