@@ -243,6 +243,25 @@ ecc_status ecc_batch_plan_autotune(ecc_batch_plan* plan, int32_t reps, void* hip
  * synchronized its launches).  A null plan is accepted and ignored. */
 ecc_status ecc_batch_plan_destroy(ecc_batch_plan* plan);
 
+/* Diagnostics (host only: needs no device, touches no memory the descriptors
+ * point to, enqueues nothing): how ecc_compute_batch, or a plan with launch
+ * shape `shape` (HOST pointer; null = the default shape), splits a batch over
+ * the workgroups of `cu_count` compute units.  The bricks of every image are cut
+ * into segments, one workgroup histogram each; a segment covers at most 2^27
+ * voxels, so its int32 counters cannot overflow (a voxel adds at most 3 in
+ * absolute value per 2D problem and a 3D voxel takes part in two; Sec. 4.3's
+ * shared-memory counters hold the sums).  Outputs (HOST pointers): *segments = the number of segments,
+ * *max_segment_voxels = the most voxels one segment covers (whole bricks), and,
+ * if not null, image_bricks[i] = the bricks of image i and covered_bricks[i] =
+ * the bricks of image i that segments cover (equal for a valid schedule).
+ * imgs: HOST array of `count` (>= 1) descriptors, validated as for
+ * ecc_compute_batch (data and out must be non-null but are not read).
+ * Errors: ECC_ERR_INVALID_ARG, ECC_ERR_UNSUPPORTED; message via
+ * ecc_last_error(NULL). */
+ecc_status ecc_batch_schedule(const ecc_image* imgs, int32_t count, int32_t nbins, const ecc_batch_shape* shape,
+                              int32_t cu_count, int32_t* segments, int64_t* max_segment_voxels,
+                              int64_t* image_bricks, int64_t* covered_bricks);
+
 /* Kernel timing, for measurement tools (the method itself does not need it).
  * With enable != 0, every later call on `ctx` records a pair of HIP events on its
  * stream around each launch of the histogram kernel (the voxel pass of Sec. 2.3

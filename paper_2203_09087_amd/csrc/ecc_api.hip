@@ -552,6 +552,12 @@ struct BatchTables {
 // The batch's launch shape unless a plan was tuned.
 constexpr ecc_batch_shape kDefaultBatchShape = {8, 128, 2, 0, 0.0};
 
+// Voxels one batch segment may cover (counted over whole bricks, so including
+// brick parts outside the image).  Its workgroup histogram and its partial row
+// are int32 and a voxel adds at most 3 in absolute value per 2D problem (two
+// problems in 3D), so 2^27 voxels keep every counter below 2^31.
+constexpr int64_t kSegVoxels = int64_t(1) << 27;
+
 void build_batch_tables(int cu_count, const std::vector<Job>& jobs, int32_t nbins, BatchTables& T,
                         const ecc_batch_shape& shape = kDefaultBatchShape)
 {
@@ -561,7 +567,7 @@ void build_batch_tables(int cu_count, const std::vector<Job>& jobs, int32_t nbin
     T.nbins = nbins;
     T.window = std::min<int32_t>(nbins, ecc::kMaxLdsBins);
     T.images.assign((size_t)count, ecc::BatchImage{});
-    std::vector<int64_t> bricks((size_t)count);
+    std::vector<int64_t> bricks((size_t)count), max_take((size_t)count);
     std::vector<double> brick_cost((size_t)count);
     for (int i = 0; i < count; ++i) {
         const Job& j = jobs[(size_t)i];
@@ -580,6 +586,8 @@ void build_batch_tables(int cu_count, const std::vector<Job>& jobs, int32_t nbin
         // per row in 3D); W / wpb teams of a workgroup share one pass
         const double teams = (double)(waves / im.wpb);
         brick_cost[(size_t)i] = (j.ndim == 3 ? 2.0 * ecc::kRows3 : 1.0) * (double)im.depth / teams;
+        // a segment's histogram is an int32 row: at most kSegVoxels voxels each
+        max_take[(size_t)i] = std::max<int64_t>(1, kSegVoxels / ecc::batch_brick_voxels(im));
     }
     // One launch per dtype present; the bricks of its images, in order, are cut
     // into one contiguous run per workgroup with about equal work.
@@ -604,6 +612,7 @@ void build_batch_tables(int cu_count, const std::vector<Job>& jobs, int32_t nbin
                 int64_t take = (int64_t)std::ceil(room / brick_cost[(size_t)i] - 1e-9);
                 if (wg == G - 1) take = bricks[(size_t)i] - b;
                 take = std::max<int64_t>(1, std::min<int64_t>(take, bricks[(size_t)i] - b));
+                take = std::min<int64_t>(take, max_take[(size_t)i]);
                 T.segs.push_back(ecc::BatchSeg{i, (int32_t)T.segs.size(), b, b + take});
                 acc += take * brick_cost[(size_t)i];
                 b += take;
@@ -992,6 +1001,50 @@ ecc_status ecc_compute_batch(ecc_ctx* ctx, const ecc_image* imgs, int32_t count,
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed");
     return enqueue_batch(ctx, jobs, nbins, (hipStream_t)hip_stream);
+}
+
+ecc_status ecc_batch_schedule(const ecc_image* imgs, int32_t count, int32_t nbins, const ecc_batch_shape* shape,
+                              int32_t cu_count, int32_t* segments, int64_t* max_segment_voxels,
+                              int64_t* image_bricks, int64_t* covered_bricks)
+{
+    g_create_err.clear();
+    if (count < 1 || !imgs || cu_count < 1 || !segments || !max_segment_voxels) {
+        g_create_err = "ecc_batch_schedule: bad argument";
+        return ECC_ERR_INVALID_ARG;
+    }
+    ecc_batch_shape sh = shape ? *shape : kDefaultBatchShape;
+    if (sh.depth3 < 1 || sh.depth2 < 1 || sh.wgs_per_cu < 1) {
+        g_create_err = "ecc_batch_schedule: shape fields must be positive";
+        return ECC_ERR_INVALID_ARG;
+    }
+    ecc_ctx probe;   // carries validation messages only; owns no device resource
+    std::vector<Job> jobs((size_t)count);
+    for (int32_t i = 0; i < count; ++i) {
+        char where[64];
+        snprintf(where, sizeof where, "ecc_batch_schedule: image %d", i);
+        const ecc_status st = validate(&probe, imgs[i], nbins, where, &jobs[(size_t)i]);
+        if (st != ECC_OK) {
+            g_create_err = probe.err;
+            return st;
+        }
+    }
+    BatchTables T;
+    build_batch_tables(cu_count, jobs, nbins, T, sh);
+    int64_t mx = 0;
+    std::vector<int64_t> cov((size_t)count, 0);
+    for (const auto& sg : T.segs) {
+        const int64_t v = (sg.b1 - sg.b0) * ecc::batch_brick_voxels(T.images[(size_t)sg.image]);
+        mx = std::max(mx, v);
+        cov[(size_t)sg.image] += sg.b1 - sg.b0;
+    }
+    *segments = (int32_t)T.segs.size();
+    *max_segment_voxels = mx;
+    for (int32_t i = 0; i < count; ++i) {
+        ecc::BatchImage im = T.images[(size_t)i];
+        if (image_bricks) image_bricks[i] = ecc::batch_bricks(im, ecc::kBatchWaves, sh.depth3, sh.depth2);
+        if (covered_bricks) covered_bricks[i] = cov[(size_t)i];
+    }
+    return ECC_OK;
 }
 
 ecc_status ecc_set_kernel_timing(ecc_ctx* ctx, int32_t enable)

@@ -84,11 +84,13 @@ void k_ecc_batch(BatchLaunch B)
         const uint32_t nxc = (uint32_t)I.nxc, nyb = (uint32_t)I.nyb;
         if (team < teams) {
             for (int64_t b = S.b0 + team; b < S.b1; b += teams) {
-                const uint32_t bb = (uint32_t)b;
+                // brick coordinates from the 64-bit index; each fits 32 bits
+                const int64_t row = b / nxc;
+                const uint32_t xc = (uint32_t)(b - row * nxc);
                 if (I.ndim == 3)
-                    run_brick_3d<DT, CONS, WIN>(L, P, H, chunk, bb % nxc, (bb / nxc) % nyb, bb / (nxc * nyb), xw);
+                    run_brick_3d<DT, CONS, WIN>(L, P, H, chunk, xc, (uint32_t)(row % nyb), (uint32_t)(row / nyb), xw);
                 else
-                    run_brick_2d<DT, CONS, WIN>(L, P, H, chunk, bb % nxc, bb / nxc, xw);
+                    run_brick_2d<DT, CONS, WIN>(L, P, H, chunk, xc, (uint32_t)row, xw);
             }
         }
         flush_hist(hist, B.partials + (size_t)S.slot * (size_t)B.width, B.width);
@@ -160,6 +162,12 @@ int64_t batch_bricks(BatchImage& im, int waves, int depth3, int depth2)
     im.depth = depth2;
     im.nyb = (int32_t)((im.g.n1 + im.depth - 1) / im.depth);
     return (int64_t)im.nxc * im.nyb;
+}
+
+int64_t batch_brick_voxels(const BatchImage& im)
+{
+    const int64_t cols = 62 * (int64_t)im.wpb;
+    return im.ndim == 3 ? cols * kRows3 * im.depth : cols * im.depth;
 }
 
 hipError_t launch_minmax_batch(const BatchImage* images, const BatchPiece* pieces, int npieces, uint32_t* mm,

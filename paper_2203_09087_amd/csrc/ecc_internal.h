@@ -155,6 +155,9 @@ hipError_t launch_merge_batch(const BatchLaunch& B, bool scan, hipStream_t s);
 // Bricks of one batch image for the batched launch shape (sets nxc, nyb, depth):
 // 3D bricks of depth3 planes, 2D bricks of depth2 rows.
 int64_t batch_bricks(BatchImage& im, int waves, int depth3, int depth2);
+// Voxels of one brick of a batch image whose shape batch_bricks has set (whole
+// brick, including any part outside the image).
+int64_t batch_brick_voxels(const BatchImage& im);
 #ifndef ECC_BATCH_WAVES
 #define ECC_BATCH_WAVES 9
 #endif

@@ -34,7 +34,7 @@ EXPORTED = ("ecc_create", "ecc_destroy", "ecc_last_error", "ecc_compute", "ecc_c
             "ecc_compute_batch", "ecc_set_kernel_timing", "ecc_kernel_time", "ecc_batch_plan_create",
             "ecc_batch_plan_launch", "ecc_batch_plan_destroy", "ecc_batch_plan_autotune", "ecc_autotune",
             "ecc_set_launch_shape", "ecc_compute_streamed",
-            "ecc_smooth13")
+            "ecc_smooth13", "ecc_batch_schedule")
 
 
 class ecc_image(ctypes.Structure):
@@ -125,6 +125,9 @@ def load_library(path: str = LIB_PATH):
     fltp = ctypes.POINTER(ctypes.c_float)
     lib.ecc_smooth13.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_int64, fltp, vp]
     lib.ecc_smooth13.restype = ctypes.c_int
+    lib.ecc_batch_schedule.argtypes = [ctypes.POINTER(ecc_image), i32, i32, ctypes.POINTER(ecc_batch_shape), i32,
+                                       ctypes.POINTER(i32), i64p, i64p, i64p]
+    lib.ecc_batch_schedule.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -194,6 +197,18 @@ def ecc_batch_plan_autotune(plan: int, reps: int, stream: int, shape: ecc_batch_
 
 def ecc_batch_plan_destroy(plan: int) -> int:
     return load_library().ecc_batch_plan_destroy(plan)
+
+
+def ecc_batch_schedule(imgs, nbins: int, shape=None, cu_count: int = 256):
+    """Host-only split of a batch (no device needed): (status, segments,
+    max_segment_voxels, image_bricks list, covered_bricks list)."""
+    ptr, keep, n = _descriptor_array(imgs)
+    segs, mx = ctypes.c_int32(), ctypes.c_int64()
+    ib, cb = (ctypes.c_int64 * max(1, n))(), (ctypes.c_int64 * max(1, n))()
+    sh = ctypes.byref(shape) if shape is not None else None
+    st = load_library().ecc_batch_schedule(ptr, n, int(nbins), sh, int(cu_count), ctypes.byref(segs),
+                                           ctypes.byref(mx), ib, cb)
+    return st, segs.value, mx.value, list(ib)[:n], list(cb)[:n]
 
 
 def ecc_autotune(ctx: int, img: ecc_image, nbins: int, reps: int, stream: int = 0):

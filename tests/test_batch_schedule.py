@@ -1,0 +1,78 @@
+"""Host-side checks of how a batch is split over workgroups (no GPU needed).
+
+Each segment of a batch is counted into one int32 workgroup histogram and one
+int32 partial row (the block-shared counters of Sec. 4.3).  A voxel adds at most
+3 in absolute value per 2D problem and a 3D voxel takes part in two, so a segment
+must cover at most 2^27 voxels.  The schedule is computed by the library's own
+host code through ``ecc_batch_schedule``; the descriptors point nowhere (the
+diagnostic reads no image memory).
+"""
+import os
+
+import pytest
+
+from paper_2203_09087_amd import ecc
+
+CAP = 1 << 27
+FAKE = 0x1000   # never dereferenced: the schedule is host-only
+
+
+def _img(dims, dtype=ecc.ECC_U8):
+    im = ecc.ecc_image()
+    im.data = FAKE
+    im.out = FAKE
+    im.ndim = len(dims)
+    im.dtype = dtype
+    for i, d in enumerate(dims):
+        im.dims[i] = d
+    im.range_mode = ecc.ECC_RANGE_DEFAULT
+    return im
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    if not os.path.exists(ecc.LIB_PATH):
+        pytest.skip("libecc_hip.so not built")
+    ecc.load_library()
+
+
+@pytest.mark.parametrize("wgs", [1, 2, 4])
+@pytest.mark.parametrize("shape3", [4, 8, 16])
+@pytest.mark.parametrize("cus", [8, 256])
+def test_one_large_image_is_cut_below_the_counter_bound(wgs, shape3, cus):
+    # one 4096^3 volume alone in a batch (6.9e10 voxels): an even split over
+    # cus * wgs workgroups gives each 2^36 / (cus * wgs) voxels, 2^33 .. 2^26, far
+    # above 2^27 for the small counts; the cap cuts those runs into more segments
+    shape = ecc.ecc_batch_shape(shape3, 64, wgs, 0, 0.0)
+    n = 4096
+    st, segs, mx, ib, cb = ecc.ecc_batch_schedule([_img((n, n, n))], 256, shape, cu_count=cus)
+    assert st == ecc.ECC_OK, ecc.ecc_last_error(None)
+    assert 0 < mx <= CAP
+    assert ib == cb
+    if n ** 3 // (cus * wgs) > CAP:
+        assert segs > cus * wgs   # runs were split
+
+
+def test_large_2d_image_and_a_mix():
+    imgs = [_img((40000, 40000), ecc.ECC_U16), _img((64, 64)), _img((300, 200, 100), ecc.ECC_F32), _img((7, 9))]
+    for wgs in (1, 3):
+        shape = ecc.ecc_batch_shape(8, 128, wgs, 0, 0.0)
+        st, segs, mx, ib, cb = ecc.ecc_batch_schedule(imgs, 4096, shape, cu_count=256)
+        assert st == ecc.ECC_OK, ecc.ecc_last_error(None)
+        assert mx <= CAP and ib == cb and all(b > 0 for b in ib)
+
+
+def test_small_batches_keep_one_segment_per_image_per_workgroup():
+    # the cap never splits small images: each image's bricks go to contiguous runs
+    imgs = [_img((100, 120)), _img((33, 17, 50))]
+    st, segs, mx, ib, cb = ecc.ecc_batch_schedule(imgs, 256, None, cu_count=256)
+    assert st == ecc.ECC_OK
+    assert ib == cb and segs == sum(ib)   # more workgroups than bricks: one brick each
+
+
+def test_schedule_rejects_bad_descriptors():
+    bad = _img((0, 5))
+    st = ecc.ecc_batch_schedule([bad], 256)[0]
+    assert st == ecc.ECC_ERR_INVALID_ARG and "dims" in ecc.ecc_last_error(None)
+    st = ecc.ecc_batch_schedule([_img((2, 3, 4, 5))], 256)[0]
+    assert st == ecc.ECC_ERR_UNSUPPORTED
