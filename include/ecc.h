@@ -127,6 +127,21 @@ ecc_status ecc_compute(ecc_ctx* ctx, const void* image, int32_t ndim, const int6
  * 4D image is the min/max of all its hyperplanes. */
 ecc_status ecc_compute_ex(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, void* hip_stream);
 
+/* ecc_compute_ex for callers that cannot allocate device memory: code being
+ * captured into a HIP graph, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, semantics, results and errors as ecc_compute_ex
+ * (ndim 2|3|4), but the call allocates nothing (no hipMalloc/hipFree, no
+ * allocating library routine): its scratch is a fixed array of 24 MiB
+ * (kNoAllocBytes) that the library keeps on each device it runs on, set up by
+ * the first ecc_create on that device and held until the process ends.  The
+ * context's own scratch is not used.  All calls on one device share that
+ * array, so calls that overlap in time on one device (any context, any
+ * stream) race and give wrong results: the caller serialises them.  The
+ * launch grid is narrowed to fit the array; an image that cannot fit (more than
+ * about 2^38 voxels) is refused with ECC_ERR_UNSUPPORTED before anything is
+ * enqueued.  Asynchronous on hip_stream like ecc_compute_ex. */
+ecc_status ecc_compute_noalloc(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, void* hip_stream);
+
 /* ECC of `count` images in one persistent histogram launch per dtype present
  * (then one merge and one scan launch for all images).  imgs: HOST array of `count`
  * descriptors; images may differ in ndim, dtype, size and range mode but share

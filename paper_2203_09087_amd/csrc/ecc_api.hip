@@ -12,6 +12,7 @@
 #include <cstddef>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <new>
 #include <string>
@@ -348,7 +349,91 @@ Sizes plan_sizes(const ecc_ctx* ctx, const Job& j, int32_t nbins, const ecc_laun
     return s;
 }
 
-// The histogram launches (and merges) of one image or slab.  With pass_only
+// ------------------------------------------- fixed scratch (no allocation)
+//
+// ecc_compute_noalloc takes its scratch from this array instead of the
+// context's buffer.  Each device the library runs on holds its own copy from
+// the first context created there until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it only stands in for the
+// symbol): it uses the device address that hipGetSymbolAddress returned for the
+// current device, kept per device in g_noalloc_ptr.
+constexpr size_t kNoAllocBytes = size_t(24) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+char* g_noalloc_ptr[kMaxDevices] = {};   // device address of `scratch` per device; null until set up
+
+__global__ void k_zero_words(uint32_t* p, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
+// Sets up the fixed scratch of `device`, which must be current: finds its
+// device address and clears the merge counters (which the merge re-arms after
+// every use; the rest of the scratch is written before it is read).  Runs once
+// per device; later calls return at once.
+ecc_status noalloc_setup(int device, std::string& err)
+{
+    if (device < 0 || device >= kMaxDevices) {
+        err = "fixed scratch: device index beyond the supported devices";
+        return ECC_ERR_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (g_noalloc_ptr[device]) return ECC_OK;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        return ECC_ERR_DEVICE;
+    }
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, (hipStream_t)0, (uint32_t*)ptr,
+                       (int)(kCounterBytes / sizeof(uint32_t)));
+    if ((e = hipGetLastError()) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
+        err = std::string("fixed scratch set-up: ") + hipGetErrorString(e);
+        return ECC_ERR_DEVICE;
+    }
+    g_noalloc_ptr[device] = (char*)ptr;
+    return ECC_OK;
+}
+
+// Device scratch of one call, laid out as `sz`: the context's buffer (grown
+// with hipMalloc when too small), or with no_alloc the device's fixed array.
+// For the fixed array the grid is narrowed until the partial rows fit, but never
+// below the workgroups that keep each int32 row from overflowing (a workgroup
+// takes at most 2^27 voxels); an image that cannot fit is refused before
+// anything is enqueued.
+ecc_status call_scratch(ecc_ctx* ctx, const Job& j, bool no_alloc, Sizes& sz, char** base)
+{
+    if (!no_alloc) {
+        const ecc_status st = ensure_ws(ctx, sz.total);
+        if (st != ECC_OK) return st;
+        *base = (char*)ctx->ws;
+        return ECC_OK;
+    }
+    char* ptr = (ctx->device >= 0 && ctx->device < kMaxDevices) ? g_noalloc_ptr[ctx->device] : nullptr;
+    if (!ptr) return fail(ctx, ECC_ERR_DEVICE, "ecc_compute_noalloc: the fixed scratch of this device is not set up");
+    if (sz.total > kNoAllocBytes) {
+        const size_t row = (size_t)sz.window * sizeof(int32_t);
+        const int64_t fit = sz.off_partials < kNoAllocBytes ? (int64_t)((kNoAllocBytes - sz.off_partials) / row) : 0;
+        const int64_t need = (j.nvox >> 27) + 1;
+        if (fit < need) {
+            char buf[160];
+            snprintf(buf, sizeof buf,
+                     "ecc_compute_noalloc: the image needs at least %lld workgroup rows of %zu bytes; the fixed "
+                     "scratch holds %lld",
+                     (long long)need, row, (long long)fit);
+            return fail(ctx, ECC_ERR_UNSUPPORTED, buf);
+        }
+        sz.grid = (int)std::min<int64_t>(sz.grid, fit);
+        sz.total = sz.off_partials + align_up((size_t)sz.grid * row);
+    }
+    *base = ptr;
+    return ECC_OK;
+}
+
+// The histogram launches (and merges) of one image or slab, with the scratch
+// laid out as `sz` from `base`.  With pass_only
 // (one LDS window only) just the histogram kernel runs, writing (or with
 // pass_add adding) its workgroup histograms times `sign` into the partial rows,
 // which a later merge sums.  pdev: binning
@@ -356,11 +441,10 @@ Sizes plan_sizes(const ecc_ctx* ctx, const Job& j, int32_t nbins, const ecc_laun
 // [0, z_own) of j's planes are counted; they are planes z_base.. of a volume
 // of n0_global planes.  accumulate: add the VCEC to out instead of writing it;
 // scan: prefix-sum out after the last window.
-ecc_status enqueue_hist(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t stream, const Sizes& sz,
+ecc_status enqueue_hist(ecc_ctx* ctx, char* base, const Job& j, int32_t nbins, hipStream_t stream, const Sizes& sz,
                         const ecc::BinParams* pdev, int64_t z_own, int64_t z_base, int64_t n0_global,
                         bool accumulate, bool scan, int sign = 1, bool pass_only = false, bool pass_add = false)
 {
-    char* base = (char*)ctx->ws;
     uint32_t* counters = (uint32_t*)(base + sz.off_counters);
     ecc::EccLaunch L;
     L.data = j.data;
@@ -408,12 +492,12 @@ ecc_status enqueue_hist(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t s
 }
 
 ecc_status enqueue_one(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t stream,
-                       const ecc_launch_shape* force = nullptr)
+                       const ecc_launch_shape* force = nullptr, bool no_alloc = false)
 {
-    const Sizes sz = plan_sizes(ctx, j, nbins, force);
-    ecc_status st = ensure_ws(ctx, sz.total);
+    Sizes sz = plan_sizes(ctx, j, nbins, force);
+    char* base = nullptr;
+    ecc_status st = call_scratch(ctx, j, no_alloc, sz, &base);
     if (st != ECC_OK) return st;
-    char* base = (char*)ctx->ws;
     ecc::BinParams* pdev = nullptr;
     hipError_t e;
     if (j.range_mode == ECC_RANGE_AUTO) {
@@ -425,7 +509,7 @@ ecc_status enqueue_one(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t st
         if ((e = ecc::launch_params_from_minmax(mm, blocks, j.dtype, nbins, pdev, stream)) != hipSuccess)
             return hip_fail(ctx, e, "params launch");
     }
-    return enqueue_hist(ctx, j, nbins, stream, sz, pdev, j.g.n0, 0, j.g.n0, false, true);
+    return enqueue_hist(ctx, base, j, nbins, stream, sz, pdev, j.g.n0, 0, j.g.n0, false, true);
 }
 
 // A 4D image as signed 3D passes (the cells of a 4D complex are 3D cells times
@@ -436,7 +520,7 @@ ecc_status enqueue_one(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t st
 // A pair pass reads both hyperplanes and counts the max (min) of their keys.
 // Every pass adds into (or subtracts from) the caller's output, the last one
 // scans it.  The binning parameters are the whole image's.
-ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t stream)
+ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t stream, bool no_alloc = false)
 {
     const int64_t nw = j4.nw;
     const int64_t hv = j4.g.n0 * j4.g.n1 * j4.g.n2;
@@ -445,10 +529,10 @@ ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t st
     h.ndim = 3;
     h.nw = 1;
     h.nvox = hv;
-    const Sizes sz = plan_sizes(ctx, h, nbins);
-    ecc_status st = ensure_ws(ctx, sz.total);
+    Sizes sz = plan_sizes(ctx, h, nbins);
+    char* base = nullptr;
+    ecc_status st = call_scratch(ctx, h, no_alloc, sz, &base);
     if (st != ECC_OK) return st;
-    char* base = (char*)ctx->ws;
     ecc::BinParams* pdev = nullptr;
     hipError_t e;
     if (j4.range_mode == ECC_RANGE_AUTO) {
@@ -462,14 +546,11 @@ ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t st
     }
     const char* img = (const char*)j4.data;
     const bool vertex = ctx->construction == ECC_VERTEX;
-    // the passes in order: hyperplane w, or the pair (w, w+1), with a sign
-    struct Pass { int64_t w; int sign; bool pair; };
-    std::vector<Pass> passes;
-    for (int64_t w = 0; w < nw; ++w) {
-        const int c = vertex ? 1 : -1 + (w == 0) + (w == nw - 1);
-        if (c != 0) passes.push_back({w, c, false});
-        if (w + 1 < nw) passes.push_back({w, vertex ? -1 : 1, true});
-    }
+    // the passes in order: hyperplane w (sign c_w, skipped when 0), then the
+    // pair (w, w+1); counted first, then enqueued (no host allocation)
+    auto single_sign = [&](int64_t w) { return vertex ? 1 : -1 + (w == 0) + (w == nw - 1); };
+    int64_t npasses = 0;
+    for (int64_t w = 0; w < nw; ++w) npasses += (single_sign(w) != 0) + (w + 1 < nw);
     auto plane = [&](int64_t w) { return (const void*)(img + (size_t)w * (size_t)hv * esize); };
     // With one LDS window the passes add into the same workgroup rows and one
     // merge follows, when the int32 rows cannot overflow: a workgroup sees at
@@ -477,14 +558,19 @@ ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t st
     // a voxel adds at most 7 in absolute value.
     const int64_t bricks = ecc::wg_bricks(3, h.g, sz.waves, sz.depth);
     const int64_t per_wg = (bricks + sz.grid - 1) / sz.grid * 62 * sz.waves * ecc::kRows3 * sz.depth;
-    const bool one_merge = sz.window >= nbins && (int64_t)passes.size() * per_wg < (int64_t(1) << 28);
-    for (size_t k = 0; k < passes.size(); ++k) {
-        const Pass& p = passes[k];
-        h.data = plane(p.w);
-        h.data2 = p.pair ? plane(p.w + 1) : nullptr;
-        if ((st = enqueue_hist(ctx, h, nbins, stream, sz, pdev, h.g.n0, 0, h.g.n0, k > 0, k + 1 == passes.size(),
-                               p.sign, one_merge, k > 0)) != ECC_OK)
-            return st;
+    const bool one_merge = sz.window >= nbins && npasses * per_wg < (int64_t(1) << 28);
+    int64_t k = 0;
+    for (int64_t w = 0; w < nw; ++w) {
+        for (int pair = 0; pair < 2; ++pair) {
+            const int sign = pair ? (vertex ? -1 : 1) : single_sign(w);
+            if (sign == 0 || (pair && w + 1 >= nw)) continue;
+            h.data = plane(w);
+            h.data2 = pair ? plane(w + 1) : nullptr;
+            if ((st = enqueue_hist(ctx, base, h, nbins, stream, sz, pdev, h.g.n0, 0, h.g.n0, k > 0,
+                                   k + 1 == npasses, sign, one_merge, k > 0)) != ECC_OK)
+                return st;
+            ++k;
+        }
     }
     if (one_merge) {
         uint32_t* counters = (uint32_t*)(base + sz.off_counters);
@@ -847,7 +933,7 @@ ecc_status enqueue_streamed(ecc_ctx* ctx, const Job& vol, int32_t nbins, int64_t
         Sizes ssz = plan_sizes(ctx, slab, nbins);
         ssz.off_counters = sz.off_counters;   // the layout of the scratch sized above
         if (ssz.total > sz.total) ssz = sz;
-        if ((st = enqueue_hist(ctx, slab, nbins, stream, ssz, pdev, n, z0, N, k > 0, k == nslabs - 1)) != ECC_OK)
+        if ((st = enqueue_hist(ctx, base, slab, nbins, stream, ssz, pdev, n, z0, N, k > 0, k == nslabs - 1)) != ECC_OK)
             return st;
         if ((e = hipEventRecord(ctx->consumed[b], stream)) != hipSuccess)
             return hip_fail(ctx, e, "hipEventRecord(consumed)");
@@ -914,6 +1000,13 @@ ecc_status ecc_create(ecc_ctx** ctx, int32_t device, int32_t construction)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->cu_count = prop.multiProcessorCount;
+    {
+        // the fixed scratch of ecc_compute_noalloc on this device (once per
+        // device; a failure here is reported by that entry point, which retries)
+        DeviceGuard g(device);
+        std::string ignored;
+        if (g.ok) (void)noalloc_setup(device, ignored);
+    }
     g_create_err.clear();
     *ctx = c;
     return ECC_OK;
@@ -957,6 +1050,23 @@ ecc_status ecc_compute_ex(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, voi
     if (!g.ok) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed");
     if (j.ndim == 4) return enqueue_4d(ctx, j, nbins, (hipStream_t)hip_stream);
     return enqueue_one(ctx, j, nbins, (hipStream_t)hip_stream);
+}
+
+ecc_status ecc_compute_noalloc(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, void* hip_stream)
+{
+    if (!ctx) return ECC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (!img) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_compute_noalloc: null descriptor");
+    Job j;
+    ecc_status st = validate(ctx, *img, nbins, "ecc_compute_noalloc", &j, 4);
+    if (st != ECC_OK) return st;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed");
+    if (ctx->device < 0 || ctx->device >= kMaxDevices || !g_noalloc_ptr[ctx->device]) {
+        if ((st = noalloc_setup(ctx->device, ctx->err)) != ECC_OK) return st;
+    }
+    if (j.ndim == 4) return enqueue_4d(ctx, j, nbins, (hipStream_t)hip_stream, true);
+    return enqueue_one(ctx, j, nbins, (hipStream_t)hip_stream, nullptr, true);
 }
 
 ecc_status ecc_compute(ecc_ctx* ctx, const void* image, int32_t ndim, const int64_t* dims,

@@ -34,7 +34,7 @@ EXPORTED = ("ecc_create", "ecc_destroy", "ecc_last_error", "ecc_compute", "ecc_c
             "ecc_compute_batch", "ecc_set_kernel_timing", "ecc_kernel_time", "ecc_batch_plan_create",
             "ecc_batch_plan_launch", "ecc_batch_plan_destroy", "ecc_batch_plan_autotune", "ecc_autotune",
             "ecc_set_launch_shape", "ecc_compute_streamed",
-            "ecc_smooth13", "ecc_batch_schedule")
+            "ecc_smooth13", "ecc_batch_schedule", "ecc_compute_noalloc")
 
 
 class ecc_image(ctypes.Structure):
@@ -102,6 +102,8 @@ def load_library(path: str = LIB_PATH):
     lib.ecc_compute.restype = ctypes.c_int
     lib.ecc_compute_ex.argtypes = [vp, ctypes.POINTER(ecc_image), i32, vp]
     lib.ecc_compute_ex.restype = ctypes.c_int
+    lib.ecc_compute_noalloc.argtypes = [vp, ctypes.POINTER(ecc_image), i32, vp]
+    lib.ecc_compute_noalloc.restype = ctypes.c_int
     lib.ecc_compute_batch.argtypes = [vp, ctypes.POINTER(ecc_image), i32, i32, vp]
     lib.ecc_compute_batch.restype = ctypes.c_int
     lib.ecc_set_kernel_timing.argtypes = [vp, i32]
@@ -160,6 +162,10 @@ def ecc_compute(ctx: int, image_ptr: int, ndim: int, dims, dtype: int, nbins: in
 
 def ecc_compute_ex(ctx: int, img: ecc_image, nbins: int, stream: int = 0) -> int:
     return load_library().ecc_compute_ex(ctx, ctypes.byref(img), int(nbins), stream)
+
+
+def ecc_compute_noalloc(ctx: int, img: ecc_image, nbins: int, stream: int = 0) -> int:
+    return load_library().ecc_compute_noalloc(ctx, ctypes.byref(img), int(nbins), stream)
 
 
 def ecc_compute_batch(ctx: int, imgs, nbins: int, stream: int = 0) -> int:
@@ -360,6 +366,13 @@ class Context:
             out = torch.empty(int(nbins), dtype=torch.int64, device=image.device)
         im = make_image(image, out, value_range)
         self._check(ecc_compute_ex(self.handle, im, nbins, self._stream(stream)))
+        return out
+
+    def compute_noalloc(self, image, nbins: int, out, value_range=None, stream=None):
+        """As compute(), through the entry point that allocates nothing (its
+        scratch is the library's fixed per-device array); `out` is required."""
+        im = make_image(image, out, value_range)
+        self._check(ecc_compute_noalloc(self.handle, im, nbins, self._stream(stream)))
         return out
 
     def compute_batch(self, images, nbins: int, value_ranges=None, outs=None, stream=None):
