@@ -181,7 +181,7 @@ ecc_status ecc_smooth13(ecc_ctx* ctx, const float* in, float* out, int64_t n1, i
                         void* hip_stream);
 
 /* Launch shape of the single-image kernel: waves per workgroup (a workgroup
- * covers waves * 62 consecutive columns), rows (2D) or planes (3D) per
+ * covers waves * 63 consecutive position columns), rows (2D) or planes (3D) per
  * workgroup brick, and resident workgroups per CU aimed for.  `ms` is the mean
  * time of one call measured by ecc_autotune. */
 typedef struct {
@@ -259,21 +259,23 @@ ecc_status ecc_batch_plan_autotune(ecc_batch_plan* plan, int32_t reps, void* hip
 ecc_status ecc_batch_plan_destroy(ecc_batch_plan* plan);
 
 /* Diagnostics (host only: needs no device, touches no memory the descriptors
- * point to, enqueues nothing): how ecc_compute_batch, or a plan with launch
- * shape `shape` (HOST pointer; null = the default shape), splits a batch over
- * the workgroups of `cu_count` compute units.  The bricks of every image are cut
- * into segments, one workgroup histogram each; a segment covers at most 2^27
- * voxels, so its int32 counters cannot overflow (a voxel adds at most 3 in
- * absolute value per 2D problem and a 3D voxel takes part in two; Sec. 4.3's
- * shared-memory counters hold the sums).  Outputs (HOST pointers): *segments = the number of segments,
- * *max_segment_voxels = the most voxels one segment covers (whole bricks), and,
- * if not null, image_bricks[i] = the bricks of image i and covered_bricks[i] =
- * the bricks of image i that segments cover (equal for a valid schedule).
- * imgs: HOST array of `count` (>= 1) descriptors, validated as for
- * ecc_compute_batch (data and out must be non-null but are not read).
+ * point to, enqueues nothing): how ecc_compute_batch on a context of filtration
+ * `construction` (ecc_construction), or a plan with launch shape `shape` (HOST
+ * pointer; null = the default shape), splits a batch over the workgroups of
+ * `cu_count` compute units.  The bricks of every image are cut into segments,
+ * one workgroup histogram each; a segment covers at most 2^27 voxels, so its
+ * int32 counters cannot overflow (a voxel position adds at most 8 in absolute
+ * value; Sec. 4.3's shared-memory counters hold the sums).  Outputs (HOST
+ * pointers): *segments = the number of segments, *max_segment_voxels = the most
+ * voxels one segment covers (whole bricks), and, if not null, image_bricks[i] =
+ * the bricks of image i and covered_bricks[i] = the bricks of image i that
+ * segments cover (equal for a valid schedule).  imgs: HOST array of `count`
+ * (>= 1) descriptors, validated as for ecc_compute_batch (data and out must be
+ * non-null but are not read).
  * Errors: ECC_ERR_INVALID_ARG, ECC_ERR_UNSUPPORTED; message via
  * ecc_last_error(NULL). */
-ecc_status ecc_batch_schedule(const ecc_image* imgs, int32_t count, int32_t nbins, const ecc_batch_shape* shape,
+ecc_status ecc_batch_schedule(const ecc_image* imgs, int32_t count, int32_t nbins, int32_t construction,
+                              const ecc_batch_shape* shape,
                               int32_t cu_count, int32_t* segments, int64_t* max_segment_voxels,
                               int64_t* image_bricks, int64_t* covered_bricks);
 

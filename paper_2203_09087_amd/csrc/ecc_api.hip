@@ -288,13 +288,15 @@ struct Sizes {
 };
 
 // Launch shape of the main kernel for one image:
-//  - waves: a workgroup's waves cover a contiguous x-chunk of 62 * waves columns,
-//    the whole row when it is at most 9 * 62 wide, else chunks of 8 * 62;
+//  - waves: a workgroup's waves cover a contiguous x-chunk of 63 * waves position
+//    columns, the whole row when it has at most 9 * 63 positions, else chunks of
+//    8 * 63;
 //  - depth: planes (3D) or rows (2D) per workgroup brick, chosen so that there are
 //    about two bricks per CU;
 //  - grid: at most two resident workgroups per CU (more concurrent bricks cost
 //    DRAM locality), at least enough that no workgroup histogram can reach 2^31
-//    (every voxel adds at most 6 in absolute value).
+//    (every voxel position adds at most 8 in absolute value: four type counts of
+//    at most 1, and at a brick's last plane four more).
 using TuneKey = std::tuple<int, int, int, int, int64_t, int64_t, int64_t>;
 
 TuneKey tune_key(const ecc_ctx* ctx, const Job& j, int32_t nbins)
@@ -312,15 +314,17 @@ Sizes plan_sizes(const ecc_ctx* ctx, const Job& j, int32_t nbins, const ecc_laun
         auto it = ctx->tuned.find(tune_key(ctx, j, nbins));
         if (it != ctx->tuned.end()) tuned = &it->second;
     }
-    const int64_t cols = (j.g.n2 + 61) / 62;
+    const int cons = ctx->construction;
+    const int64_t xpos = ecc::axis_positions(j.g.n2, cons);
+    const int64_t cols = (xpos + ecc::kLaneCols - 1) / ecc::kLaneCols;
     const int64_t max_waves = j.ndim == 3 ? ECC_MAX_WAVES_3D : ecc::kMaxWaves;
     s.waves = (int)(cols <= max_waves ? cols : std::min<int64_t>(8, max_waves));
     if (tuned && tuned->waves > 0) s.waves = (int)std::min<int64_t>(std::min<int64_t>(tuned->waves, ecc::kMaxWaves), cols);
-    const int64_t chunk = 62 * (int64_t)s.waves;
-    const int64_t nxc = (j.g.n2 + chunk - 1) / chunk;
+    const int64_t chunk = ecc::kLaneCols * (int64_t)s.waves;
+    const int64_t nxc = (xpos + chunk - 1) / chunk;
     const int64_t target = 2 * (int64_t)ctx->cu_count;
     if (j.ndim == 3) {
-        const int64_t nyb = (j.g.n1 + ecc::kRows3 - 1) / ecc::kRows3;
+        const int64_t nyb = (ecc::axis_positions(j.g.n1, cons) + ecc::kRows3 - 1) / ecc::kRows3;
         int64_t d = (j.g.n0 * nxc * nyb + target - 1) / target;
         s.depth = std::min<int64_t>(std::max<int64_t>(d, 4), 32);
         if (tuned && tuned->depth > 0) s.depth = std::min<int64_t>(tuned->depth, 256);
@@ -330,7 +334,7 @@ Sizes plan_sizes(const ecc_ctx* ctx, const Job& j, int32_t nbins, const ecc_laun
         if (tuned && tuned->depth > 0) d = std::min<int64_t>(tuned->depth, 4096);
         s.depth = (d + ecc::kChunk2 - 1) / ecc::kChunk2 * ecc::kChunk2;
     }
-    const int64_t bricks = ecc::wg_bricks(j.ndim, j.g, s.waves, s.depth);
+    const int64_t bricks = ecc::wg_bricks(j.ndim, cons, j.g, s.waves, s.depth);
     const bool windowed = nbins > ecc::kMaxLdsBins;
     int want_per_cu = j.ndim == 3 ? ECC_MAX_WGS_PER_CU_3D : ECC_MAX_WGS_PER_CU_2D;
     if (tuned && tuned->wgs_per_cu > 0) want_per_cu = tuned->wgs_per_cu;
@@ -555,9 +559,9 @@ ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t st
     // With one LDS window the passes add into the same workgroup rows and one
     // merge follows, when the int32 rows cannot overflow: a workgroup sees at
     // most ceil(bricks / grid) bricks of chunk x rows x depth voxels per pass, and
-    // a voxel adds at most 7 in absolute value.
-    const int64_t bricks = ecc::wg_bricks(3, h.g, sz.waves, sz.depth);
-    const int64_t per_wg = (bricks + sz.grid - 1) / sz.grid * 62 * sz.waves * ecc::kRows3 * sz.depth;
+    // a voxel adds at most 8 in absolute value.
+    const int64_t bricks = ecc::wg_bricks(3, ctx->construction, h.g, sz.waves, sz.depth);
+    const int64_t per_wg = (bricks + sz.grid - 1) / sz.grid * ecc::kLaneCols * sz.waves * ecc::kRows3 * sz.depth;
     const bool one_merge = sz.window >= nbins && npasses * per_wg < (int64_t(1) << 28);
     int64_t k = 0;
     for (int64_t w = 0; w < nw; ++w) {
@@ -640,11 +644,12 @@ constexpr ecc_batch_shape kDefaultBatchShape = {8, 128, 2, 0, 0.0};
 
 // Voxels one batch segment may cover (counted over whole bricks, so including
 // brick parts outside the image).  Its workgroup histogram and its partial row
-// are int32 and a voxel adds at most 3 in absolute value per 2D problem (two
-// problems in 3D), so 2^27 voxels keep every counter below 2^31.
+// are int32 and a voxel position adds at most 8 in absolute value (four type
+// counts of at most 1 in 3D, two in 2D, and as many again at a brick's last
+// plane or row), so 2^27 voxels keep every counter below 2^31.
 constexpr int64_t kSegVoxels = int64_t(1) << 27;
 
-void build_batch_tables(int cu_count, const std::vector<Job>& jobs, int32_t nbins, BatchTables& T,
+void build_batch_tables(int cu_count, int construction, const std::vector<Job>& jobs, int32_t nbins, BatchTables& T,
                         const ecc_batch_shape& shape = kDefaultBatchShape)
 {
     const int count = (int)jobs.size();
@@ -667,7 +672,7 @@ void build_batch_tables(int cu_count, const std::vector<Job>& jobs, int32_t nbin
         im.nvox = j.nvox;
         im.params = host_params(j, nbins);
         im.out = j.out;
-        bricks[(size_t)i] = ecc::batch_bricks(im, waves, shape.depth3, shape.depth2);
+        bricks[(size_t)i] = ecc::batch_bricks(im, construction, waves, shape.depth3, shape.depth2);
         // time of one brick: a team of wpb waves walks its rows (two 2D problems
         // per row in 3D); W / wpb teams of a workgroup share one pass
         const double teams = (double)(waves / im.wpb);
@@ -802,7 +807,7 @@ ecc_status launch_batch_kernels(ecc_ctx* ctx, const BatchTables& T, char* d, boo
 ecc_status enqueue_batch(ecc_ctx* ctx, const std::vector<Job>& jobs, int32_t nbins, hipStream_t stream)
 {
     BatchTables T;
-    build_batch_tables(ctx->cu_count, jobs, nbins, T);
+    build_batch_tables(ctx->cu_count, ctx->construction, jobs, nbins, T);
     // the tables follow the single-image counters in the scratch (never overwritten)
     const size_t base = kCounterBytes;
     ecc_status st = ensure_ws(ctx, base + T.lay.total);
@@ -959,7 +964,7 @@ ecc_status plan_upload(ecc_batch_plan* p, const ecc_batch_shape& shape)
 {
     ecc_ctx* ctx = p->ctx;
     BatchTables T;
-    build_batch_tables(ctx->cu_count, p->jobs, p->nbins, T, shape);
+    build_batch_tables(ctx->cu_count, ctx->construction, p->jobs, p->nbins, T, shape);
     const BatchLayout& lay = T.lay;
     std::vector<char> host(lay.tables_end);
     pack_batch_tables(T, host.data());
@@ -1113,13 +1118,18 @@ ecc_status ecc_compute_batch(ecc_ctx* ctx, const ecc_image* imgs, int32_t count,
     return enqueue_batch(ctx, jobs, nbins, (hipStream_t)hip_stream);
 }
 
-ecc_status ecc_batch_schedule(const ecc_image* imgs, int32_t count, int32_t nbins, const ecc_batch_shape* shape,
+ecc_status ecc_batch_schedule(const ecc_image* imgs, int32_t count, int32_t nbins, int32_t construction,
+                              const ecc_batch_shape* shape,
                               int32_t cu_count, int32_t* segments, int64_t* max_segment_voxels,
                               int64_t* image_bricks, int64_t* covered_bricks)
 {
     g_create_err.clear();
     if (count < 1 || !imgs || cu_count < 1 || !segments || !max_segment_voxels) {
         g_create_err = "ecc_batch_schedule: bad argument";
+        return ECC_ERR_INVALID_ARG;
+    }
+    if (construction != ECC_VERTEX && construction != ECC_TOP) {
+        g_create_err = "ecc_batch_schedule: unknown construction";
         return ECC_ERR_INVALID_ARG;
     }
     ecc_batch_shape sh = shape ? *shape : kDefaultBatchShape;
@@ -1139,7 +1149,7 @@ ecc_status ecc_batch_schedule(const ecc_image* imgs, int32_t count, int32_t nbin
         }
     }
     BatchTables T;
-    build_batch_tables(cu_count, jobs, nbins, T, sh);
+    build_batch_tables(cu_count, construction, jobs, nbins, T, sh);
     int64_t mx = 0;
     std::vector<int64_t> cov((size_t)count, 0);
     for (const auto& sg : T.segs) {
@@ -1151,7 +1161,7 @@ ecc_status ecc_batch_schedule(const ecc_image* imgs, int32_t count, int32_t nbin
     *max_segment_voxels = mx;
     for (int32_t i = 0; i < count; ++i) {
         ecc::BatchImage im = T.images[(size_t)i];
-        if (image_bricks) image_bricks[i] = ecc::batch_bricks(im, ecc::kBatchWaves, sh.depth3, sh.depth2);
+        if (image_bricks) image_bricks[i] = ecc::batch_bricks(im, construction, ecc::kBatchWaves, sh.depth3, sh.depth2);
         if (covered_bricks) covered_bricks[i] = cov[(size_t)i];
     }
     return ECC_OK;
@@ -1347,7 +1357,7 @@ ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32
     // candidates: the default shape, then waves, depth and workgroups per CU
     // around it (every shape gives the same result; only the time differs)
     const Sizes def = plan_sizes(ctx, j, nbins);
-    const int64_t cols = (j.g.n2 + 61) / 62;
+    const int64_t cols = (ecc::axis_positions(j.g.n2, ctx->construction) + ecc::kLaneCols - 1) / ecc::kLaneCols;
     std::vector<ecc_launch_shape> cand;
     auto add = [&](int waves, int64_t depth, int wgs) {
         ecc_launch_shape c = {};

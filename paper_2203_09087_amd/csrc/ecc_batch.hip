@@ -80,7 +80,7 @@ void k_ecc_batch(BatchLaunch B)
         // bricks b0 + t, b0 + t + teams, ... (waves beyond the last team idle)
         const int wpb = uniform_u32((uint32_t)I.wpb);
         const int teams = W / wpb, team = wave / wpb, xw = wave - team * wpb;
-        const int64_t chunk = 62 * (int64_t)wpb;
+        const int64_t chunk = kLaneCols * (int64_t)wpb;
         const uint32_t nxc = (uint32_t)I.nxc, nyb = (uint32_t)I.nyb;
         if (team < teams) {
             for (int64_t b = S.b0 + team; b < S.b1; b += teams) {
@@ -148,25 +148,27 @@ hipError_t launch_batch_d(const BatchLaunch& B, hipStream_t s)
 
 }  // namespace
 
-int64_t batch_bricks(BatchImage& im, int waves, int depth3, int depth2)
+int64_t batch_bricks(BatchImage& im, int construction, int waves, int depth3, int depth2)
 {
-    const int64_t cols = (im.g.n2 + 61) / 62;
+    const int64_t xpos = axis_positions(im.g.n2, construction);
+    const int64_t cols = (xpos + kLaneCols - 1) / kLaneCols;
     im.wpb = (int32_t)(cols < waves ? cols : waves);
-    const int64_t chunk = 62 * (int64_t)im.wpb;
-    im.nxc = (int32_t)((im.g.n2 + chunk - 1) / chunk);
+    const int64_t chunk = kLaneCols * (int64_t)im.wpb;
+    im.nxc = (int32_t)((xpos + chunk - 1) / chunk);
     if (im.ndim == 3) {
         im.depth = depth3;
-        im.nyb = (int32_t)((im.g.n1 + kRows3 - 1) / kRows3);
+        im.nyb = (int32_t)((axis_positions(im.g.n1, construction) + kRows3 - 1) / kRows3);
         return (int64_t)im.nxc * im.nyb * ((im.g.n0 + im.depth - 1) / im.depth);
     }
-    im.depth = depth2;
+    // whole chunks of rows per brick (the 2D brick body steps a chunk at a time)
+    im.depth = ((int64_t)(depth2 < 1 ? 1 : depth2) + kChunk2 - 1) / kChunk2 * kChunk2;
     im.nyb = (int32_t)((im.g.n1 + im.depth - 1) / im.depth);
     return (int64_t)im.nxc * im.nyb;
 }
 
 int64_t batch_brick_voxels(const BatchImage& im)
 {
-    const int64_t cols = 62 * (int64_t)im.wpb;
+    const int64_t cols = kLaneCols * (int64_t)im.wpb;
     return im.ndim == 3 ? cols * kRows3 * im.depth : cols * im.depth;
 }
 

@@ -1,51 +1,42 @@
 // ecc_device.h -- device-side building blocks shared by the single-image and
-// the batched kernels (binning, wave helpers, the 2D row step, brick bodies).
+// the batched kernels (binning, wave helpers, type functions, brick bodies).
 //
 // What is computed (Wang, Wagner, Chen, SoCG 2022):
 //   VCEC[j] = sum over cells of the cubical complex whose value has bin j of
 //             (-1)^dim  (Sec. 2.3), and the ECC is its prefix sum (Eq. (1)).
-// Each cell is credited to the voxel that completes it (Sec. 2.3, "Faces
-// introduced by a voxel"; Algorithm 1), so every voxel adds one signed count to
-// the histogram at its own bin.
 //
-// Who completes a cell.  In the vertex filtration a cell's value is the largest
-// bin among its vertices; voxel v completes it if v beats every other vertex,
-// "beats" = larger bin, ties won by the later raster position.  In the top
-// filtration (the paper's) a face takes the smallest bin among the voxels that
-// contain it; v introduces it if v beats them all with "beats" = smaller bin,
-// ties won by the earlier position (the paper's tie-break).  Between two voxels
-// inside the image exactly one of "v beats u (vertex)" and "v beats u (top)"
-// holds, and a voxel outside the image loses every top comparison and wins
-// every vertex one (it belongs to no vertex cell).  So one bit per neighbour,
-//     w(u) = [v wins the vertex comparison against u]   (0 for u outside),
-// serves both filtrations: x = w (vertex) or x = ~w (top).
+// How the cells are counted here.  A cell of a d-dimensional cubical complex is
+// a product of one choice per axis: a single position or a pair of adjacent
+// positions.  Vertex filtration (voxels are vertices, a cell takes the largest
+// value of its voxels): a single is one voxel index k (dimension 0 along the
+// axis), a pair the edge {k, k+1} (dimension 1).  Top filtration (the paper's,
+// Sec. 2.1: voxels are top cells, a face takes the smallest value of the voxels
+// that contain it): a single is the voxel interval k (dimension 1), a pair the
+// lattice point between voxels k-1 and k with voxel set {k-1, k} (dimension 0),
+// the points before the first and after the last voxel included (their outside
+// voxel is ignored).  Fix the choices on all axes but the first ("the marching
+// axis") and take, at every position p of that axis, the max (vertex) or min
+// (top) over the chosen voxels: a "type function" C(p).  The cells of that type
+// are the 1D complex of C along the marching axis with an overall sign
+// (-1)^(number of pairs) (vertex) or (-1)^(number of singles) (top), and a 1D
+// complex is counted by crediting each interval {p, p+1} to the position that
+// attains its value: position p adds +-(1 - [p wins its left interval] -
+// [p wins its right interval]) at C(p) (vertex; the top filtration's points are
+// credited the same way, with -1 for the voxel itself).  Both reduce to
+//     count(p) = d(p) - d(p-1),   d(p) = -[C(p) > C(p+1)] = sign bit of C(p+1) - C(p),
+// with C beyond the image = the sentinel and d(-1) = -1 (vertex ties go to the
+// later position, top ties to the earlier one; the VCEC does not depend on
+// either, since an interval's value is that of whichever position attains it).
+// 3D: the marching axis is z and the types are the four choices in (y, x),
+// two per axis; 2D: the marching axis is y and the types are the two in x.
+// Every count is added to a workgroup histogram in LDS at the key of C(p).
+// Nothing is compared position by position and no per-voxel cell logic remains:
+// a type function is one max/min (the right neighbour through a DPP lane move),
+// a count is two subtractions and a shift.
 //
-// 2D: around a pixel, the 9 cells that contain it are summed as
-//     P(x) = 1 - sum_{i in (t, r, b, l)} x(e_i) & ~(x(e_{i-1}) & x(d_{i-1,i}))
-// (e = edge neighbours in cyclic order, d = the diagonal between two of them).
-// The vertex VCEC of an image is sum_v P(w)(v) at bin(v); the top VCEC is
-// sum_v P(~w)(v).
-//
-// 3D: a cell is (2D cell) x (z-vertex or z-edge).  Its value is the max (vertex)
-// or min (top) over its voxels, so the cells over the z-edge [z, z+1] behave like
-// the 2D complex of the plane max(P_z, P_{z+1}) (vertex) and the faces at the
-// lattice point z like the 2D complex of min(P_{z-1}, P_z) (top):
-//   vertex:  VCEC = sum_z V2(P_z) - sum_{z<n-1} V2(max(P_z, P_{z+1}))
-//   top:     VCEC = sum_z c_z T2(P_z) + sum_{z<n-1} T2(min(P_z, P_{z+1})),
-//            c_z = -1 + [z == 0] + [z == n-1]
-// so the 3D kernel solves two 2D problems per plane.
-//
-// Mapping to the hardware.  One wave handles a brick of 64 consecutive x
-// positions; lanes 0 and 63 are halo (read, never credited), lanes 1..62 own their
-// voxel.  Neighbours along x come from the adjacent lane through DPP; every
-// comparison is one v_cmp whose result is a 64-bit lane mask in SGPRs, and all of
-// the cell logic runs on the scalar unit, 64 voxels per instruction.  Only the
-// comparisons a voxel makes with its right and lower neighbours are evaluated;
-// the ones with its left and upper neighbours are the complements of the
-// neighbours' results, shifted by one lane.  The per-voxel signed count is
-// assembled with carry-in adds (v_addc/v_subb with the mask as carry) and added
-// to a workgroup histogram in LDS by one ds_add per row (lanes that own no voxel
-// add into a spare word of their own, which is cheaper than masking the add).
+// Mapping to the hardware.  One wave handles 64 consecutive x positions; lanes
+// 0..62 own theirs, lane 63 only supplies lane 62's right neighbour.  Rows and
+// planes stay in registers while a wave walks its brick along the marching axis.
 // Workgroup histograms are merged and prefix-scanned by a second kernel.
 #pragma once
 
@@ -55,10 +46,20 @@ namespace ecc {
 namespace dev {
 
 
-constexpr uint32_t kSentinel = 0xFFFFFFFFu;   // above every key
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr uint64_t kOwnLanes = 0x7FFFFFFFFFFFFFFEull;   // lanes 1..62
+
+// Sentinel key: above every key, below 2^31, and such that OR-ing it into any
+// key gives the sentinel (keys are bin << 2 with bins below 4096 in one LDS
+// window, below 65535 with windows).  With one window it is also the byte
+// address of a spare LDS word that absorbs the counts of cells that do not
+// exist (a vertex cell reaching outside the image, a top face with no voxel
+// inside), so they need no masking.
+template <bool WIN>
+__device__ __forceinline__ constexpr uint32_t sentinel_key()
+{
+    return WIN ? 0x3FFFCu : 0x7FFCu;
+}
 
 // ------------------------------------------------------------------ binning
 //
@@ -71,7 +72,8 @@ template <> struct ValT<DT_U16> { using T = uint16_t; };
 template <> struct ValT<DT_F32> { using T = float; };
 
 // Key (bin << kKeyShift, its LDS byte address) of one value, OR-ed with `oob`:
-// 0, or ~0 for lanes outside the image, which makes the key the sentinel.
+// 0, or the sentinel for lanes outside the image, which makes the key the
+// sentinel.
 // IDENT: integer data with nbins == hi - lo + 1, where the bin is the level.
 template <int DT, bool IDENT>
 __device__ __forceinline__ uint32_t key_of(typename ValT<DT>::T v, const BinParams& p, uint32_t oob)
@@ -232,7 +234,7 @@ __device__ __forceinline__ void block_scan_inplace(int64_t* v, int32_t n)
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
-// lane i <- lane i+1 (lane 63 gets 0; it is never owned)
+// lane i <- lane i+1 (lane 63 gets 0; it owns no position)
 __device__ __forceinline__ uint32_t from_right(uint32_t v)
 {
     return __builtin_amdgcn_mov_dpp(v, 0x130 /* wave_shl:1 */, 0xF, 0xF, true);
@@ -242,117 +244,83 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_bal
 
 __device__ __forceinline__ bool lane_bit(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
+// ---------------------------------------------------------- type functions
 
-// acc - [lane bit of m]
-__device__ __forceinline__ int32_t sub_bit(int32_t acc, uint64_t m)
+// The pair operation of the filtration: a vertex-filtration cell takes the
+// largest key of its voxels, a top-filtration face the smallest of the voxels
+// that contain it (voxels outside the image carry the sentinel, so a vertex
+// cell that leaves the image and a top face with no voxel inside get it too).
+template <int CONS>
+__device__ __forceinline__ uint32_t op2(uint32_t a, uint32_t b)
 {
-    int32_t r;
-    uint64_t carry;
-    asm("v_subb_co_u32_e64 %0, %1, %2, 0, %3" : "=v"(r), "=s"(carry) : "v"(acc), "s"(m));
-    return r;
+    return CONS == CONS_VERTEX ? max(a, b) : min(a, b);
 }
 
-// acc + [lane bit of m]
-__device__ __forceinline__ int32_t add_bit(int32_t acc, uint64_t m)
+// op2 of this lane's key and its right neighbour's (lane 63: meaningless, never counted)
+template <int CONS>
+__device__ __forceinline__ uint32_t op_right(uint32_t a)
 {
-    int32_t r;
-    uint64_t carry;
-    asm("v_addc_co_u32_e64 %0, %1, %2, 0, %3" : "=v"(r), "=s"(carry) : "v"(acc), "s"(m));
-    return r;
-}
-
-// ------------------------------------------------- one row of a 2D problem
-
-// State carried from row to row of one 2D problem (one wave, 64 columns).
-struct RowState {
-    uint32_t c;        // keys of the current row
-    uint32_t c_right;  // keys of the current row, one lane to the right
-    uint64_t fb;       // previous row: [above(x) > current(x)]
-    uint64_t fbr;      // previous row: [above(x) > current(x+1)]
-    uint64_t q;        // previous row: [current(x) >= above(x+1)]
-};
-
-__device__ __forceinline__ void row_start(RowState& s, uint32_t above, uint32_t cur)
-{
-    s.c = cur;
-    s.c_right = from_right(cur);
-    const uint32_t above_right = from_right(above);
-    s.fb = ballot(above > cur);
-    s.fbr = ballot(above > s.c_right);
-    s.q = ballot(cur >= above_right);
+    return op2<CONS>(a, from_right(a));
 }
 
 struct HistRef {
-    int32_t* hist;     // LDS: kMaxLdsBins counters, then one spare word per lane
-    uint32_t key_lo;   // key of the first bin of the window
-    uint32_t key_span; // keys in the window
-    uint32_t spare;    // byte offset of this lane's spare word (absorbs adds that do not count)
+    int32_t* hist;     // LDS: kHistCopies copies of kMaxLdsBins counters and spare words
+    uint32_t key_lo;   // key of the first bin of the window (windowed launches)
+    uint32_t key_span; // keys in the window: also the byte offset of the spare word that
+                       // absorbs keys outside the window (windowed launches)
+    uint32_t copy;     // byte offset of this lane's copy (odd lanes: the second)
 };
-
-__device__ __forceinline__ uint32_t spare_offset() { return (uint32_t)(kMaxLdsBins + lane_id()) * 4u; }
 
 __device__ __forceinline__ HistRef hist_ref(int32_t* hist, int32_t bin_lo, int32_t width)
 {
-    return HistRef{hist, (uint32_t)bin_lo << kKeyShift, (uint32_t)width << kKeyShift, spare_offset()};
+    return HistRef{hist, (uint32_t)bin_lo << kKeyShift, (uint32_t)width << kKeyShift,
+                   (__lane_id() & (kHistCopies - 1)) * (uint32_t)(kCopyWords * 4)};
 }
 
+// Adds v to the counter of `key` in this lane's copy.  One window: the key is the
+// counter's byte address in the copy (the sentinel's address is a spare word).
+// Windows: keys outside the window (the sentinel included; below it the
+// subtraction wraps) go to the spare word after the window.
+template <bool WIN>
 __device__ __forceinline__ void hist_add(const HistRef& H, uint32_t key, int32_t v)
 {
-    atomicAdd((int32_t*)((char*)H.hist + key), v);
+    uint32_t a = key;
+    if constexpr (WIN) a = min(key - H.key_lo, H.key_span);
+    atomicAdd((int32_t*)((char*)H.hist + (a + H.copy)), v);
 }
 
-// Credits the current row (owned lanes `own`) with sign SIGN and advances the
-// state to `below`.
-template <int CONS, int SIGN, bool WIN, bool CHECK = true>
-__device__ __forceinline__ void row_step(RowState& s, uint32_t below, uint64_t own, const HistRef& H)
+// One step of a type function along the marching axis.  The type's cells at
+// position p (value `cur`) and on the interval from p to p+1 (value op2(cur,
+// next)) are counted at key `cur` as SIGN * (d - dp): d = -[cur > next] is the
+// sign bit of next - cur (every key is below 2^31), dp the previous step's d,
+// and the interval from p to p+1 goes to the side that attains op2 (vertex:
+// p wins with cur > next, ties to the later position; top: p wins with
+// cur <= next, ties to the earlier one; both give d).  Returns the count and
+// leaves d in dp.
+template <int SIGN>
+__device__ __forceinline__ int32_t step_count(uint32_t cur, uint32_t next, int32_t& dp)
 {
-    const uint32_t c = s.c;
-    // The four comparisons of this row pair.  The lower-left one comes out of q
-    // shifted by a lane, [c(x) > b(x-1)] = ~[b(x-1) >= c(x)], which saves moving
-    // the lower row to the left; the next row reads q itself as its upper-right
-    // comparison.
-    const uint32_t b_right = from_right(below);
-    const uint64_t fr = ballot(c > s.c_right);
-    const uint64_t fbr = ballot(c > b_right);
-    const uint64_t q = ballot(below >= s.c_right);
-    const uint64_t fb = ballot(c > below);
-    if (!CHECK || own) {
-        // vertex-comparison bits of the 8 neighbours (later voxels win ties)
-        uint64_t er = fr, eb = fb, dbr = fbr, dbl = ~(q << 1);
-        uint64_t el = ~(fr << 1), et = ~s.fb, dtl = ~(s.fbr << 1), dtr = s.q;
-        if constexpr (CONS == CONS_TOP) {
-            er = ~er; eb = ~eb; dbr = ~dbr; dbl = ~dbl;
-            el = ~el; et = ~et; dtl = ~dtl; dtr = ~dtr;
-        }
-        const uint64_t tt = et & ~(el & dtl);
-        const uint64_t tr = er & ~(et & dtr);
-        const uint64_t tb = eb & ~(er & dbr);
-        const uint64_t tl = el & ~(eb & dbl);
-        int32_t v;
-        if constexpr (SIGN > 0) v = sub_bit(sub_bit(sub_bit(sub_bit(1, tt), tr), tb), tl);
-        else v = add_bit(add_bit(add_bit(add_bit(-1, tt), tr), tb), tl);
-        // every lane adds; lanes that do not count add into their spare word
-        uint32_t key = c;
-        bool hit = lane_bit(own);
-        if constexpr (WIN) {
-            key -= H.key_lo;
-            hit = hit && key < H.key_span;
-        }
-        hist_add(H, hit ? key : H.spare, v);
-    }
-    s.fb = fb;
-    s.fbr = fbr;
-    s.q = q;
-    s.c = below;
-    s.c_right = b_right;
+    const int32_t d = (int32_t)(next - cur) >> 31;
+    const int32_t c = SIGN > 0 ? d - dp : dp - d;
+    dp = d;
+    return c;
 }
 
 // ------------------------------------------------------------ main kernels
 
 __device__ __forceinline__ void zero_hist(int32_t* hist, int width)
 {
-    for (int j = threadIdx.x; j < width; j += blockDim.x) hist[j] = 0;
+    for (int c = 0; c < kHistCopies; ++c)
+        for (int j = threadIdx.x; j < width; j += blockDim.x) hist[c * kCopyWords + j] = 0;
     __syncthreads();
+}
+
+// The workgroup's count of bin j of the window: the sum of its copies.
+__device__ __forceinline__ int32_t hist_value(const int32_t* hist, int j)
+{
+    int32_t t = hist[j];
+    for (int c = 1; c < kHistCopies; ++c) t += hist[c * kCopyWords + j];
+    return t;
 }
 
 // Writes the workgroup histogram (negated with sign -1) to dst[0..width), or
@@ -363,7 +331,7 @@ __device__ __forceinline__ void flush_hist(const int32_t* hist, int32_t* dst, in
     __syncthreads();
     if (!add) {
         for (int j = threadIdx.x; j < width; j += blockDim.x) {
-            const int32_t t = hist[j];
+            const int32_t t = hist_value(hist, j);
             dst[j] = sign < 0 ? -t : t;
         }
         return;
@@ -380,7 +348,7 @@ __device__ __forceinline__ void flush_hist(const int32_t* hist, int32_t* dst, in
         for (int k = 0; k < R; ++k) {
             const int j = j0 + k * step;
             if (j < width) {
-                const int32_t t = hist[j];
+                const int32_t t = hist_value(hist, j);
                 dst[j] = old[k] + (sign < 0 ? -t : t);
             }
         }
@@ -432,123 +400,216 @@ __device__ __forceinline__ uint32_t advance(uint32_t off, uint32_t step)
     return off;
 }
 
-// One plane step of a 3D brick: problem A on plane z with sign SA (0: skipped)
-// and, with HASB, problem B on the combined plane of z and z+1 with sign SB.
-// The two problems are independent and are advanced row by row together.
-template <int CONS, bool WIN, bool FULL, int SA, bool HASB, int NR>
-__device__ __forceinline__ void plane_step(const uint32_t (&Bc)[NR + 2], const uint32_t (&Bn)[NR + 2],
-                                           uint64_t own_x, int rows_owned, const HistRef& H)
-{
-    constexpr int SB = (CONS == CONS_TOP) ? +1 : -1;
-    auto comb = [&](int r) -> uint32_t {
-        return (CONS == CONS_TOP) ? min(Bc[r], Bn[r]) : max(Bc[r], Bn[r]);
-    };
-    RowState sa, sb;
-    if constexpr (SA != 0) row_start(sa, Bc[0], Bc[1]);
-    if constexpr (HASB) row_start(sb, comb(0), comb(1));
-#pragma unroll
-    for (int r = 1; r <= NR; ++r) {
-        const uint64_t own = (FULL || r <= rows_owned) ? own_x : 0ull;
-        if constexpr (SA != 0) row_step<CONS, SA, WIN, false>(sa, Bc[r + 1], own, H);
-        if constexpr (HASB) row_step<CONS, SB, WIN, false>(sb, comb(r + 1), own, H);
-    }
-}
+// Lanes of a wave: lane l sits at position column x0 + l of its chunk; lanes
+// 0..62 own their position, lane 63 only supplies lane 62's right neighbour.
+constexpr uint64_t kOwnLanes = 0x7FFFFFFFFFFFFFFFull;
 
-// The planes of one 3D brick.  Row r of the brick is image row y0 - 1 + r.
-// FULL: every row of the brick and its halo lies inside the image.  Otherwise
-// the rows outside [0, n1) read the nearest row inside (so every load is in
-// bounds) and take the sentinel key, and rows past the brick's owned rows count
-// nothing; both without branches, so boundary bricks cost about what inner ones
-// do.  Plane indices are 32-bit (see brick_2d).
+// The planes of one 3D brick.  Row r of the brick (0 <= r <= kRows3) is image
+// row ys + r; rows 0 .. kRows3-1 are the brick's, row kRows3 only completes the
+// pairs of row kRows3-1.  FULL: every row read lies inside the image.  Otherwise
+// the rows outside [0, n1) read the nearest row inside (every load in bounds)
+// and take the sentinel key, without branches.  Plane indices are 32-bit.
+// Types of a row (one per choice of a single position or a pair in y and in x):
+//   T0 = row r, T1 = op2(row r, row r+1), T2 = op2(T0, right), T3 = op2(T1, right)
+// with signs +, -, -, + in both filtrations (two type axes).  Planes are the
+// marching axis: plane z of the brick counts every type against plane z+1.
 // PAIR: the volume is the elementwise max (vertex) or min (top) of L.data and
 // L.data2, taken on the keys (the bins' order, so exactly the bin of the max or
 // min value): the combined hyperplanes of a 4D image.
 template <int DT, int CONS, bool WIN, bool FULL, bool IDENT, bool PAIR>
-__device__ __forceinline__ void brick_3d(const EccLaunch& L, const BinParams& P, const HistRef& H, int64_t y0,
+__device__ __forceinline__ void brick_3d(const EccLaunch& L, const BinParams& P, const HistRef& H, int64_t ys,
                                          uint32_t z0, uint32_t zend, uint32_t xob, uint32_t oob, uint64_t own_x,
-                                         int rows_owned, int r_lo, int r_hi)
+                                         int r_lo, int r_hi)
 {
     constexpr int NR = kRows3;
+    constexpr uint32_t SM = sentinel_key<WIN>();
     using T = typename ValT<DT>::T;
     const uint32_t n0 = (uint32_t)L.g.n0;
     const int64_t n1 = L.g.n1, n2 = L.g.n2;
     const uint32_t row_bytes = (uint32_t)(n2 * (int64_t)sizeof(T));
     const char* img = (const char*)L.data;
     const char* img2 = (const char*)L.data2;
-    // first row read: y0 - 1, or the first row inside the image
-    const int64_t ybase = y0 - 1 + (FULL ? 0 : r_lo);
-    constexpr int NR2 = PAIR ? NR + 2 : 1;
+    // first row read: ys, or the first row inside the image
+    const int64_t ybase = ys + (FULL ? 0 : r_lo);
+    constexpr int NR2 = PAIR ? NR + 1 : 1;
 
-    auto load_plane = [&](uint32_t z, T (&raw)[NR + 2], T (&raw2)[NR2]) {
+    auto load_plane = [&](uint32_t z, T (&raw)[NR + 1], T (&raw2)[NR2]) {
         const int64_t off = ((int64_t)z * n1 + ybase) * (int64_t)row_bytes;
         const __amdgpu_buffer_rsrc_t rs = rsrc_at(img + off);
         __amdgpu_buffer_rsrc_t rs2 = rs;
         if constexpr (PAIR) rs2 = rsrc_at(img2 + off);
         uint32_t soff = 0;
 #pragma unroll
-        for (int r = 0; r < NR + 2; ++r) {
+        for (int r = 0; r < NR + 1; ++r) {
             raw[r] = buffer_load<T>(rs, xob, soff);
             if constexpr (PAIR) raw2[r] = buffer_load<T>(rs2, xob, soff);
             // advance while the next row still lies inside the image
             if (FULL || (r >= r_lo && r + 1 < r_hi)) soff = advance(soff, row_bytes);
         }
     };
-    auto keys = [&](const T (&raw)[NR + 2], const T (&raw2)[NR2], uint32_t (&B)[NR + 2]) {
+    auto keys = [&](const T (&raw)[NR + 1], const T (&raw2)[NR2], uint32_t (&K)[NR + 1]) {
 #pragma unroll
-        for (int r = 0; r < NR + 2; ++r) {
-            const uint32_t outside = (FULL || (r >= r_lo && r < r_hi)) ? 0u : ~0u;
-            B[r] = key_of<DT, IDENT>(raw[r], P, oob | outside);
-            if constexpr (PAIR) {
-                const uint32_t k2 = key_of<DT, IDENT>(raw2[r], P, oob | outside);
-                B[r] = CONS == CONS_VERTEX ? max(B[r], k2) : min(B[r], k2);
+        for (int r = 0; r < NR + 1; ++r) {
+            const uint32_t outside = (FULL || (r >= r_lo && r < r_hi)) ? 0u : SM;
+            K[r] = key_of<DT, IDENT>(raw[r], P, oob | outside);
+            if constexpr (PAIR) K[r] = op2<CONS>(K[r], key_of<DT, IDENT>(raw2[r], P, oob | outside));
+        }
+    };
+
+    // lanes that add, per row and kind of y choice (single: T0, T2; pair: T1, T3):
+    // a row's cells of a kind exist only inside the image's positions -- vertex:
+    // singles at rows [0, n1), pairs at rows [0, n1 - 1); top: singles at rows
+    // [0, n1), pairs (lattice points) at rows [-1, n1).  Counts of cells that do
+    // not exist would all go to the one spare word and collide there.
+    uint64_t own1[NR], own2[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        own1[r] = (FULL || (r >= r_lo && r < r_hi)) ? own_x : 0ull;
+        own2[r] = (FULL || (CONS == CONS_TOP ? r < r_hi : r + 1 < r_hi)) ? own_x : 0ull;
+    }
+    // One step of the marching axis: the types of the next plane (keys K) go to
+    // Cn, each type of the current plane (Cc, previous d in Dc) is counted
+    // against them, and the new d goes to Dn.  Two register sets alternate from
+    // step to step, so no state is copied.
+    auto plane_step = [&](const uint32_t (&K)[NR + 1], const uint32_t (&Cc)[NR][4], uint32_t (&Cn)[NR][4],
+                          const int32_t (&Dc)[NR][4], int32_t (&Dn)[NR][4]) {
+        // every count of the step first, then all adds under one lane mask: a
+        // mask switch per row would cut the step into blocks that the compiler
+        // cannot schedule across
+        int32_t c[NR][4];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const uint32_t b = op2<CONS>(K[r], K[r + 1]);
+            Cn[r][0] = K[r];
+            Cn[r][1] = b;
+            Cn[r][2] = op_right<CONS>(K[r]);
+            Cn[r][3] = op_right<CONS>(b);
+            int32_t d[4] = {Dc[r][0], Dc[r][1], Dc[r][2], Dc[r][3]};
+            c[r][0] = step_count<+1>(Cc[r][0], Cn[r][0], d[0]);
+            c[r][1] = step_count<-1>(Cc[r][1], Cn[r][1], d[1]);
+            c[r][2] = step_count<-1>(Cc[r][2], Cn[r][2], d[2]);
+            c[r][3] = step_count<+1>(Cc[r][3], Cn[r][3], d[3]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) Dn[r][t] = d[t];
+        }
+        if (FULL) {
+            if (lane_bit(own_x)) {
+#pragma unroll
+                for (int r = 0; r < NR; ++r)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) hist_add<WIN>(H, Cc[r][t], c[r][t]);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                if (lane_bit(own1[r])) {
+                    hist_add<WIN>(H, Cc[r][0], c[r][0]);
+                    hist_add<WIN>(H, Cc[r][2], c[r][2]);
+                }
+                if (lane_bit(own2[r])) {
+                    hist_add<WIN>(H, Cc[r][1], c[r][1]);
+                    hist_add<WIN>(H, Cc[r][3], c[r][3]);
+                }
+            }
+        }
+    };
+    // the keys of plane z (the sentinel past the volume's last plane)
+    auto plane_keys = [&](uint32_t z, const T (&raw)[NR + 1], const T (&raw2)[NR2], uint32_t (&K)[NR + 1]) {
+        if (z < n0) {
+            keys(raw, raw2, K);
+        } else {
+#pragma unroll
+            for (int r = 0; r < NR + 1; ++r) K[r] = SM;
+        }
+    };
+    // the next brick's first plane (zend) starts with d = 0: its count there
+    // lacks the -d of this brick's last step, which is added here
+    auto end_adds = [&](const uint32_t (&Cc)[NR][4], const int32_t (&Dc)[NR][4]) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (lane_bit(own1[r])) {
+                hist_add<WIN>(H, Cc[r][0], -Dc[r][0]);
+                hist_add<WIN>(H, Cc[r][2], Dc[r][2]);
+            }
+            if (lane_bit(own2[r])) {
+                hist_add<WIN>(H, Cc[r][1], Dc[r][1]);
+                hist_add<WIN>(H, Cc[r][3], -Dc[r][3]);
             }
         }
     };
 
-    uint32_t Bc[NR + 2], Bn[NR + 2];
-    T raw[NR + 2], raw2[NR2];
-    load_plane(z0, raw, raw2);
-    keys(raw, raw2, Bc);
-    for (uint32_t z = z0; z < zend; ++z) {
-        // the next plane's loads are waited for here; other waves' arithmetic
-        // covers their latency (a plane prefetched one step ahead measured no gain)
-        const bool has1 = z + 1 < n0;
-        if (has1) {
-            load_plane(z + 1, raw, raw2);
-            keys(raw, raw2, Bn);
-        }
-        if constexpr (CONS == CONS_VERTEX) {
-            if (has1) plane_step<CONS, WIN, FULL, +1, true, NR>(Bc, Bn, own_x, rows_owned, H);
-            else plane_step<CONS, WIN, FULL, +1, false, NR>(Bc, Bn, own_x, rows_owned, H);
-        } else {
-            // top filtration: plane z enters with -1 + [z == 0] + [z == n0-1]
-            // (positions in the whole volume)
-            const int64_t zg = L.z_base + (int64_t)z;
-            const int ca = -1 + (zg == 0) + (zg == L.n0_global - 1);
-            if (has1) {
-                if (ca < 0) plane_step<CONS, WIN, FULL, -1, true, NR>(Bc, Bn, own_x, rows_owned, H);
-                else plane_step<CONS, WIN, FULL, 0, true, NR>(Bc, Bn, own_x, rows_owned, H);
-            } else {
-                if (ca > 0) plane_step<CONS, WIN, FULL, +1, false, NR>(Bc, Bn, own_x, rows_owned, H);
-                else if (ca < 0) plane_step<CONS, WIN, FULL, -1, false, NR>(Bc, Bn, own_x, rows_owned, H);
-            }
-        }
+    uint32_t Ca[NR][4], Cb[NR][4];   // types of the current plane (the sets alternate)
+    int32_t Da[NR][4], Db[NR][4];    // d of each type's previous step
+    T raw[NR + 1], raw2[NR2];        // loads of the next plane, issued a step ahead
+    {
+        uint32_t K[NR + 1];
+        load_plane(z0, raw, raw2);
+        keys(raw, raw2, K);
 #pragma unroll
-        for (int r = 0; r < NR + 2; ++r) Bc[r] = Bn[r];
+        for (int r = 0; r < NR; ++r) {
+            const uint32_t b = op2<CONS>(K[r], K[r + 1]);
+            Ca[r][0] = K[r];
+            Ca[r][1] = b;
+            Ca[r][2] = op_right<CONS>(K[r]);
+            Ca[r][3] = op_right<CONS>(b);
+        }
+    }
+    // the volume's first plane has nothing before it (d = -1: it wins the
+    // interval before it); a later brick's first plane gets the rest of its
+    // count from the brick before it (end_adds).  A type whose cells do not exist
+    // (its value is the sentinel in every plane) starts with d = 0, so all its
+    // counts are 0: they may land on any word, the other copy's counters included.
+    if (L.z_base + (int64_t)z0 == 0) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) Da[r][t] = Ca[r][t] == SM ? 0 : -1;
+    } else {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) Da[r][t] = 0;
+    }
+    if (z0 + 1 < n0) load_plane(z0 + 1, raw, raw2);
+    bool odd = false;   // the last step wrote the b set
+    for (uint32_t z = z0; z < zend; z += 2) {
+        {
+            uint32_t K[NR + 1];
+            plane_keys(z + 1, raw, raw2, K);
+            if (z + 1 < zend && z + 2 < n0) load_plane(z + 2, raw, raw2);
+            plane_step(K, Ca, Cb, Da, Db);
+        }
+        if (z + 1 < zend) {
+            uint32_t K[NR + 1];
+            plane_keys(z + 2, raw, raw2, K);
+            if (z + 2 < zend && z + 3 < n0) load_plane(z + 3, raw, raw2);
+            plane_step(K, Cb, Ca, Db, Da);
+        } else {
+            odd = true;
+        }
+    }
+    if (L.z_base + (int64_t)zend < L.n0_global) {
+        if (odd) end_adds(Cb, Db);
+        else end_adds(Ca, Da);
     }
 }
 
-// The rows [y0, yend) of one 2D brick for one wave: rows are streamed in chunks
-// of kChunk2, the next chunk loading while the current one is processed.
-// Row indices are 32-bit (the scalar unit compares 32-bit values only; 64-bit
-// loop bounds would move the loop, and every mask derived from it, to vector
-// registers).  Rows are at most 2^31, so y + 2 * kChunk2 does not wrap.
+// The rows [y0, yend) of one 2D brick for one wave: rows are the marching axis,
+// loaded in chunks of kChunk2, the next chunk loading while the current one is
+// counted.  Types of a row: T0 = the row, T1 = op2(T0, right), with signs +, -
+// (vertex) or -, + (top: a single position is a voxel, of dimension 1 along x).
+// yend - y0 is a multiple of kChunk2 unless yend == n1 (the rows past the image
+// carry the sentinel and count into the spare word).  Row indices are 32-bit.
 template <int DT, int CONS, bool WIN, bool IDENT>
 __device__ __forceinline__ void brick_2d(const void* data, uint32_t n1, int64_t n2, const BinParams& P,
                                          const HistRef& H, uint32_t y0, uint32_t yend, uint32_t xo, uint32_t oob,
                                          uint64_t own_x)
 {
     constexpr uint32_t CH = kChunk2;
+    constexpr uint32_t kGroup2 = 8;   // rows whose adds share one lane mask
+    static_assert(CH % kGroup2 == 0, "row chunks hold whole groups");
+    constexpr uint32_t SM = sentinel_key<WIN>();
+    constexpr int S0 = CONS == CONS_VERTEX ? 1 : -1;
     using T = typename ValT<DT>::T;
     const T* __restrict__ img = (const T*)data;
     const uint32_t row_bytes = (uint32_t)(n2 * (int64_t)sizeof(T));
@@ -573,75 +634,110 @@ __device__ __forceinline__ void brick_2d(const void* data, uint32_t n1, int64_t 
             soff = advance(soff, row_bytes);
         }
     };
-    RowState s;
+    uint32_t c0, c1;   // types of the current row
+    int32_t d0, d1;    // d of the previous step
     {
-        const uint32_t above = y0 == 0 ? kSentinel : key_of<DT, IDENT>(img[(int64_t)(y0 - 1) * n2 + xo], P, oob);
-        row_start(s, above, key_of<DT, IDENT>(img[(int64_t)y0 * n2 + xo], P, oob));
+        const uint32_t k = key_of<DT, IDENT>(img[(int64_t)y0 * n2 + xo], P, oob);
+        c0 = k;
+        c1 = op_right<CONS>(k);
+        // the image's first row wins the interval before it (d = -1); a type
+        // whose cells do not exist (the sentinel) starts with d = 0, so all its
+        // counts are 0 (they may land on any word, the other copy's included)
+        d0 = (y0 == 0 && c0 != SM) ? -1 : 0;
+        d1 = (y0 == 0 && c1 != SM) ? -1 : 0;
     }
     T raw[CH];
     if (y0 + CH < n1) load_chunk_full(y0 + 1, raw);
     else load_chunk(y0 + 1, raw);
     for (uint32_t y = y0; y < yend; y += CH) {
-        // Uniform per chunk: the rows below (y+1 .. y+CH) all lie in the image,
-        // and the rows owned (y .. y+CH-1) all lie in the brick.
-        const bool keys_full = y + CH < n1;
-        const bool own_full = y + CH <= yend;
+        // uniform per chunk: the rows below (y+1 .. y+CH) all lie in the image
         uint32_t b[CH];
-        if (keys_full) {
+        if (y + CH < n1) {
 #pragma unroll
             for (uint32_t k = 0; k < CH; ++k) b[k] = key_of<DT, IDENT>(raw[k], P, oob);
         } else {
 #pragma unroll
             for (uint32_t k = 0; k < CH; ++k)
-                b[k] = (y + 1 + k < n1) ? key_of<DT, IDENT>(raw[k], P, oob) : kSentinel;
+                b[k] = (y + 1 + k < n1) ? key_of<DT, IDENT>(raw[k], P, oob) : SM;
         }
         if (y + CH < yend) {
             if (y + 2 * CH < n1) load_chunk_full(y + CH + 1, raw);
             else load_chunk(y + CH + 1, raw);
         }
-        if (own_full) {
+        // the counts of a group of rows first, then their adds under one lane
+        // mask (rows past the image, at the end of the last chunk, have no cells)
 #pragma unroll
-            for (uint32_t k = 0; k < CH; ++k) row_step<CONS, +1, WIN, false>(s, b[k], own_x, H);
-        } else {
-            // rows past the brick run with no owned lanes (a branch around
-            // them here would make the compiler treat the row state as divergent)
+        for (uint32_t g = 0; g < CH; g += kGroup2) {
+            uint32_t a0[kGroup2], a1[kGroup2];
+            int32_t e0[kGroup2], e1[kGroup2];
 #pragma unroll
-            for (uint32_t k = 0; k < CH; ++k) {
-                const uint64_t own = (y + k < yend) ? own_x : 0ull;
-                row_step<CONS, +1, WIN, false>(s, b[k], own, H);
+            for (uint32_t k = 0; k < kGroup2; ++k) {
+                const uint32_t n0 = b[g + k], n1v = op_right<CONS>(b[g + k]);
+                a0[k] = c0;
+                a1[k] = c1;
+                e0[k] = step_count<S0>(c0, n0, d0);
+                e1[k] = step_count<-S0>(c1, n1v, d1);
+                c0 = n0;
+                c1 = n1v;
+            }
+            if (y + g + kGroup2 <= n1) {
+                if (lane_bit(own_x)) {
+#pragma unroll
+                    for (uint32_t k = 0; k < kGroup2; ++k) {
+                        hist_add<WIN>(H, a0[k], e0[k]);
+                        hist_add<WIN>(H, a1[k], e1[k]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (uint32_t k = 0; k < kGroup2; ++k) {
+                    if (lane_bit(y + g + k < n1 ? own_x : 0ull)) {
+                        hist_add<WIN>(H, a0[k], e0[k]);
+                        hist_add<WIN>(H, a1[k], e1[k]);
+                    }
+                }
             }
         }
     }
+    // the next brick's first row (yend) starts with d = 0: the -d of this
+    // brick's last step is added here
+    if (yend < n1 && lane_bit(own_x)) {
+        hist_add<WIN>(H, c0, S0 > 0 ? -d0 : d0);
+        hist_add<WIN>(H, c1, S0 > 0 ? d1 : -d1);
+    }
 }
 
-// Column placement of one wave inside a workgroup brick: lane 0 and lane 63 are
-// halo, lanes 1..62 own columns x0 + 62 * wave + lane - 1.
+// Column placement of one wave inside a workgroup brick whose first lane sits
+// at position column x0: lane l at column x0 + 63 * wave + l.
 struct WaveCols {
-    bool active;       // the wave owns at least one column of the image
-    uint32_t oob;      // 0 if this lane's column lies inside the image, else ~0
-    uint64_t own_x;    // owned lanes
-    uint32_t xo;       // this lane's column, clamped into the image
+    bool active;       // the wave owns at least one position column (columns below n2)
+    uint32_t oob;      // 0 if this lane's column lies inside the image, else the sentinel
+    uint64_t own;      // lanes 0..62 at columns below n2: the lanes that add (a lane past
+                       // the image only has cells that do not exist, whose counts would all
+                       // go to the one spare word and collide there)
+    uint32_t xo;       // this lane's column, clamped into the image (what it loads)
 };
 
 // Index of this wave in its workgroup, known to the compiler to be wave-uniform.
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
+template <bool WIN>
 __device__ __forceinline__ WaveCols wave_cols(int64_t x0, int wave, int64_t n2)
 {
     WaveCols w;
-    const int64_t first = x0 + (int64_t)wave * 62;
+    const int64_t first = x0 + (int64_t)wave * kLaneCols;
     w.active = first < n2;
-    const int64_t x = first - 1 + (int64_t)lane_id();
+    const int64_t x = first + (int64_t)lane_id();
     const bool x_ok = x >= 0 && x < n2;
-    const uint64_t xmask = ballot(x_ok);
-    w.oob = x_ok ? 0u : ~0u;
-    w.own_x = xmask & kOwnLanes;
+    w.oob = x_ok ? 0u : sentinel_key<WIN>();
+    w.own = ballot(x < n2) & kOwnLanes;
     w.xo = (uint32_t)(x < 0 ? 0 : (x >= n2 ? n2 - 1 : x));
     return w;
 }
 
 // One 3D workgroup brick (x-chunk xc, row block yb, plane block zb) for this wave.
-// `xw`: this wave's place among the waves of the brick (columns xw*62 ..).
+// `xw`: this wave's place among the waves of the brick.  Position columns and
+// rows start at -1 for the top filtration (the lattice point before voxel 0).
 template <int DT, int CONS, bool WIN, bool PAIR = false>
 __device__ __forceinline__ void run_brick_3d(const EccLaunch& L, const BinParams& P, const HistRef& H,
                                              int64_t chunk, uint32_t xc, uint32_t yb, uint32_t zb, int xw)
@@ -650,26 +746,26 @@ __device__ __forceinline__ void run_brick_3d(const EccLaunch& L, const BinParams
     yb = uniform_u32(yb);
     zb = uniform_u32(zb);
     constexpr int NR = kRows3;
+    constexpr int64_t org = CONS == CONS_TOP ? -1 : 0;
     using T = typename ValT<DT>::T;
     const int64_t n1 = L.g.n1, n2 = L.g.n2;
-    const WaveCols w = wave_cols((int64_t)xc * chunk, xw, n2);
+    const WaveCols w = wave_cols<WIN>(org + (int64_t)xc * chunk, xw, n2);
     if (!w.active) return;
     const uint32_t xob = w.xo * (uint32_t)sizeof(T);
-    const int64_t y0 = (int64_t)yb * NR;
-    const int rows_owned = (int)((n1 - y0) < NR ? (n1 - y0) : NR);
+    const int64_t ys = org + (int64_t)yb * NR;
     const uint32_t z0 = zb * (uint32_t)L.depth;
     const int64_t z_own = L.z_own;   // planes counted (the image's, or a slab's)
     const uint32_t zend = ((int64_t)z0 + L.depth < z_own) ? z0 + (uint32_t)L.depth : (uint32_t)z_own;
-    // rows r in [r_lo, r_hi) of the brick (row r is y0 - 1 + r) lie inside the image
-    const int r_lo = (y0 == 0) ? 1 : 0;
-    const int r_hi = (int)((n1 - (y0 - 1)) < NR + 2 ? (n1 - (y0 - 1)) : NR + 2);
-    const bool full = r_lo == 0 && r_hi == NR + 2;
+    // rows r in [r_lo, r_hi) of the brick (row r is ys + r) lie inside the image
+    const int r_lo = ys < 0 ? (int)(-ys) : 0;
+    const int r_hi = (int)((n1 - ys) < NR + 1 ? (n1 - ys) : NR + 1);
+    const bool full = r_lo == 0 && r_hi == NR + 1;
     if (DT != DT_F32 && uniform_flag(P.ident)) {
-        if (full) brick_3d<DT, CONS, WIN, true, true, PAIR>(L, P, H, y0, z0, zend, xob, w.oob, w.own_x, rows_owned, r_lo, r_hi);
-        else brick_3d<DT, CONS, WIN, false, true, PAIR>(L, P, H, y0, z0, zend, xob, w.oob, w.own_x, rows_owned, r_lo, r_hi);
+        if (full) brick_3d<DT, CONS, WIN, true, true, PAIR>(L, P, H, ys, z0, zend, xob, w.oob, w.own, r_lo, r_hi);
+        else brick_3d<DT, CONS, WIN, false, true, PAIR>(L, P, H, ys, z0, zend, xob, w.oob, w.own, r_lo, r_hi);
     } else {
-        if (full) brick_3d<DT, CONS, WIN, true, false, PAIR>(L, P, H, y0, z0, zend, xob, w.oob, w.own_x, rows_owned, r_lo, r_hi);
-        else brick_3d<DT, CONS, WIN, false, false, PAIR>(L, P, H, y0, z0, zend, xob, w.oob, w.own_x, rows_owned, r_lo, r_hi);
+        if (full) brick_3d<DT, CONS, WIN, true, false, PAIR>(L, P, H, ys, z0, zend, xob, w.oob, w.own, r_lo, r_hi);
+        else brick_3d<DT, CONS, WIN, false, false, PAIR>(L, P, H, ys, z0, zend, xob, w.oob, w.own, r_lo, r_hi);
     }
 }
 
@@ -680,15 +776,16 @@ __device__ __forceinline__ void run_brick_2d(const EccLaunch& L, const BinParams
 {
     xc = uniform_u32(xc);
     yb = uniform_u32(yb);
+    constexpr int64_t org = CONS == CONS_TOP ? -1 : 0;
     const int64_t n1 = L.g.n1, n2 = L.g.n2;
-    const WaveCols w = wave_cols((int64_t)xc * chunk, xw, n2);
+    const WaveCols w = wave_cols<WIN>(org + (int64_t)xc * chunk, xw, n2);
     if (!w.active) return;
     const uint32_t y0 = yb * (uint32_t)L.depth;
     const uint32_t yend = (int64_t)y0 + L.depth < n1 ? y0 + (uint32_t)L.depth : (uint32_t)n1;
     if (DT != DT_F32 && uniform_flag(P.ident))
-        brick_2d<DT, CONS, WIN, true>(L.data, (uint32_t)n1, n2, P, H, y0, yend, w.xo, w.oob, w.own_x);
+        brick_2d<DT, CONS, WIN, true>(L.data, (uint32_t)n1, n2, P, H, y0, yend, w.xo, w.oob, w.own);
     else
-        brick_2d<DT, CONS, WIN, false>(L.data, (uint32_t)n1, n2, P, H, y0, yend, w.xo, w.oob, w.own_x);
+        brick_2d<DT, CONS, WIN, false>(L.data, (uint32_t)n1, n2, P, H, y0, yend, w.xo, w.oob, w.own);
 }
 
 }  // namespace dev

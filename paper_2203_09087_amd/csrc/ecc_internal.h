@@ -41,22 +41,22 @@ struct Geom {
 // Histogram window: bins [bin_lo, bin_lo + width) are accumulated in LDS.
 constexpr int kMaxLdsBins = 4096;
 
-// Brick shapes of the wave kernels (64 x-lanes, 62 of them owned).  The
+// Brick shapes of the wave kernels (64 x-lanes, 63 of them owned).  The
 // ECC_* macros exist for tuning builds; the defaults are the shipped shapes.
 #ifndef ECC_ROWS3
-#define ECC_ROWS3 8
+#define ECC_ROWS3 3
 #endif
 #ifndef ECC_CHUNK2
 #define ECC_CHUNK2 16
 #endif
 #ifndef ECC_WAVES_PER_EU_3D
-#define ECC_WAVES_PER_EU_3D 7   // resident waves per SIMD the 3D kernels are compiled for
+#define ECC_WAVES_PER_EU_3D 5   // resident waves per SIMD the 3D kernels are compiled for
 #endif
 #ifndef ECC_WAVES_PER_EU_2D
 #define ECC_WAVES_PER_EU_2D 5   // resident waves per SIMD the 2D kernels are compiled for
 #endif
 #ifndef ECC_MAX_WAVES_3D
-#define ECC_MAX_WAVES_3D 9   // waves per workgroup of a single 3D image (a whole row up to 558 columns)
+#define ECC_MAX_WAVES_3D 9   // waves per workgroup of a single 3D image (a whole row up to 567 positions)
 #endif
 #ifndef ECC_MAX_WGS_PER_CU_3D
 #define ECC_MAX_WGS_PER_CU_3D 2   // resident workgroups per CU a single 3D image launches
@@ -66,10 +66,30 @@ constexpr int kMaxLdsBins = 4096;
 #endif
 // A key is 4 * bin: the LDS byte address of its counter.
 constexpr int kKeyShift = 2;
-constexpr int kLdsWords = kMaxLdsBins + 64;   // counters, then one spare word per lane
+// A workgroup histogram is kept in two copies, one for the even and one for the
+// odd lanes of every wave: equal keys of neighbouring lanes (frequent in smooth
+// images) then fall into different copies, and the second copy starts 8 words
+// further in the bank cycle, so they do not collide in one LDS bank.  The merge
+// adds the copies.
+constexpr int kHistCopies = 2;
+constexpr int kCopyWords = kMaxLdsBins + 8;   // stride of the copies, in words
+// LDS words of a workgroup histogram: each copy's counters, then spare words up
+// to the copy's one-window sentinel word (byte 0x7FFC of the copy), which absorbs
+// the counts of cells that do not exist.
+constexpr int kLdsWords = kCopyWords * (kHistCopies - 1) + 8192;
+// Positions a wave owns along x (lanes 0..62; lane 63 only supplies lane 62's
+// right neighbour).
+constexpr int kLaneCols = 63;
+// Positions along an axis of n voxels that carry a single or a pair (the cell
+// types of the kernels): n for the vertex filtration; n + 1 lattice points for
+// the top filtration (the first one before voxel 0).
+inline __host__ __device__ int64_t axis_positions(int64_t n, int construction)
+{
+    return n + (construction == CONS_TOP ? 1 : 0);
+}
 constexpr int kRows3 = ECC_ROWS3;      // rows per 3D brick
 constexpr int kChunk2 = ECC_CHUNK2;    // rows loaded together in the 2D kernel
-// Waves per workgroup of the main kernels (x-chunk = waves * 62 columns).
+// Waves per workgroup of the main kernels (x-chunk = waves * 63 position columns).
 constexpr int kMaxWaves = 9;
 
 struct EccLaunch {
@@ -82,7 +102,7 @@ struct EccLaunch {
     int32_t bin_lo, width;
     int32_t windowed;              // nbins > width: skip bins outside the window
     int32_t grid;                  // number of workgroups
-    int32_t waves;                 // waves per workgroup (x-chunk = 62 * waves columns)
+    int32_t waves;                 // waves per workgroup (x-chunk = 63 * waves position columns)
     int64_t depth;                 // planes (3D) or rows (2D) per workgroup brick
     // 3D slab of a larger volume (streaming): planes [0, z_own) of the g.n0 in
     // memory are counted (a plane beyond them is the collar the last one needs);
@@ -104,7 +124,7 @@ struct BatchImage {
     Geom g;
     int32_t ndim, dtype;
     int32_t auto_range;   // parameters come from the min/max keys mm[2*i], mm[2*i+1]
-    int32_t nxc;          // x-chunks of 62 * wpb columns
+    int32_t nxc;          // x-chunks of 63 * wpb position columns
     int32_t nyb;          // row blocks (3D: kRows3 rows; 2D: `depth` rows)
     int32_t wpb;          // waves per brick; a workgroup works on kBatchWaves / wpb bricks side by side
     int64_t depth;        // planes (3D) or rows (2D) per brick
@@ -153,8 +173,8 @@ hipError_t launch_mm_init(uint32_t* mm, int count, hipStream_t s);
 // `scan`, prefix-sums its out[0 .. nbins).
 hipError_t launch_merge_batch(const BatchLaunch& B, bool scan, hipStream_t s);
 // Bricks of one batch image for the batched launch shape (sets nxc, nyb, depth):
-// 3D bricks of depth3 planes, 2D bricks of depth2 rows.
-int64_t batch_bricks(BatchImage& im, int waves, int depth3, int depth2);
+// 3D bricks of depth3 planes, 2D bricks of depth2 rows (a multiple of kChunk2).
+int64_t batch_bricks(BatchImage& im, int construction, int waves, int depth3, int depth2);
 // Voxels of one brick of a batch image whose shape batch_bricks has set (whole
 // brick, including any part outside the image).
 int64_t batch_brick_voxels(const BatchImage& im);
@@ -195,7 +215,7 @@ hipError_t launch_merge(const int32_t* partials, int rows, int32_t width, int32_
 hipError_t launch_mm_fold(const uint32_t* mm, int blocks, uint32_t* acc, bool first, hipStream_t s);
 
 // Workgroup bricks of an image for a launch shape.
-int64_t wg_bricks(int ndim, const Geom& g, int waves, int64_t depth);
+int64_t wg_bricks(int ndim, int construction, const Geom& g, int waves, int64_t depth);
 // Workgroups of the main kernel variant (of `waves` waves) that fit on one CU.
 int resident_wgs_per_cu(int ndim, int dtype, int construction, bool windowed, int waves);
 

@@ -11,7 +11,7 @@ namespace {
 using namespace dev;
 
 // 3D images.  A workgroup brick is a contiguous x-chunk (the workgroup's waves
-// side by side, each 64 lanes wide with 62 owned) x kRows3 rows x L.depth planes.
+// side by side, each 64 lanes wide with 63 owned) x kRows3 rows x L.depth planes.
 // All waves of a workgroup read the same rows at about the same time, so every
 // plane step of a workgroup reads whole row segments of memory.
 template <int DT, int CONS, bool WIN, bool PAIR>
@@ -21,9 +21,9 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
     const BinParams P = L.params_dev ? *L.params_dev : L.params;
     const HistRef H = hist_ref(hist, L.bin_lo, L.width);
     zero_hist(hist, L.width);
-    const int64_t chunk = (int64_t)(blockDim.x >> 6) * 62;
-    const uint32_t nxc = (uint32_t)((L.g.n2 + chunk - 1) / chunk);
-    const uint32_t nyb = (uint32_t)((L.g.n1 + kRows3 - 1) / kRows3);
+    const int64_t chunk = (int64_t)(blockDim.x >> 6) * kLaneCols;
+    const uint32_t nxc = (uint32_t)((axis_positions(L.g.n2, CONS) + chunk - 1) / chunk);
+    const uint32_t nyb = (uint32_t)((axis_positions(L.g.n1, CONS) + kRows3 - 1) / kRows3);
     const uint32_t nzb = (uint32_t)((L.z_own + L.depth - 1) / L.depth);
     const uint32_t nbricks = nxc * nyb * nzb;
     for (uint32_t brick = blockIdx.x; brick < nbricks; brick += gridDim.x)
@@ -40,8 +40,8 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
     const BinParams P = L.params_dev ? *L.params_dev : L.params;
     const HistRef H = hist_ref(hist, L.bin_lo, L.width);
     zero_hist(hist, L.width);
-    const int64_t chunk = (int64_t)(blockDim.x >> 6) * 62;
-    const uint32_t nxc = (uint32_t)((L.g.n2 + chunk - 1) / chunk);
+    const int64_t chunk = (int64_t)(blockDim.x >> 6) * kLaneCols;
+    const uint32_t nxc = (uint32_t)((axis_positions(L.g.n2, CONS) + chunk - 1) / chunk);
     const uint32_t nyb = (uint32_t)((L.g.n1 + L.depth - 1) / L.depth);
     const uint32_t nbricks = nxc * nyb;
     for (uint32_t brick = blockIdx.x; brick < nbricks; brick += gridDim.x)
@@ -54,12 +54,12 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
 // ----------------------------------------------------------------- launchers
 
 
-int64_t wg_bricks(int ndim, const Geom& g, int waves, int64_t depth)
+int64_t wg_bricks(int ndim, int construction, const Geom& g, int waves, int64_t depth)
 {
-    const int64_t chunk = (int64_t)waves * 62;
-    const int64_t nxc = (g.n2 + chunk - 1) / chunk;
+    const int64_t chunk = (int64_t)waves * kLaneCols;
+    const int64_t nxc = (axis_positions(g.n2, construction) + chunk - 1) / chunk;
     if (ndim == 2) return nxc * ((g.n1 + depth - 1) / depth);
-    return nxc * ((g.n1 + kRows3 - 1) / kRows3) * ((g.n0 + depth - 1) / depth);
+    return nxc * ((axis_positions(g.n1, construction) + kRows3 - 1) / kRows3) * ((g.n0 + depth - 1) / depth);
 }
 
 template <int NDIM, int DT, int CONS, bool WIN>

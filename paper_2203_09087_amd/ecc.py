@@ -127,7 +127,7 @@ def load_library(path: str = LIB_PATH):
     fltp = ctypes.POINTER(ctypes.c_float)
     lib.ecc_smooth13.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_int64, fltp, vp]
     lib.ecc_smooth13.restype = ctypes.c_int
-    lib.ecc_batch_schedule.argtypes = [ctypes.POINTER(ecc_image), i32, i32, ctypes.POINTER(ecc_batch_shape), i32,
+    lib.ecc_batch_schedule.argtypes = [ctypes.POINTER(ecc_image), i32, i32, i32, ctypes.POINTER(ecc_batch_shape), i32,
                                        ctypes.POINTER(i32), i64p, i64p, i64p]
     lib.ecc_batch_schedule.restype = ctypes.c_int
     _lib = lib
@@ -205,14 +205,15 @@ def ecc_batch_plan_destroy(plan: int) -> int:
     return load_library().ecc_batch_plan_destroy(plan)
 
 
-def ecc_batch_schedule(imgs, nbins: int, shape=None, cu_count: int = 256):
+def ecc_batch_schedule(imgs, nbins: int, shape=None, cu_count: int = 256, construction: int = ECC_VERTEX):
     """Host-only split of a batch (no device needed): (status, segments,
     max_segment_voxels, image_bricks list, covered_bricks list)."""
     ptr, keep, n = _descriptor_array(imgs)
     segs, mx = ctypes.c_int32(), ctypes.c_int64()
     ib, cb = (ctypes.c_int64 * max(1, n))(), (ctypes.c_int64 * max(1, n))()
     sh = ctypes.byref(shape) if shape is not None else None
-    st = load_library().ecc_batch_schedule(ptr, n, int(nbins), sh, int(cu_count), ctypes.byref(segs),
+    st = load_library().ecc_batch_schedule(ptr, n, int(nbins), int(construction), sh, int(cu_count),
+                                           ctypes.byref(segs),
                                            ctypes.byref(mx), ib, cb)
     return st, segs.value, mx.value, list(ib)[:n], list(cb)[:n]
 

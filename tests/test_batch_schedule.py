@@ -1,9 +1,8 @@
 """Host-side checks of how a batch is split over workgroups (no GPU needed).
 
 Each segment of a batch is counted into one int32 workgroup histogram and one
-int32 partial row (the block-shared counters of Sec. 4.3).  A voxel adds at most
-3 in absolute value per 2D problem and a 3D voxel takes part in two, so a segment
-must cover at most 2^27 voxels.  The schedule is computed by the library's own
+int32 partial row (the block-shared counters of Sec. 4.3).  A voxel position adds
+at most 8 in absolute value, so a segment must cover at most 2^27 voxels.  The schedule is computed by the library's own
 host code through ``ecc_batch_schedule``; the descriptors point nowhere (the
 diagnostic reads no image memory).
 """
@@ -53,13 +52,29 @@ def test_one_large_image_is_cut_below_the_counter_bound(wgs, shape3, cus):
         assert segs > cus * wgs   # runs were split
 
 
-def test_large_2d_image_and_a_mix():
+@pytest.mark.parametrize("cons", [ecc.ECC_VERTEX, ecc.ECC_TOP])
+def test_large_2d_image_and_a_mix(cons):
     imgs = [_img((40000, 40000), ecc.ECC_U16), _img((64, 64)), _img((300, 200, 100), ecc.ECC_F32), _img((7, 9))]
     for wgs in (1, 3):
         shape = ecc.ecc_batch_shape(8, 128, wgs, 0, 0.0)
-        st, segs, mx, ib, cb = ecc.ecc_batch_schedule(imgs, 4096, shape, cu_count=256)
+        st, segs, mx, ib, cb = ecc.ecc_batch_schedule(imgs, 4096, shape, cu_count=256, construction=cons)
         assert st == ecc.ECC_OK, ecc.ecc_last_error(None)
         assert mx <= CAP and ib == cb and all(b > 0 for b in ib)
+
+
+def test_top_filtration_counts_the_extra_lattice_points():
+    # the top filtration has one more position per type axis (the lattice point
+    # before voxel 0): 24 rows (a whole number of row blocks) need one row block
+    # more there
+    im = [_img((2, 24, 10))]
+    shape = ecc.ecc_batch_shape(8, 16, 1, 0, 0.0)
+    _, _, _, ib_v, _ = ecc.ecc_batch_schedule(im, 256, shape, construction=ecc.ECC_VERTEX)
+    _, _, _, ib_t, _ = ecc.ecc_batch_schedule(im, 256, shape, construction=ecc.ECC_TOP)
+    assert ib_t[0] == ib_v[0] + 1
+
+
+def test_schedule_rejects_an_unknown_construction():
+    assert ecc.ecc_batch_schedule([_img((5, 5))], 256, construction=7)[0] == ecc.ECC_ERR_INVALID_ARG
 
 
 def test_small_batches_keep_one_segment_per_image_per_workgroup():

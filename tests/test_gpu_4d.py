@@ -36,13 +36,13 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def check(ctx, oracle_mod, img, nbins, cons, rng=None):
+def check(ctx, oracle_mod, img, nbins, cons, rng=None, threads=8):
     print(f"case: 4d {cons} shape={img.shape} dtype={img.dtype} nbins={nbins} range={rng}", flush=True,
           file=sys.stderr)
     got = ctx.compute(to_dev(img), nbins, value_range=rng)
     torch.cuda.synchronize()
     got = got.cpu().numpy()
-    want = oracle_mod.ecc(img, nbins, cons, value_range=rng, threads=8)
+    want = oracle_mod.ecc(img, nbins, cons, value_range=rng, threads=threads)
     if not np.array_equal(got, want):
         bad = np.nonzero(got != want)[0]
         raise AssertionError(f"{cons} {img.shape} {img.dtype} nbins={nbins} range={rng}: "
@@ -102,6 +102,15 @@ def test_4d_larger_image(ctxs, oracle_mod, cons):
     from paper_2203_09087_amd import synth
     field = synth.grf((16, 32, 64, 128), seed=97)
     check(ctxs[cons], oracle_mod, field, 4096, cons, rng="auto")
+
+
+@pytest.mark.parametrize("cons", CONS)
+def test_4d_benchmark_field(ctxs, oracle_mod, cons):
+    """The 4D workload the benchmark times: an 8 x 256^3 float32 GRF (k^-3 in four
+    dimensions, seed 9), 4096 bins over its [min, max]."""
+    from paper_2203_09087_amd import synth
+    field = synth.grf((8, 256, 256, 256), seed=9)
+    check(ctxs[cons], oracle_mod, field, 4096, cons, rng=(float(field.min()), float(field.max())), threads=16)
 
 
 def test_4d_is_rejected_where_unsupported(ctxs):

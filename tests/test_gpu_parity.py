@@ -151,15 +151,45 @@ def test_workload_grf_512_cubed(ctxs, oracle_mod, grf3d, cons):
     """512^3 float32 GRF (k^-3), 4096 bins over [min, max], explicit and AUTO."""
     lo, hi = float(grf3d.min()), float(grf3d.max())
     check(ctxs[cons], oracle_mod, grf3d, 4096, cons, rng=(lo, hi), threads=16)
-    if cons == "vertex":
-        check(ctxs[cons], oracle_mod, grf3d, 4096, cons, rng="auto", threads=16)
+    check(ctxs[cons], oracle_mod, grf3d, 4096, cons, rng="auto", threads=16)
 
 
-def test_workload_grf_16384_squared(ctxs, oracle_mod):
-    """16384^2 uint16 GRF quantized to 4096 levels, 4096 bins over [min, max]."""
+@pytest.fixture(scope="module")
+def grf2d_u16():
     from paper_2203_09087_amd import synth
-    img = synth.quantize_u16(synth.grf((16384, 16384), seed=4), 4096)
-    check(ctxs["vertex"], oracle_mod, img, 4096, "vertex", rng="auto", threads=16)
+    return synth.quantize_u16(synth.grf((16384, 16384), seed=4), 4096)
+
+
+@pytest.mark.parametrize("cons", CONS)
+def test_workload_grf_16384_squared(ctxs, oracle_mod, grf2d_u16, cons):
+    """16384^2 uint16 GRF quantized to 4096 levels, 4096 bins over [min, max]
+    (AUTO), and over the explicit range [0, 4095]."""
+    check(ctxs[cons], oracle_mod, grf2d_u16, 4096, cons, rng="auto", threads=16)
+    check(ctxs[cons], oracle_mod, grf2d_u16, 4096, cons, rng=(0, 4095), threads=16)
+
+
+@pytest.mark.parametrize("cons", CONS)
+def test_compute_entry_point(ctxs, oracle_mod, cons):
+    """ecc_compute itself (default range: [0, 255] for u8, AUTO otherwise), called
+    through the C ABI on a 2D u8, a 3D u16 and a 4D f32 image."""
+    from paper_2203_09087_amd import ecc, synth
+    rng = np.random.default_rng(321 if cons == "vertex" else 322)
+    cases = [
+        (synth.uniform_u8((300, 517), seed=13), ecc.ECC_U8, 256),
+        (rng.integers(0, 3000, size=(37, 70, 129)).astype(np.uint16), ecc.ECC_U16, 4096),
+        (synth.grf((5, 20, 33, 70), seed=14), ecc.ECC_F32, 1000),
+    ]
+    for img, code, nbins in cases:
+        say(f"case: ecc_compute {cons} {img.shape} {img.dtype} nbins={nbins}")
+        dev = to_dev(img)
+        out = torch.full((nbins,), -5, dtype=torch.int64, device="cuda")
+        st = ecc.ecc_compute(ctxs[cons].handle, dev.data_ptr(), img.ndim, img.shape, code, nbins, out.data_ptr(), 0)
+        assert st == ecc.ECC_OK, ecc.ecc_last_error(ctxs[cons].handle)
+        torch.cuda.synchronize()
+        rng_mode = None if code == ecc.ECC_U8 else "auto"
+        want = oracle_mod.ecc(img, nbins, cons, value_range=rng_mode, threads=8)
+        got = out.cpu().numpy()
+        assert np.array_equal(got, want), (img.shape, np.nonzero(got != want)[0][:5])
 
 
 @pytest.mark.parametrize("cons", CONS)
