@@ -13,6 +13,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-side
 from __future__ import annotations
 
 import argparse
+import collections
 import json
 import os
 import sys
@@ -49,6 +50,40 @@ def timed_calls(fn, stream, steps, warmup):
     return [s.elapsed_time(e) for s, e in zip(starts, ends)], wall
 
 
+COPY_BYTES = 512 << 20
+# The workloads the counter passes profile: the kernel whose dispatches are read,
+# how many dispatches one call makes, and the launch shape pinned for it (under
+# the counter profiler the tuner's timings are distorted and it would pick
+# another; these are the shapes the timed runs use).
+PROFILES = {
+    "3d": {"kernel": "k_ecc_3d", "file": "k_ecc_3d_f32_512cubed", "per_call": 1,
+           "what": "512^3 float32 GRF (seed 3), vertex filtration, 4096 bins over [min, max]",
+           "shape": {"waves": 9, "wgs_per_cu": 3, "depth": 32}},
+    "2d": {"kernel": "k_ecc_2d", "file": "k_ecc_2d_u16_16384sq", "per_call": 1,
+           "what": "16384^2 uint16 GRF (seed 4, 4096 levels), vertex filtration, 4096 bins over [min, max]",
+           "shape": {"waves": 4, "wgs_per_cu": 4, "depth": 256}},
+    "batch": {"kernel": "k_ecc_batch", "file": "k_ecc_batch_u8_512images", "per_call": 1,
+              "what": "the uneven 512-image uint8 batch (seed 5), vertex filtration, 256 bins, default batch shape",
+              "shape": None},
+    "4d": {"kernel": "k_ecc_3d<2, 0, false, true>", "file": "k_ecc_3d_pair_f32_8x256cubed", "per_call": 7,
+           "what": "the 7 pair passes (elementwise max of two neighbouring 256^3 hyperplanes) of one call on the "
+                   "8 x 256^3 float32 GRF (seed 9), vertex filtration, 4096 bins over [min, max]",
+           "shape": None},
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", PROFILES["3d"]["file"] + "_traffic.txt")
+TRAFFIC_SHAPE = PROFILES["3d"]["shape"]
+
+
+def kernel_sources_sha256():
+    """Hash of the sources the histogram kernels are compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2203_09087_amd", "csrc")
+    for name in ("ecc_internal.h", "ecc_device.h", "ecc_kernels.hip", "ecc_batch.hip"):
+        h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()
+
+
 def traffic_bytes():
     """HBM bytes per launch of the histogram kernel on the 512^3 f32 step, from the
     committed rocprofv3 counter summary, if it was taken from the current kernel
@@ -63,125 +98,154 @@ def traffic_bytes():
     if fields.get("kernel_sources_sha256") != kernel_sources_sha256():
         return None
     try:
-        return int(fields["hbm_bytes_per_launch"])
+        return int(fields["hbm_bytes_per_call"])
     except (KeyError, ValueError):
         return None
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ecc_3d_f32_512cubed_traffic.txt")
-COPY_BYTES = 512 << 20
-TRAFFIC_SHAPE = {"waves": 9, "wgs_per_cu": 4, "depth": 64}
-
-
-def kernel_sources_sha256():
-    """Hash of the sources the histogram kernel is compiled from."""
-    import hashlib
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2203_09087_amd", "csrc")
-    for name in ("ecc_internal.h", "ecc_device.h", "ecc_kernels.hip"):
-        h.update(open(os.path.join(csrc, name), "rb").read())
-    return h.hexdigest()
-
-
-def traffic_run():
-    """The program the counter passes profile: three plain copies of a 512 MiB
-    buffer (the calibration kernel, known bytes) and three steps of the 512^3 f32
-    ECC."""
+def profile_input(which):
+    """(run, algorithmic bytes per call) for a profiled workload: run() makes one call."""
     import torch
     from paper_2203_09087_amd import ecc, synth
     dev = torch.device("cuda", 0)
-    vol = synth.grf((512, 512, 512), seed=3)
-    lo, hi = float(vol.min()), float(vol.max())
-    vol_d = torch.from_numpy(vol).to(dev)
+    spec = PROFILES[which]
+    ctx = ecc.Context(0, "vertex")
+    if which == "batch":
+        imgs = [torch.from_numpy(a).to(dev) for a in synth.batch_images(count=512, seed=5)]
+        outs = [torch.empty(256, dtype=torch.int64, device=dev) for _ in imgs]
+        return ctx, (lambda: ctx.compute_batch(imgs, 256, outs=outs)), int(sum(t.numel() for t in imgs))
+    if which == "3d":
+        a = synth.grf((512, 512, 512), seed=3)
+        rng = (float(a.min()), float(a.max()))
+        t = torch.from_numpy(a).to(dev)
+    elif which == "2d":
+        a = synth.quantize_u16(synth.grf((16384, 16384), seed=4), 4096)
+        rng = (int(a.min()), int(a.max()))
+        t = torch.from_numpy(a.view(np.int16)).to(dev)
+    else:
+        a = synth.grf((8, 256, 256, 256), seed=9)
+        rng = (float(a.min()), float(a.max()))
+        t = torch.from_numpy(a).to(dev)
+    out = torch.empty(4096, dtype=torch.int64, device=dev)
+    if spec["shape"]:
+        ctx.set_launch_shape(t, 4096, **spec["shape"])
+    return ctx, (lambda: ctx.compute(t, 4096, value_range=rng, out=out)), int(a.nbytes)
+
+
+def traffic_run(which="3d"):
+    """The program the counter passes profile: three plain copies of a 512 MiB
+    buffer (the calibration kernel, known bytes) and three calls of a workload
+    (PROFILES)."""
+    import torch
+    dev = torch.device("cuda", 0)
+    ctx, run, alg = profile_input(which)
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
     b = torch.empty_like(a)
     for _ in range(3):
         b.copy_(a)
-    ctx = ecc.Context(0, "vertex")
-    out = torch.empty(4096, dtype=torch.int64, device=dev)
-    # the launch shape the benchmark's tuner picks on this volume, pinned: under
-    # the counter profiler the tuner's timings are distorted and it would pick
-    # another (the summary reads the last three dispatches of the histogram kernel)
-    ctx.set_launch_shape(vol_d, 4096, **TRAFFIC_SHAPE)
-    log(f"traffic run shape {TRAFFIC_SHAPE}")
+    log(f"profile run {which}: {alg} algorithmic bytes per call, shape {PROFILES[which]['shape']}")
     for _ in range(3):
-        ctx.compute(vol_d, 4096, value_range=(lo, hi), out=out)
+        run()
     torch.cuda.synchronize()
     ctx.close()
-    log("traffic run done")
+    log("profile run done")
 
 
-def write_traffic(fetch_csv, write_csv):
-    """Turns the FETCH_SIZE and WRITE_SIZE passes over traffic_run() into the
-    summary that traffic_bytes() reads.  Each counter is scaled by the bytes the
-    copy kernel is known to move over what the counter reads for it."""
+def _dispatch_values(path, counter=None, kernel=None):
+    """{kernel name: [per-dispatch value in dispatch order]} for one counter (rows of
+    one dispatch summed), or for every counter when counter is None."""
     import csv
+    per = {}
+    for r in csv.DictReader(open(path)):
+        if counter and r["Counter_Name"] != counter:
+            continue
+        if kernel and kernel not in r["Kernel_Name"]:
+            continue
+        key = (int(r["Dispatch_Id"]), r["Kernel_Name"], r["Counter_Name"])
+        per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    out = {}
+    for (_, name, cn), v in sorted(per.items()):
+        out.setdefault((name, cn), []).append(v)
+    return out
 
-    def per_kernel(path, counter):
-        # one value per dispatch (rows of one dispatch summed), in dispatch order
-        per = {}
-        for r in csv.DictReader(open(path)):
-            if r["Counter_Name"] == counter:
-                key = (int(r["Dispatch_Id"]), r["Kernel_Name"])
-                per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
-        vals = {}
-        for (_, name), v in sorted(per.items()):
-            vals.setdefault(name, []).append(v)
-        return vals
 
-    f, w = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
-    # launch shape of the histogram kernel's last dispatch in the FETCH pass (the
-    # tuner of that run picked it; the halo re-reads depend on it)
-    grids = [(int(r["Dispatch_Id"]), int(r["Grid_Size"]), int(r["Workgroup_Size"]))
-             for r in csv.DictReader(open(fetch_csv)) if "k_ecc_3d" in r["Kernel_Name"]]
-    _, grid_items, wg_items = max(grids) if grids else (0, 0, 1)
-    # the histogram kernel's last three dispatches are the timed launch shape
-    for vals in (f, w):
-        for k in vals:
-            if "k_ecc_3d" in k:
-                vals[k] = vals[k][-3:]
-    copy = [k for k in f if "copy" in k.lower()]
-    ecck = [k for k in f if "k_ecc_3d" in k]
-    if not copy or not ecck:
+def write_traffic(which, fetch_csv, write_csv):
+    """Turns the FETCH_SIZE and WRITE_SIZE passes over traffic_run(which) into the
+    profile summary (traffic_bytes() reads the 3D one).  Each counter is scaled by
+    the bytes the copy kernel is known to move over what the counter reads for it."""
+    spec = PROFILES[which]
+    f = _dispatch_values(fetch_csv, "FETCH_SIZE")
+    w = _dispatch_values(write_csv, "WRITE_SIZE")
+    copy = [k for k in f if "copy" in k[0].lower()]
+    main = [k for k in f if spec["kernel"] in k[0]]
+    if not copy or not main:
         raise SystemExit(f"copy or histogram kernel not found in {sorted(f)}")
     copy = max(copy, key=lambda k: np.mean(f[k]))
-    ecck = ecck[0]
-    cf, cw = float(np.mean(f[copy])), float(np.mean(w[copy]))
-    ef, ew = float(np.mean(f[ecck])), float(np.mean(w[ecck]))
+    cf = float(np.mean(f[copy]))
+    cw = float(np.mean(w[(copy[0], "WRITE_SIZE")]))
     fs, ws = COPY_BYTES / (cf * 1024), COPY_BYTES / (cw * 1024)
+    n = spec["per_call"]
+    # every variant of the histogram kernel in dispatch order; the last call's
+    # dispatches (per_call of them) are summed, averaged over the three calls
+    disp_f = sorted(v for k in main for v in zip(_dispatch_ids(fetch_csv, k[0]), f[k]))
+    disp_w = sorted(v for k in [(m[0], "WRITE_SIZE") for m in main] if k in w
+                    for v in zip(_dispatch_ids(write_csv, k[0]), w[k]))
+    calls_f = [sum(x for _, x in disp_f[i:i + n]) for i in range(len(disp_f) - 3 * n, len(disp_f), n)]
+    calls_w = [sum(x for _, x in disp_w[i:i + n]) for i in range(len(disp_w) - 3 * n, len(disp_w), n)]
+    ef, ew = float(np.mean(calls_f)), float(np.mean(calls_w))
     hf, hw = ef * 1024 * fs, ew * 1024 * ws
+    alg = _alg_bytes(which)
     lines = [
-        "# HBM traffic per launch of the histogram kernel, 512^3 float32 GRF (seed 3),",
-        "# vertex filtration, 4096 bins over [min, max]; counters in KiB per dispatch.",
-        "command_fetch: cd /tmp && timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv "
-        "-d $REPO/gpurun_out/pmc_fetch -o run -- python3 $REPO/bench.py --traffic",
-        "command_write: cd /tmp && timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv "
-        "-d $REPO/gpurun_out/pmc_write -o run -- python3 $REPO/bench.py --traffic",
-        f"command_summary: python3 bench.py --write-traffic {fetch_csv} {write_csv}",
-        f"calibration_kernel: {copy}",
+        f"# HBM traffic per call of the histogram kernel ({spec['kernel']}, {n} dispatch(es) per call):",
+        f"# {spec['what']}; counters in KiB per dispatch.",
+        f"command_fetch: cd /tmp && timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv "
+        f"-d $REPO/gpurun_out/pmc_fetch_{which} -o run -- python3 $REPO/bench.py --traffic {which}",
+        f"command_write: cd /tmp && timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv "
+        f"-d $REPO/gpurun_out/pmc_write_{which} -o run -- python3 $REPO/bench.py --traffic {which}",
+        f"command_summary: python3 bench.py --write-traffic {which} FETCH_CSV WRITE_CSV",
+        f"launch_shape: {spec['shape'] or 'default'}",
+        f"calibration_kernel: {copy[0]}",
         f"calibration_bytes: {COPY_BYTES} read and {COPY_BYTES} written per dispatch",
-        f"copy_fetch_kib: {cf:.1f} (mean of {len(f[copy])})",
-        f"copy_write_kib: {cw:.1f} (mean of {len(w[copy])})",
+        f"copy_fetch_kib: {cf:.1f}",
+        f"copy_write_kib: {cw:.1f}",
         f"fetch_scale: {fs:.4f}",
         f"write_scale: {ws:.4f}",
-        f"histogram_kernel: {ecck}",
-        f"ecc_fetch_kib: {ef:.1f} (mean of {len(f[ecck])})",
-        f"ecc_write_kib: {ew:.1f} (mean of {len(w[ecck])})",
-        f"histogram_launch: {grid_items // max(wg_items, 1)} workgroups of {wg_items} work-items",
-        f"hbm_fetch_bytes_per_launch: {int(round(hf))}",
-        f"hbm_write_bytes_per_launch: {int(round(hw))}",
-        f"hbm_bytes_per_launch: {int(round(hf + hw))}",
-        f"algorithmic_bytes_per_launch: {512 ** 3 * 4}",
+        f"histogram_fetch_kib_per_call: {ef:.1f} (mean of the last 3 calls)",
+        f"histogram_write_kib_per_call: {ew:.1f}",
+        f"hbm_fetch_bytes_per_call: {int(round(hf))}",
+        f"hbm_write_bytes_per_call: {int(round(hw))}",
+        f"hbm_bytes_per_call: {int(round(hf + hw))}",
+        f"algorithmic_bytes_per_call: {alg}",
+        f"traffic_over_algorithmic: {(hf + hw) / alg:.3f}",
         f"kernel_sources_sha256: {kernel_sources_sha256()}",
     ]
-    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
-    with open(TRAFFIC_FILE, "w") as fh:
+    path = os.path.join(ROOT, "profiles", spec["file"] + "_traffic.txt")
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
 
+def _dispatch_ids(path, kernel_name):
+    """Dispatch ids of one kernel (one per dispatch, in order)."""
+    import csv
+    ids = sorted({int(r["Dispatch_Id"]) for r in csv.DictReader(open(path)) if r["Kernel_Name"] == kernel_name})
+    return ids
+
+
+def _alg_bytes(which):
+    """Algorithmic bytes of one call (each voxel read once)."""
+    if which == "3d":
+        return 512 ** 3 * 4
+    if which == "2d":
+        return 16384 ** 2 * 2
+    if which == "4d":
+        return 7 * 2 * 256 ** 3 * 4   # each pair pass reads two hyperplanes
+    from paper_2203_09087_amd import synth
+    return int(sum(int(np.prod(s)) for s in synth.batch_shapes(count=512, seed=5)))
+
+
 TRACE_FILE = os.path.join(ROOT, "profiles", "k_ecc_3d_f32_512cubed_trace.md")
-SQ_FILE = os.path.join(ROOT, "profiles", "k_ecc_3d_f32_512cubed_sq.md")
 MAIN_KERNEL = "k_ecc_3d<2, 0, false, false>"
 
 
@@ -224,55 +288,74 @@ def write_trace_summary(db_path, bench_json):
     print("\n".join(out))
 
 
-def write_sq_summary(csv_a, csv_b):
-    """Summarizes two SQ counter passes over `bench.py --traffic` (the last three
-    dispatches of the histogram kernel, the timed launch shape) into the
-    profiles folder, with the issue-rate figures derived from them."""
+SQ_A = ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_INST_ANY "
+        "SQ_ACTIVE_INST_VALU")
+SQ_B = ("SQ_LDS_IDX_ACTIVE SQ_LDS_BANK_CONFLICT SQ_WAIT_INST_LDS SQ_INSTS_VMEM SQ_ACTIVE_INST_LDS GRBM_GUI_ACTIVE "
+        "SQ_WAIT_ANY SQ_ACTIVE_INST_MISC")
+
+
+def write_sq_summary(which, csv_a, csv_b):
+    """Summarizes two SQ counter passes over `bench.py --traffic which` (the last
+    call's dispatches of the histogram kernel, at the pinned launch shape) into the
+    profiles folder, with the issue and LDS figures derived from them."""
+    spec = PROFILES[which]
+    n = spec["per_call"]
+    meta = {}
     import csv
-    vals, meta = {}, {}
+    passes = []
     for path in (csv_a, csv_b):
         per = {}
         for r in csv.DictReader(open(path)):
-            if MAIN_KERNEL not in r["Kernel_Name"]:
+            if spec["kernel"] not in r["Kernel_Name"]:
                 continue
             key = (int(r["Dispatch_Id"]), r["Counter_Name"])
             per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
             meta = {k: r[k] for k in ("Grid_Size", "Workgroup_Size", "LDS_Block_Size", "Scratch_Size")}
-        ids = sorted({d for d, _ in per})[-3:]
+        ids = sorted({d for d, _ in per})[-3 * n:]
+        vals = {}
         for (d, c), v in per.items():
             if d in ids:
-                vals.setdefault(c, []).append(v)
-    m = {c: float(np.mean(v)) for c, v in vals.items()}
-    simds, xcds = 1024, 8
+                vals[c] = vals.get(c, 0.0) + v
+        # per call: the call's dispatches summed, the mean over the three calls
+        passes.append({c: v / 3.0 for c, v in vals.items()})
+    # a counter taken in both passes (GRBM_GUI_ACTIVE): the mean of the two
+    m = collections.defaultdict(lambda: float("nan"))
+    for c in set(passes[0]) | set(passes[1]):
+        m[c] = float(np.mean([p[c] for p in passes if c in p]))
+    simds, xcds, cus = 1024, 8, 256
     cyc = m["GRBM_GUI_ACTIVE"] / xcds
-    row_steps = 2 * 512 ** 3 / 62
     slots = cyc / 4
-    out = [f"# SQ counters: `{MAIN_KERNEL}`, 512^3 float32 GRF, vertex, 4096 bins", "",
+    alg = _alg_bytes(which)
+    esize = {"3d": 4, "2d": 2, "4d": 4, "batch": 1}[which]
+    kvox = alg / esize / 1000.0
+    out = [f"# SQ counters: `{spec['kernel']}`, {spec['what']}", "",
            "Commands (one pass each, from /tmp, $REPO the repository root):", "",
-           "    timeout -s KILL 120 rocprofv3 --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_WAVE_CYCLES "
-           "SQ_BUSY_CYCLES SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU --output-format csv -d $REPO/gpurun_out/sqa -o run "
-           "-- python3 $REPO/bench.py --traffic",
-           "    timeout -s KILL 120 rocprofv3 --pmc SQ_INST_CYCLES_SALU SQ_ACTIVE_INST_LDS SQ_LDS_BANK_CONFLICT "
-           "SQ_WAIT_ANY SQ_INSTS_VMEM SQ_ACTIVE_INST_ANY GRBM_GUI_ACTIVE SQ_ACTIVE_INST_MISC --output-format csv "
-           "-d $REPO/gpurun_out/sqb -o run -- python3 $REPO/bench.py --traffic",
-           "    python3 $REPO/bench.py --sq-summary $REPO/gpurun_out/sqa/run_counter_collection.csv "
-           "$REPO/gpurun_out/sqb/run_counter_collection.csv", "",
+           f"    timeout -s KILL 120 rocprofv3 --pmc {SQ_A} --output-format csv -d $REPO/gpurun_out/sqa_{which} "
+           f"-o run -- python3 $REPO/bench.py --traffic {which}",
+           f"    timeout -s KILL 120 rocprofv3 --pmc {SQ_B} --output-format csv -d $REPO/gpurun_out/sqb_{which} "
+           f"-o run -- python3 $REPO/bench.py --traffic {which}",
+           f"    python3 $REPO/bench.py --sq-summary {which} $REPO/gpurun_out/sqa_{which}/run_counter_collection.csv "
+           f"$REPO/gpurun_out/sqb_{which}/run_counter_collection.csv", "",
            f"Dispatch: grid {meta.get('Grid_Size')} work-items, workgroup {meta.get('Workgroup_Size')}, "
-           f"LDS {meta.get('LDS_Block_Size')} B, scratch {meta.get('Scratch_Size')} B.  Means over the last three "
-           "dispatches (the timed launch shape).", "",
+           f"LDS {meta.get('LDS_Block_Size')} B, scratch {meta.get('Scratch_Size')} B; launch shape "
+           f"{spec['shape'] or 'default'}.  Values per call ({n} dispatch(es)), means over the last three calls.", "",
            "| counter | value |", "|---|---:|"]
     for c in sorted(m):
         out.append(f"| {c} | {m[c]:.4g} |")
-    out += ["", "Derived (GRBM_GUI_ACTIVE summed over 8 XCDs; 1024 SIMDs; a slot is one SIMD's",
-            "four-cycle issue turn; a row step is one 64-lane row of one 2D problem, 2 * 512^3 / 62 of them):", "",
+    out += ["", "Derived (GRBM_GUI_ACTIVE summed over 8 XCDs; 1024 SIMDs, 256 CUs; a slot is one SIMD's",
+            "four-cycle issue turn):", "",
             f"* kernel cycles per XCD: {cyc:.0f} ({cyc / 2.4e3:.1f} us at 2.4 GHz)",
-            f"* VALU instructions per slot per SIMD: {m['SQ_INSTS_VALU'] / simds / slots:.2f}; "
-            f"SALU: {m['SQ_INSTS_SALU'] / simds / slots:.2f}",
-            f"* instructions per row step: VALU {m['SQ_INSTS_VALU'] / row_steps:.1f}, "
-            f"SALU {m['SQ_INSTS_SALU'] / row_steps:.1f}, LDS {m['SQ_INSTS_LDS'] / row_steps:.2f}, "
-            f"VMEM {m['SQ_INSTS_VMEM'] / row_steps:.2f}",
+            f"* instructions per slot per SIMD: VALU {m['SQ_INSTS_VALU'] / simds / slots:.2f}, "
+            f"SALU {m['SQ_INSTS_SALU'] / simds / slots:.2f}, LDS {m['SQ_INSTS_LDS'] / simds / slots:.3f}",
+            f"* VALU busy: {100 * 4 * m['SQ_ACTIVE_INST_VALU'] / (cyc * simds):.0f}% of SIMD cycles",
+            f"* instructions per 1000 voxels: VALU {m['SQ_INSTS_VALU'] / kvox:.1f}, "
+            f"SALU {m['SQ_INSTS_SALU'] / kvox:.1f}, LDS {m['SQ_INSTS_LDS'] / kvox:.2f}, "
+            f"VMEM {m['SQ_INSTS_VMEM'] / kvox:.2f}",
+            f"* LDS busy: {100 * m['SQ_LDS_IDX_ACTIVE'] / (cyc * cus):.0f}% of CU cycles, of which "
+            f"{100 * m['SQ_LDS_BANK_CONFLICT'] / max(m['SQ_LDS_IDX_ACTIVE'], 1):.0f}% bank-conflict stalls",
             f"* mean resident waves per SIMD: {4 * m['SQ_WAVE_CYCLES'] / (cyc * simds):.2f}"]
-    with open(SQ_FILE, "w") as fh:
+    path = os.path.join(ROOT, "profiles", spec["file"] + "_sq.md")
+    with open(path, "w") as fh:
         fh.write("\n".join(out) + "\n")
     print("\n".join(out))
 
@@ -364,6 +447,51 @@ def fourd_leg(ctx, stream, nbins=4096):
             "passes": 2 * shape[0] - 1}
 
 
+def rotated_leg(ctx, stream, make, shape, copies, nbins, reps, warmup, label):
+    """One small workload timed call by call over `copies` device copies of the
+    input (at least 1 GiB in all, more than the 256 MB Infinity Cache), each call
+    on the next copy, so no call reads an input a recent call left in cache."""
+    import torch
+    img = make()
+    one_d = torch.from_numpy(img).to(stream.device)
+    pool = one_d.unsqueeze(0).expand((copies,) + tuple(img.shape)).contiguous()
+    del one_d
+    out = torch.empty(nbins, dtype=torch.int64, device=pool.device)
+    shape_t = ctx.autotune(pool[0], nbins, reps=5, stream=stream)
+    i = [0]
+
+    def one():
+        ctx.compute(pool[i[0] % copies], nbins, out=out, stream=stream)
+        i[0] += 1
+    ms, wall = timed_calls(one, stream, reps, warmup)
+    # back to back without per-call events: the rate a stream of calls reaches
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        one()
+    torch.cuda.synchronize()
+    per_call = (time.perf_counter() - t0) / reps * 1e3
+    nv = int(np.prod(shape))
+    m = float(np.median(ms))
+    res = {"workload": label, "shape": list(shape), "nbins": nbins, "calls": reps,
+           "input_rotation": f"{copies} copies, {copies * img.nbytes / 2**30:.2f} GiB",
+           "p10_ms": round(float(np.percentile(ms, 10)), 4), "p50_ms": round(m, 4),
+           "p90_ms": round(float(np.percentile(ms, 90)), 4),
+           "gvox_s": round(nv / (m * 1e-3) / 1e9, 2),
+           "hbm_frac": round(nv * img.itemsize / (m * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "back_to_back_ms_per_call": round(per_call, 4), "launch_shape": shape_t}
+    del pool
+    return res
+
+
+def read_ceiling(vol_d, stream):
+    """A measured streaming-read rate of the same 512 MiB: a read-only reduction
+    (torch's max over the volume), best of 10."""
+    import torch
+    ms, _ = timed_calls(lambda: torch.amax(vol_d), stream, 10, 2)
+    return vol_d.numel() * vol_d.element_size() / (min(ms) * 1e-3) / 1e9
+
+
 def serving_leg(dev, rates=(100, 200, 500, 1000, 2000, 5000), seconds=2.0, max_requests=4000):
     """Open-loop Poisson request streams over crops of two GRF pools (uint16,
     4096 levels), 4096 bins, HBM-footprint admission; p50/p99 per rate."""
@@ -421,12 +549,13 @@ def main():
     ap.add_argument("--no-side", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
-    ap.add_argument("--traffic", action="store_true", help="only the program the counter passes profile")
-    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+    ap.add_argument("--traffic", nargs="?", const="3d", choices=sorted(PROFILES),
+                    help="only the program the counter passes profile (a workload of PROFILES)")
+    ap.add_argument("--write-traffic", nargs=3, metavar=("WORKLOAD", "FETCH_CSV", "WRITE_CSV"),
                     help="summarize the two counter passes into the profiles folder")
     ap.add_argument("--trace-summary", nargs=2, metavar=("RESULTS_DB", "BENCH_JSON"),
                     help="summarize a kernel-trace database into the profiles folder")
-    ap.add_argument("--sq-summary", nargs=2, metavar=("CSV_A", "CSV_B"),
+    ap.add_argument("--sq-summary", nargs=3, metavar=("WORKLOAD", "CSV_A", "CSV_B"),
                     help="summarize the two SQ counter passes into the profiles folder")
     args = ap.parse_args()
     if args.write_traffic:
@@ -444,7 +573,7 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.traffic:
-        traffic_run()
+        traffic_run(args.traffic)
         return
 
     import torch
@@ -527,20 +656,48 @@ def main():
         ms_a, _ = timed_calls(lambda: ctx.compute(vol_d, nbins, value_range="auto", out=out,
                                                   stream=stream), stream, 20, 3)
         result["auto_range_ms"] = round(float(np.mean(ms_a)), 4)
+        # the min/max pass alone: the AUTO call minus the explicit one
+        mm_ms = max(1e-6, float(np.mean(ms_a)) - ms_mean)
+        mm_rate = alg_bytes / (mm_ms * 1e-3) / 1e9
+        torch_rate = read_ceiling(vol_d, stream)
+        result["roofline"]["minmax_pass_gb_s"] = round(mm_rate, 1)
+        result["roofline"]["torch_amax_gb_s"] = round(torch_rate, 1)
+        result["roofline"]["read_ceiling_gb_s"] = round(max(mm_rate, torch_rate), 1)
+        result["roofline"]["read_ceiling_how"] = ("the faster of two read-only passes over the same 512 MiB: the "
+                                                  "library's AUTO-range min/max pass (the AUTO step minus the "
+                                                  "explicit step) and torch.amax (best of 10)")
+        result["roofline"]["frac_of_read_ceiling"] = round(achieved / result["roofline"]["read_ceiling_gb_s"], 4)
         del vol_d
         log("generating 16384^2 u16 GRF ...")
         img2 = synth.quantize_u16(synth.grf((16384, 16384), seed=4), 4096)
         img2_d = torch.from_numpy(img2.view(np.int16)).to(dev)
+        shape2 = None
         if not args.no_autotune:
-            ctx.autotune(img2_d, nbins, value_range="auto", reps=3, stream=stream)
+            shape2 = ctx.autotune(img2_d, nbins, value_range="auto", reps=3, stream=stream)
         ms2, _ = timed_calls(lambda: ctx.compute(img2_d, nbins, value_range="auto", out=out,
                                                  stream=stream), stream, 20, 3)
         m2 = float(np.mean(ms2))
+        lo2, hi2 = int(img2.min()), int(img2.max())
+        ms2e, _ = timed_calls(lambda: ctx.compute(img2_d, nbins, value_range=(lo2, hi2), out=out,
+                                                  stream=stream), stream, 20, 3)
+        m2e = float(np.mean(ms2e))
         result["plain_2d_u16"] = {"shape": [16384, 16384], "ms": round(m2, 4),
                                   "gvox_s": round(img2.size / (m2 * 1e-3) / 1e9, 2),
-                                  "hbm_frac": round(img2.size * 2 / (m2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                                  "hbm_frac": round(img2.size * 2 / (m2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                  "range": "auto (a second read for the min/max pass)",
+                                  "explicit_range_ms": round(m2e, 4),
+                                  "explicit_range_gvox_s": round(img2.size / (m2e * 1e-3) / 1e9, 2),
+                                  "explicit_range_hbm_frac": round(img2.size * 2 / (m2e * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                  "launch_shape": shape2}
         del img2_d, img2
 
+        log("small configs (inputs rotated over 1 GiB) ...")
+        result["small_2d_u8"] = rotated_leg(ctx, stream, lambda: synth.uniform_u8((256, 256), seed=1), (256, 256),
+                                            16384, 256, 1000, 20, "256^2 uint8 uniform noise (seed 1), 256 bins")
+        result["small_3d_u8"] = rotated_leg(ctx, stream,
+                                            lambda: synth.smoothed_noise_u8((256, 256, 256), sigma=2.0, seed=2),
+                                            (256, 256, 256), 64, 256, 200, 10,
+                                            "256^3 uint8 smoothed noise (sigma 2, seed 2), 256 bins")
         log("generating the uneven batch ...")
         imgs = synth.batch_images(count=512, seed=5)
         nv = int(sum(a.size for a in imgs))
@@ -603,7 +760,27 @@ def main():
         log("cpu baseline ...")
         result["cpu_baseline"] = cpu_baseline(vol, nbins, lo, hi)
 
+    result["configs"] = config_summary(result)
     print(json.dumps(result), flush=True)
+
+
+def config_summary(r):
+    """Gvoxels/s and fraction of HBM peak of each of the five workloads, gathered
+    from the legs above (None where a leg was skipped)."""
+    def pick(d, *keys):
+        return {k: d.get(k) for k in keys} if d else None
+    c = {"C1 256^2 u8 uniform, 256 bins": pick(r.get("small_2d_u8"), "p50_ms", "gvox_s", "hbm_frac"),
+         "C2 256^3 u8 smoothed, 256 bins": pick(r.get("small_3d_u8"), "p50_ms", "gvox_s", "hbm_frac"),
+         "C3 512^3 f32 GRF, 4096 bins, explicit range": {"ms": r.get("ms_per_step"), "gvox_s": r.get("value"),
+                                                         "kernel_hbm_frac": r["roofline"]["frac"]},
+         "C3 16384^2 u16 GRF, 4096 bins": pick(r.get("plain_2d_u16"), "ms", "gvox_s", "hbm_frac", "explicit_range_ms",
+                                               "explicit_range_gvox_s", "explicit_range_hbm_frac"),
+         "C4 512-image batch, 256 bins": pick(r.get("batched"), "ms", "planned_ms", "gvox_s", "hbm_frac",
+                                              "speedup_vs_per_image")}
+    srv = r.get("serving")
+    c["C5 serving, 4096 bins"] = ({rate: pick(v, "p50_ms", "p99_ms", "completed_per_s", "gvox_s")
+                                   for rate, v in srv["rates"].items()} if srv else None)
+    return c
 
 
 if __name__ == "__main__":

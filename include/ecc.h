@@ -56,6 +56,7 @@
 #ifndef ECC_H
 #define ECC_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -105,6 +106,23 @@ ecc_status ecc_create(ecc_ctx** ctx, int32_t device, int32_t construction);
  * must have synchronized every stream the context enqueued work on.  A null
  * ctx is accepted and ignored. */
 ecc_status ecc_destroy(ecc_ctx* ctx);
+
+/* Grows the context's device scratch to at least scratch_bytes and each of its
+ * pinned table buffers (host memory the batch descriptors are staged in before
+ * their copy to the device) to at least table_bytes, now, so that later calls
+ * whose needs fit neither allocate nor wait: growing the scratch inside a call
+ * waits for the whole device (the old buffer may still be in use on any
+ * stream), which a serving loop with several streams cannot afford.  This call
+ * itself may wait for the device.  Generous bounds for a batch
+ * (ecc_compute_batch) of n images of V voxels in all, with W = min(nbins, 4096)
+ * and C compute units: at most S = 2 n + 6 C + V / 2^25 + 3 workgroup segments;
+ * tables <= 2 KiB + 160 n + 28 S + 24 C + 24 (V / 2^20 + n) bytes; scratch <=
+ * 1 KiB + tables + 4 W S bytes.  A single image needs less scratch than a
+ * batch of it.
+ * Calls that need more still work, growing the buffers as before.
+ * Errors: ECC_ERR_INVALID_ARG (ctx null, scratch_bytes > 2^40 or table_bytes >
+ * 2^30), ECC_ERR_OUT_OF_MEMORY, ECC_ERR_DEVICE. */
+ecc_status ecc_reserve(ecc_ctx* ctx, size_t scratch_bytes, size_t table_bytes);
 
 /* Text of the last error recorded on `ctx` ("" if none); valid until the next
  * call on the same context.  A null ctx returns the last ecc_create error. */

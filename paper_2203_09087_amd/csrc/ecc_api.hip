@@ -29,10 +29,17 @@ struct ecc_ctx {
     int cu_count = 256;
     void* ws = nullptr;          // device scratch
     size_t ws_bytes = 0;
-    void* staging = nullptr;     // pinned host memory for the batch tables
-    size_t staging_bytes = 0;
-    hipEvent_t staging_done = nullptr;   // recorded after the last copy out of `staging`
-    bool staging_pending = false;
+    // pinned host buffers for the batch tables, used in turn: a call waits for a
+    // buffer's previous copy only when all of them are still being copied from
+    struct Staging {
+        void* ptr = nullptr;
+        size_t bytes = 0;
+        hipEvent_t done = nullptr;   // recorded after the last copy out of ptr
+        bool pending = false;
+    };
+    static constexpr int kStagingSlots = 4;
+    Staging staging[kStagingSlots];
+    int staging_next = 0;
     // streaming (ecc_compute_streamed): two device slab buffers, a copy stream,
     // and events ordering copies and kernels on them
     void* slab_buf[2] = {nullptr, nullptr};
@@ -588,28 +595,33 @@ ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t st
 
 // ------------------------------------------------------------------ batches
 
-ecc_status ensure_staging(ecc_ctx* ctx, size_t bytes)
+// The next staging buffer, of at least `bytes`.  Only when its previous copy
+// (kStagingSlots calls ago) is still in flight does the host wait for it; only
+// a buffer that is too small is replaced.
+ecc_status ensure_staging(ecc_ctx* ctx, size_t bytes, ecc_ctx::Staging** out)
 {
     hipError_t e;
-    if (!ctx->staging_done) {
-        if ((e = hipEventCreateWithFlags(&ctx->staging_done, hipEventDisableTiming)) != hipSuccess)
+    ecc_ctx::Staging& sl = ctx->staging[ctx->staging_next];
+    ctx->staging_next = (ctx->staging_next + 1) % ecc_ctx::kStagingSlots;
+    if (!sl.done) {
+        if ((e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess)
             return hip_fail(ctx, e, "hipEventCreate");
     }
-    // the previous batch's table copy must have left the pinned buffer
-    if (ctx->staging_pending) {
-        if ((e = hipEventSynchronize(ctx->staging_done)) != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize");
-        ctx->staging_pending = false;
+    if (sl.pending) {
+        if ((e = hipEventSynchronize(sl.done)) != hipSuccess) return hip_fail(ctx, e, "hipEventSynchronize");
+        sl.pending = false;
     }
-    if (bytes <= ctx->staging_bytes) return ECC_OK;
-    if (ctx->staging) (void)hipHostFree(ctx->staging);
-    ctx->staging = nullptr;
-    ctx->staging_bytes = 0;
+    *out = &sl;
+    if (bytes <= sl.bytes) return ECC_OK;
+    if (sl.ptr) (void)hipHostFree(sl.ptr);
+    sl.ptr = nullptr;
+    sl.bytes = 0;
     const size_t want = std::max(bytes, (size_t)64 << 10);
-    if ((e = hipHostMalloc(&ctx->staging, want, hipHostMallocDefault)) != hipSuccess) {
-        ctx->staging = nullptr;
+    if ((e = hipHostMalloc(&sl.ptr, want, hipHostMallocDefault)) != hipSuccess) {
+        sl.ptr = nullptr;
         return hip_fail(ctx, e, "hipHostMalloc(staging)");
     }
-    ctx->staging_bytes = want;
+    sl.bytes = want;
     return ECC_OK;
 }
 
@@ -812,14 +824,15 @@ ecc_status enqueue_batch(ecc_ctx* ctx, const std::vector<Job>& jobs, int32_t nbi
     const size_t base = kCounterBytes;
     ecc_status st = ensure_ws(ctx, base + T.lay.total);
     if (st != ECC_OK) return st;
-    if ((st = ensure_staging(ctx, T.lay.tables_end)) != ECC_OK) return st;
-    pack_batch_tables(T, (char*)ctx->staging);
+    ecc_ctx::Staging* sl = nullptr;
+    if ((st = ensure_staging(ctx, T.lay.tables_end, &sl)) != ECC_OK) return st;
+    pack_batch_tables(T, (char*)sl->ptr);
     char* d = (char*)ctx->ws + base;
     hipError_t e;
-    if ((e = hipMemcpyAsync(d, ctx->staging, T.lay.tables_end, hipMemcpyHostToDevice, stream)) != hipSuccess)
+    if ((e = hipMemcpyAsync(d, sl->ptr, T.lay.tables_end, hipMemcpyHostToDevice, stream)) != hipSuccess)
         return hip_fail(ctx, e, "hipMemcpyAsync(batch tables)");
-    if ((e = hipEventRecord(ctx->staging_done, stream)) != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
-    ctx->staging_pending = true;
+    if ((e = hipEventRecord(sl->done, stream)) != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
+    sl->pending = true;
     return launch_batch_kernels(ctx, T, d, false, stream);
 }
 
@@ -1023,8 +1036,11 @@ ecc_status ecc_destroy(ecc_ctx* ctx)
     {
         DeviceGuard g(ctx->device);
         if (ctx->ws) (void)hipFree(ctx->ws);
-        if (ctx->staging) (void)hipHostFree(ctx->staging);
-        if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
+        for (auto& sl : ctx->staging) {
+            if (sl.done) (void)hipEventSynchronize(sl.done);
+            if (sl.ptr) (void)hipHostFree(sl.ptr);
+            if (sl.done) (void)hipEventDestroy(sl.done);
+        }
         for (hipEvent_t ev : ctx->tev) (void)hipEventDestroy(ev);
         for (int b = 0; b < 2; ++b) {
             if (ctx->slab_buf[b]) (void)hipFree(ctx->slab_buf[b]);
@@ -1035,6 +1051,26 @@ ecc_status ecc_destroy(ecc_ctx* ctx)
         if (ctx->smooth_tmp) (void)hipFree(ctx->smooth_tmp);
     }
     delete ctx;
+    return ECC_OK;
+}
+
+ecc_status ecc_reserve(ecc_ctx* ctx, size_t scratch_bytes, size_t table_bytes)
+{
+    if (!ctx) return ECC_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (scratch_bytes > ((size_t)1 << 40) || table_bytes > ((size_t)1 << 30)) {
+        ctx->err = "ecc_reserve: sizes beyond 1 TiB of scratch or 1 GiB of tables";
+        return ECC_ERR_INVALID_ARG;
+    }
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+    ecc_status st = ensure_ws(ctx, std::max(scratch_bytes, kCounterBytes));
+    if (st != ECC_OK) return st;
+    if (table_bytes == 0) return ECC_OK;
+    for (int i = 0; i < ecc_ctx::kStagingSlots; ++i) {
+        ecc_ctx::Staging* sl = nullptr;
+        if ((st = ensure_staging(ctx, table_bytes, &sl)) != ECC_OK) return st;
+    }
     return ECC_OK;
 }
 

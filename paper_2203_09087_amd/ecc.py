@@ -34,7 +34,7 @@ EXPORTED = ("ecc_create", "ecc_destroy", "ecc_last_error", "ecc_compute", "ecc_c
             "ecc_compute_batch", "ecc_set_kernel_timing", "ecc_kernel_time", "ecc_batch_plan_create",
             "ecc_batch_plan_launch", "ecc_batch_plan_destroy", "ecc_batch_plan_autotune", "ecc_autotune",
             "ecc_set_launch_shape", "ecc_compute_streamed",
-            "ecc_smooth13", "ecc_batch_schedule", "ecc_compute_noalloc")
+            "ecc_smooth13", "ecc_batch_schedule", "ecc_compute_noalloc", "ecc_reserve")
 
 
 class ecc_image(ctypes.Structure):
@@ -106,6 +106,8 @@ def load_library(path: str = LIB_PATH):
     lib.ecc_compute_noalloc.restype = ctypes.c_int
     lib.ecc_compute_batch.argtypes = [vp, ctypes.POINTER(ecc_image), i32, i32, vp]
     lib.ecc_compute_batch.restype = ctypes.c_int
+    lib.ecc_reserve.argtypes = [vp, ctypes.c_size_t, ctypes.c_size_t]
+    lib.ecc_reserve.restype = ctypes.c_int
     lib.ecc_set_kernel_timing.argtypes = [vp, i32]
     lib.ecc_set_kernel_timing.restype = ctypes.c_int
     lib.ecc_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64p]
@@ -172,6 +174,19 @@ def ecc_compute_batch(ctx: int, imgs, nbins: int, stream: int = 0) -> int:
     """imgs: a list of ecc_image structures or a make_images() array."""
     ptr, keep, n = _descriptor_array(imgs)
     return load_library().ecc_compute_batch(ctx, ptr, n, int(nbins), stream)
+
+
+def ecc_reserve(ctx: int, scratch_bytes: int, table_bytes: int) -> int:
+    return load_library().ecc_reserve(ctx, int(scratch_bytes), int(table_bytes))
+
+
+def batch_reserve_bytes(count: int, voxels: int, nbins: int, cu_count: int):
+    """(scratch_bytes, table_bytes) that cover any ecc_compute_batch call of at most
+    `count` images and `voxels` voxels in all (the header's bounds)."""
+    w = min(int(nbins), 4096)
+    segs = 2 * count + 6 * cu_count + voxels // (1 << 25) + 3
+    tables = 2048 + 160 * count + 28 * segs + 24 * cu_count + 24 * (voxels // (1 << 20) + count)
+    return 1024 + tables + 4 * w * segs, tables
 
 
 def ecc_set_kernel_timing(ctx: int, enable: int) -> int:
@@ -386,6 +401,11 @@ class Context:
         self._check(ecc_compute_batch(self.handle, make_images(images, outs, value_ranges), nbins,
                                       self._stream(stream)))
         return outs
+
+    def reserve(self, scratch_bytes: int, table_bytes: int = 0):
+        """Grows the context's device scratch and pinned table buffers now, so that
+        later calls that fit neither allocate nor wait for the device."""
+        self._check(ecc_reserve(self.handle, scratch_bytes, table_bytes))
 
     def set_kernel_timing(self, enable: bool = True):
         """Records HIP events around every histogram-kernel launch of later calls."""

@@ -4,7 +4,10 @@ Requests (one image each, already resident in device memory or given as a
 device view to copy from) arrive over time.  The loop admits arrived requests in
 arrival order as long as their device footprint (input copy + int64 output) fits
 the memory budget and a lane is free, gathers the admitted requests of a lane
-into one ``ecc_compute_batch`` call, and records one event per batch.  Several
+into one ``ecc_compute_batch`` call, and records one event per batch.  A request
+may be written on any stream: ``submit`` records an event on the submitting
+(current) stream, and the lane that takes the request waits for it on the device
+before reading the source.  Several
 lanes (each its own library context and HIP stream) let batches that were
 admitted at different times run on the device at the same time, so requests that
 arrive while others are on the GPU join the next batch instead of waiting for the
@@ -37,17 +40,25 @@ class Request:
     image: object = None
     nbytes: int = 0
     lane: int = -1
+    batch_size: int = 0
+    device_ms: float = -1.0   # the batch's device time, from its timing events
+    ready: object = None      # event on the submitting stream (set by submit)
+    done: object = None       # event after the request's batch (wait on it to read out)
 
     @property
     def latency(self) -> float:
         return self.t_done - self.t_arrival
+
+    @property
+    def queue_wait(self) -> float:
+        return self.t_admit - self.t_arrival
 
 
 @dataclass
 class _Lane:
     ctx: object
     stream: object
-    inflight: collections.deque = field(default_factory=collections.deque)   # (event, [requests])
+    inflight: collections.deque = field(default_factory=collections.deque)   # (start, end, [requests])
 
 
 class Server:
@@ -57,10 +68,14 @@ class Server:
     max_batch:    most requests per library call.
     lanes:        independent (context, stream) pairs; at most ``max_inflight``
                   batches are outstanding per lane.
+
+    Every lane's context reserves, at start, the scratch any admissible batch
+    needs (up to ``max_batch`` images within the budget, ``max_nbins`` bins), so
+    that no call grows it later: growing waits for the whole device.
     """
 
     def __init__(self, device=0, construction="vertex", budget_bytes=8 << 30, max_batch=64, lanes=2,
-                 max_inflight=2):
+                 max_inflight=2, max_nbins=4096):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
@@ -69,6 +84,10 @@ class Server:
         self.max_inflight = int(max_inflight)
         self.lanes = [_Lane(ecc.Context(device, construction), torch.cuda.Stream(self.device))
                       for _ in range(lanes)]
+        cus = torch.cuda.get_device_properties(self.device).multi_processor_count
+        scratch, tables = ecc.batch_reserve_bytes(self.max_batch, self.budget, max_nbins, cus)
+        for ln in self.lanes:
+            ln.ctx.reserve(scratch, tables)
         self.pending = collections.deque()
         self.held = 0             # bytes held by admitted, unfinished requests
         self.peak_held = 0
@@ -82,22 +101,28 @@ class Server:
     # ------------------------------------------------------------ scheduling
 
     def submit(self, req: Request):
-        """Queues a request that has arrived (its ``t_arrival`` is already set)."""
+        """Queues a request that has arrived (its ``t_arrival`` is already set).  Its
+        source may still be being written by work on the current stream."""
         src = req.source
         req.nbytes = src.numel() * src.element_size() + 8 * req.nbins
         if req.nbytes > self.budget:
             raise ValueError(f"request of {req.nbytes} bytes exceeds the budget of {self.budget}")
+        req.ready = self.torch.cuda.Event()
+        req.ready.record(self.torch.cuda.current_stream(self.device))
         self.pending.append(req)
 
     def _reap(self, now: float) -> int:
         done = 0
         for ln in self.lanes:
-            while ln.inflight and ln.inflight[0][0].query():
-                _, reqs = ln.inflight.popleft()
+            while ln.inflight and ln.inflight[0][1].query():
+                start, end, reqs = ln.inflight.popleft()
+                dms = start.elapsed_time(end)
                 for r in reqs:
                     r.t_done = now
+                    r.device_ms = dms
                     self.held -= r.nbytes
                     r.image = None          # the input copy can be released
+                    r.ready = None
                     self.completed.append(r)
                 done += len(reqs)
         return done
@@ -120,18 +145,30 @@ class Server:
             if not batch:
                 break      # the head request waits for memory to free up
             self.peak_held = max(self.peak_held, self.held)
+            start = torch.cuda.Event(enable_timing=True)
+            end = torch.cuda.Event(enable_timing=True)
             with torch.cuda.stream(ln.stream):
                 for r in batch:
+                    # the source was written on the submitting stream
+                    ln.stream.wait_event(r.ready)
                     r.t_admit = now
                     r.lane = li
-                    r.image = r.source.contiguous() if not r.source.is_contiguous() else r.source
+                    r.batch_size = len(batch)
+                    if r.source.is_contiguous():
+                        r.image = r.source
+                        # the lane reads memory the caller's stream allocated
+                        r.image.record_stream(ln.stream)
+                    else:
+                        r.image = r.source.contiguous()
                     r.out = torch.empty(r.nbins, dtype=torch.int64, device=self.device)
+                start.record(ln.stream)
             ln.ctx.compute_batch([r.image for r in batch], nbins,
                                  value_ranges=[r.value_range for r in batch],
                                  outs=[r.out for r in batch], stream=ln.stream)
-            ev = torch.cuda.Event()
-            ev.record(ln.stream)
-            ln.inflight.append((ev, batch))
+            end.record(ln.stream)
+            for r in batch:
+                r.done = end
+            ln.inflight.append((start, end, batch))
             self.batches += 1
             started += len(batch)
         return started
@@ -179,10 +216,26 @@ class Server:
 
 
 def latency_summary(reqs, wall_s: float) -> dict:
-    """p50/p99 latency (ms) and completed requests per second."""
+    """p50/p99 latency (ms), completed requests per second, and where the time of
+    a request goes: queue wait (arrival to admission), the device time of its
+    batch, and its batch size (p50/p99 each); for the slowest 1% of requests the
+    same means."""
     import numpy as np
     lat = np.array([r.latency for r in reqs]) * 1e3
+    wait = np.array([r.queue_wait for r in reqs]) * 1e3
+    dev = np.array([r.device_ms for r in reqs])
+    bs = np.array([r.batch_size for r in reqs])
+    tail = lat >= np.percentile(lat, 99)
+
+    def pq(x):
+        return [round(float(np.percentile(x, 50)), 3), round(float(np.percentile(x, 99)), 3)]
     return {"requests": len(reqs), "p50_ms": round(float(np.percentile(lat, 50)), 3),
             "p99_ms": round(float(np.percentile(lat, 99)), 3),
             "mean_ms": round(float(lat.mean()), 3),
-            "completed_per_s": round(len(reqs) / wall_s, 1)}
+            "completed_per_s": round(len(reqs) / wall_s, 1),
+            "queue_wait_ms_p50_p99": pq(wait), "batch_device_ms_p50_p99": pq(dev),
+            "batch_size_p50_p99": pq(bs),
+            "slowest_1pct": {"latency_ms": round(float(lat[tail].mean()), 3),
+                             "queue_wait_ms": round(float(wait[tail].mean()), 3),
+                             "batch_device_ms": round(float(dev[tail].mean()), 3),
+                             "batch_size": round(float(bs[tail].mean()), 1)}}

@@ -91,3 +91,32 @@ def test_schedule_rejects_bad_descriptors():
     assert st == ecc.ECC_ERR_INVALID_ARG and "dims" in ecc.ecc_last_error(None)
     st = ecc.ecc_batch_schedule([_img((2, 3, 4, 5))], 256)[0]
     assert st == ecc.ECC_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("cons", [ecc.ECC_VERTEX, ecc.ECC_TOP])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_segment_count_within_the_reserve_bound(cons, seed):
+    """The segment bound that ecc_reserve documents (and batch_reserve_bytes
+    sizes a serving lane's scratch with), S <= 2 n + 6 C + V / 2^25 + 3, holds for
+    mixed batches of every dtype, from tiny images to ones the 2^27 cap splits."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    for cus in (8, 256):
+        for count in (1, 5, 64, 300):
+            imgs = []
+            nvox = 0
+            for _ in range(count):
+                if rng.random() < 0.5:
+                    dims = tuple(int(v) for v in rng.integers(1, 3000, size=2))
+                else:
+                    dims = tuple(int(v) for v in rng.integers(1, 400, size=3))
+                if rng.random() < 0.02:
+                    dims = (1200, 1100, 1000)
+                imgs.append(_img(dims, int(rng.integers(0, 3))))
+                nvox += int(np.prod(dims))
+            st, segs, mx, ib, cb = ecc.ecc_batch_schedule(imgs, 4096, None, cu_count=cus, construction=cons)
+            assert st == ecc.ECC_OK, ecc.ecc_last_error(None)
+            assert ib == cb
+            assert segs <= 2 * count + 6 * cus + nvox // (1 << 25) + 3, (cus, count, segs, nvox)
+            scratch, tables = ecc.batch_reserve_bytes(count, nvox, 4096, cus)
+            assert scratch >= 1024 + tables + 4 * 4096 * segs

@@ -114,3 +114,46 @@ def test_full_size_mix_equals_alone(oracle_mod):
     finally:
         alone.close()
         srv.close()
+
+
+def test_sources_written_on_another_stream(oracle_mod):
+    """Sources still being written on a side stream when they are submitted (no
+    host synchronization in between): every lane waits for the submitting
+    stream before it reads them.  A long run of matrix products ahead of the
+    writes on that stream would make a lane that did not wait read zeros."""
+    from paper_2203_09087_amd import serve, synth
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import time
+    say("case: serving sources written on a side stream")
+    host = [synth.quantize_u16(synth.grf((256, 256) if i % 2 else (24, 40, 32), seed=100 + i), 4096)
+            for i in range(12)]
+    pinned = [torch.from_numpy(h.view(np.int16)).pin_memory() for h in host]
+    srv = serve.Server(budget_bytes=1 << 30, max_batch=4, lanes=2)
+    side = torch.cuda.Stream()
+    reqs = []
+    try:
+        with torch.cuda.stream(side):
+            m = torch.randn(2048, 2048, device="cuda")
+            for _ in range(30):
+                m = torch.tanh(m @ m)
+            for i, p in enumerate(pinned):
+                src = torch.zeros(p.shape, dtype=torch.int16, device="cuda")
+                src.copy_(p, non_blocking=True)
+                if i % 3 == 0:
+                    src = src.transpose(0, 1)   # a strided source: the lane makes the copy
+                r = serve.Request(source=src, nbins=4096, value_range=(0, 4095))
+                r.t_arrival = time.perf_counter()
+                srv.submit(r)
+                reqs.append((r, i))
+                del src
+            srv.drain()
+        torch.cuda.synchronize()
+        assert len(reqs) == len(host)
+        for r, i in reqs:
+            assert r.done is not None and r.batch_size >= 1 and r.device_ms > 0.0
+            h = np.swapaxes(host[i], 0, 1) if i % 3 == 0 else host[i]
+            want = oracle_mod.ecc(np.ascontiguousarray(h), 4096, "vertex", value_range=(0, 4095))
+            assert np.array_equal(r.out.cpu().numpy(), want), i
+    finally:
+        srv.close()
