@@ -151,50 +151,47 @@ def traffic_run(which="3d"):
     log("profile run done")
 
 
-def _dispatch_values(path, counter=None, kernel=None):
-    """{kernel name: [per-dispatch value in dispatch order]} for one counter (rows of
-    one dispatch summed), or for every counter when counter is None."""
+def _per_dispatch(path, counter):
+    """{dispatch id: (kernel name, counter value summed over the dispatch's rows)}."""
     import csv
-    per = {}
-    for r in csv.DictReader(open(path)):
-        if counter and r["Counter_Name"] != counter:
-            continue
-        if kernel and kernel not in r["Kernel_Name"]:
-            continue
-        key = (int(r["Dispatch_Id"]), r["Kernel_Name"], r["Counter_Name"])
-        per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
     out = {}
-    for (_, name, cn), v in sorted(per.items()):
-        out.setdefault((name, cn), []).append(v)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        d = int(r["Dispatch_Id"])
+        name, v = out.get(d, (r["Kernel_Name"], 0.0))
+        out[d] = (name, v + float(r["Counter_Value"]))
     return out
 
 
 def write_traffic(which, fetch_csv, write_csv):
     """Turns the FETCH_SIZE and WRITE_SIZE passes over traffic_run(which) into the
     profile summary (traffic_bytes() reads the 3D one).  Each counter is scaled by
-    the bytes the copy kernel is known to move over what the counter reads for it."""
+    the bytes the 512 MiB calibration copy is known to move over what the counter
+    reads for it (its three dispatches: the program's three largest copies)."""
     spec = PROFILES[which]
-    f = _dispatch_values(fetch_csv, "FETCH_SIZE")
-    w = _dispatch_values(write_csv, "WRITE_SIZE")
-    copy = [k for k in f if "copy" in k[0].lower()]
-    main = [k for k in f if spec["kernel"] in k[0]]
-    if not copy or not main:
-        raise SystemExit(f"copy or histogram kernel not found in {sorted(f)}")
-    copy = max(copy, key=lambda k: np.mean(f[k]))
-    cf = float(np.mean(f[copy]))
-    cw = float(np.mean(w[(copy[0], "WRITE_SIZE")]))
-    fs, ws = COPY_BYTES / (cf * 1024), COPY_BYTES / (cw * 1024)
     n = spec["per_call"]
-    # every variant of the histogram kernel in dispatch order; the last call's
-    # dispatches (per_call of them) are summed, averaged over the three calls
-    disp_f = sorted(v for k in main for v in zip(_dispatch_ids(fetch_csv, k[0]), f[k]))
-    disp_w = sorted(v for k in [(m[0], "WRITE_SIZE") for m in main] if k in w
-                    for v in zip(_dispatch_ids(write_csv, k[0]), w[k]))
-    calls_f = [sum(x for _, x in disp_f[i:i + n]) for i in range(len(disp_f) - 3 * n, len(disp_f), n)]
-    calls_w = [sum(x for _, x in disp_w[i:i + n]) for i in range(len(disp_w) - 3 * n, len(disp_w), n)]
-    ef, ew = float(np.mean(calls_f)), float(np.mean(calls_w))
+    f = _per_dispatch(fetch_csv, "FETCH_SIZE")
+    w = _per_dispatch(write_csv, "WRITE_SIZE")
+
+    def calib(d):
+        vals = sorted((v for name, v in d.values() if "copy" in name.lower()), reverse=True)[:3]
+        if len(vals) < 3:
+            raise SystemExit("calibration copies not found")
+        return float(np.mean(vals))
+
+    def calls(d):
+        ids = sorted(k for k, (name, _) in d.items() if spec["kernel"] in name)[-3 * n:]
+        if len(ids) < 3 * n:
+            raise SystemExit(f"{spec['kernel']}: {len(ids)} dispatches, {3 * n} expected")
+        return float(np.sum([d[k][1] for k in ids])) / 3.0
+    copy_name = "__amd_rocclr_copyBuffer"
+    cf, cw = calib(f), calib(w)
+    fs, ws = COPY_BYTES / (cf * 1024), COPY_BYTES / (cw * 1024)
+    ef, ew = calls(f), calls(w)
     hf, hw = ef * 1024 * fs, ew * 1024 * ws
     alg = _alg_bytes(which)
+    copy = (copy_name,)
     lines = [
         f"# HBM traffic per call of the histogram kernel ({spec['kernel']}, {n} dispatch(es) per call):",
         f"# {spec['what']}; counters in KiB per dispatch.",
@@ -204,7 +201,7 @@ def write_traffic(which, fetch_csv, write_csv):
         f"-d $REPO/gpurun_out/pmc_write_{which} -o run -- python3 $REPO/bench.py --traffic {which}",
         f"command_summary: python3 bench.py --write-traffic {which} FETCH_CSV WRITE_CSV",
         f"launch_shape: {spec['shape'] or 'default'}",
-        f"calibration_kernel: {copy[0]}",
+        f"calibration_kernel: {copy[0]} (the three largest copy dispatches)",
         f"calibration_bytes: {COPY_BYTES} read and {COPY_BYTES} written per dispatch",
         f"copy_fetch_kib: {cf:.1f}",
         f"copy_write_kib: {cw:.1f}",
@@ -224,13 +221,6 @@ def write_traffic(which, fetch_csv, write_csv):
     with open(path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
-
-
-def _dispatch_ids(path, kernel_name):
-    """Dispatch ids of one kernel (one per dispatch, in order)."""
-    import csv
-    ids = sorted({int(r["Dispatch_Id"]) for r in csv.DictReader(open(path)) if r["Kernel_Name"] == kernel_name})
-    return ids
 
 
 def _alg_bytes(which):
@@ -439,12 +429,17 @@ def fourd_leg(ctx, stream, nbins=4096):
     del vol
     out = torch.empty(nbins, dtype=torch.int64, device=d.device)
     ms, _ = timed_calls(lambda: ctx.compute(d, nbins, value_range=(lo, hi), out=out, stream=stream), stream, 20, 3)
-    m = float(np.mean(ms))
+    # the same image as a batch of one: its passes share one persistent launch
+    ms_b, _ = timed_calls(lambda: ctx.compute_batch([d], nbins, value_ranges=[(lo, hi)], outs=[out], stream=stream),
+                          stream, 20, 3)
+    m, mb = float(np.mean(ms)), float(np.mean(ms_b))
     nv = int(np.prod(shape))
     gbs = nv * 4 / (m * 1e-3) / 1e9
     return {"shape": list(shape), "nbins": nbins, "ms": round(m, 3), "gvox_s": round(nv / (m * 1e-3) / 1e9, 2),
             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-            "passes": 2 * shape[0] - 1}
+            "passes": 2 * shape[0] - 1,
+            "batched_ms": round(mb, 3), "batched_gvox_s": round(nv / (mb * 1e-3) / 1e9, 2),
+            "batched_hbm_frac": round(nv * 4 / (mb * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def rotated_leg(ctx, stream, make, shape, copies, nbins, reps, warmup, label):

@@ -35,8 +35,9 @@
  *
  * Conventions shared by every entry point:
  *   - Images are DEVICE pointers, contiguous, row-major, dims[0] slowest.  Any
- *     alignment is accepted.  ndim is 2 or 3 (also 4 for ecc_compute and
- *     ecc_compute_ex, see there; the other entry points return
+ *     alignment is accepted.  ndim is 2 or 3 (also 4 for ecc_compute,
+ *     ecc_compute_ex, ecc_compute_noalloc, ecc_compute_batch, the batch plans and
+ *     ecc_batch_schedule, see ecc_compute; the other entry points return
  *     ECC_ERR_UNSUPPORTED for a 4D image); every dim is >= 1.
  *   - `out` is a DEVICE pointer to nbins int64 values, overwritten (not
  *     accumulated) with the ECC.  1 <= nbins <= 65535.
@@ -86,7 +87,7 @@ typedef enum {
 /* One image of a call.  Enum-valued fields are int32_t for a fixed layout. */
 typedef struct {
     const void* data;    /* device pointer to the voxels */
-    int32_t ndim;        /* 2 or 3; 4 for ecc_compute_ex */
+    int32_t ndim;        /* 2 or 3; 4 where the entry point takes 4D images */
     int32_t dtype;       /* ecc_dtype */
     int64_t dims[4];     /* dims[0] slowest; entries beyond ndim are ignored */
     int32_t range_mode;  /* ecc_range_mode */
@@ -163,8 +164,11 @@ ecc_status ecc_compute_noalloc(ecc_ctx* ctx, const ecc_image* img, int32_t nbins
 /* ECC of `count` images in one persistent histogram launch per dtype present
  * (then one merge and one scan launch for all images).  imgs: HOST array of `count`
  * descriptors; images may differ in ndim, dtype, size and range mode but share
- * nbins and the context's filtration; each writes its own `out`.  The result of
- * every image is identical to what ecc_compute_ex returns for it alone.
+ * nbins and the context's filtration; each writes its own `out`.  A 4D image
+ * enters as its signed 3D passes (hyperplanes and adjacent max/min pairs, as in
+ * ecc_compute), each counted like a 3D image of the batch into rows of its own
+ * image.  The result of every image is identical to what ecc_compute_ex returns
+ * for it alone.
  * count == 0 is a no-op.  Errors as above; the index of the first bad descriptor
  * is named in ecc_last_error. */
 ecc_status ecc_compute_batch(ecc_ctx* ctx, const ecc_image* imgs, int32_t count, int32_t nbins,

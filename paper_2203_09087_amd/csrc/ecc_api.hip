@@ -177,7 +177,8 @@ struct Job {
     int64_t* out;
 };
 
-// max_ndim: 4 for the single-image calls, 3 where 4D images are not taken.
+// max_ndim: 4 for the compute, batch and plan calls, 3 where 4D images are not
+// taken (launch shapes, tuning, streaming).
 ecc_status validate(ecc_ctx* ctx, const ecc_image& im, int32_t nbins, const char* where, Job* job,
                     int max_ndim = 3)
 {
@@ -185,7 +186,7 @@ ecc_status validate(ecc_ctx* ctx, const ecc_image& im, int32_t nbins, const char
     if (!im.data) { snprintf(buf, sizeof buf, "%s: null image pointer", where); return fail(ctx, ECC_ERR_INVALID_ARG, buf); }
     if (!im.out) { snprintf(buf, sizeof buf, "%s: null output pointer", where); return fail(ctx, ECC_ERR_INVALID_ARG, buf); }
     if (im.ndim == 4 && max_ndim < 4) {
-        snprintf(buf, sizeof buf, "%s: 4D images are computed by ecc_compute and ecc_compute_ex only", where);
+        snprintf(buf, sizeof buf, "%s: 4D images are taken by the compute, batch and plan calls only", where);
         return fail(ctx, ECC_ERR_UNSUPPORTED, buf);
     }
     if (im.ndim < 2 || im.ndim > 4) {
@@ -636,6 +637,7 @@ struct BatchGroup {
     int dtype;
     int grid;
     size_t wg_seg_first;
+    bool pairs;   // the group counts pair volumes
 };
 
 // Host form of a batch: descriptor tables, workgroup segments and launch groups.
@@ -648,6 +650,7 @@ struct BatchTables {
     std::vector<uint32_t> mm;
     std::vector<ecc::BatchPiece> pieces;
     std::vector<BatchGroup> groups;
+    std::vector<int64_t> owner_bricks;   // bricks of each image's volumes
     BatchLayout lay;
 };
 
@@ -670,8 +673,9 @@ void build_batch_tables(int cu_count, int construction, const std::vector<Job>& 
     T.nbins = nbins;
     T.window = std::min<int32_t>(nbins, ecc::kMaxLdsBins);
     T.images.assign((size_t)count, ecc::BatchImage{});
-    std::vector<int64_t> bricks((size_t)count), max_take((size_t)count);
-    std::vector<double> brick_cost((size_t)count);
+    // the volumes that are counted, in image order: a 2D or 3D image itself; a
+    // 4D image's signed 3D passes (as in enqueue_4d), appended after the images
+    std::vector<int> vols;
     for (int i = 0; i < count; ++i) {
         const Job& j = jobs[(size_t)i];
         ecc::BatchImage& im = T.images[(size_t)i];
@@ -684,33 +688,70 @@ void build_batch_tables(int cu_count, int construction, const std::vector<Job>& 
         im.nvox = j.nvox;
         im.params = host_params(j, nbins);
         im.out = j.out;
+        im.sign = 1;
+        im.owner = i;
+        if (j.ndim != 4) {
+            vols.push_back(i);
+            continue;
+        }
+        const int64_t nw = j.nw, hv = j.g.n0 * j.g.n1 * j.g.n2;
+        const size_t esize = j.dtype == ECC_U8 ? 1 : (j.dtype == ECC_U16 ? 2 : 4);
+        const bool vertex = construction == ECC_VERTEX;
+        for (int64_t w = 0; w < nw; ++w) {
+            for (int pair = 0; pair < 2; ++pair) {
+                const int sign = pair ? (vertex ? -1 : 1) : (vertex ? 1 : -1 + (w == 0) + (w == nw - 1));
+                if (sign == 0 || (pair && w + 1 >= nw)) continue;
+                ecc::BatchImage v = T.images[(size_t)i];
+                v.ndim = 3;
+                v.nvox = hv;
+                v.data = (const char*)j.data + (size_t)w * (size_t)hv * esize;
+                v.data2 = pair ? (const char*)j.data + (size_t)(w + 1) * (size_t)hv * esize : nullptr;
+                v.sign = sign;
+                vols.push_back((int)T.images.size());
+                T.images.push_back(v);
+            }
+        }
+    }
+    const size_t nrec = T.images.size();
+    std::vector<int64_t> bricks(nrec, 0), max_take(nrec, 1);
+    std::vector<double> brick_cost(nrec, 0.0);
+    T.owner_bricks.assign((size_t)count, 0);
+    for (int i : vols) {
+        ecc::BatchImage& im = T.images[(size_t)i];
         bricks[(size_t)i] = ecc::batch_bricks(im, construction, waves, shape.depth3, shape.depth2);
+        T.owner_bricks[(size_t)im.owner] += bricks[(size_t)i];
         // time of one brick: a team of wpb waves walks its rows (two 2D problems
-        // per row in 3D); W / wpb teams of a workgroup share one pass
+        // per row in 3D, twice the loads for a pair volume); W / wpb teams of a
+        // workgroup share one pass
         const double teams = (double)(waves / im.wpb);
-        brick_cost[(size_t)i] = (j.ndim == 3 ? 2.0 * ecc::kRows3 : 1.0) * (double)im.depth / teams;
+        brick_cost[(size_t)i] = (im.ndim == 3 ? 2.0 * ecc::kRows3 : 1.0) * (double)im.depth / teams;
         // a segment's histogram is an int32 row: at most kSegVoxels voxels each
         max_take[(size_t)i] = std::max<int64_t>(1, kSegVoxels / ecc::batch_brick_voxels(im));
     }
-    // One launch per dtype present; the bricks of its images, in order, are cut
+    // One launch per dtype present; the bricks of its volumes, in order, are cut
     // into one contiguous run per workgroup with about equal work.
     for (int dt = 0; dt < 3; ++dt) {
         double total = 0;
         int64_t nbr = 0;
-        for (int i = 0; i < count; ++i)
-            if (T.images[(size_t)i].dtype == dt) { total += bricks[(size_t)i] * brick_cost[(size_t)i]; nbr += bricks[(size_t)i]; }
+        bool pairs = false;
+        for (int i : vols)
+            if (T.images[(size_t)i].dtype == dt) {
+                total += bricks[(size_t)i] * brick_cost[(size_t)i];
+                nbr += bricks[(size_t)i];
+                pairs = pairs || T.images[(size_t)i].data2 != nullptr;
+            }
         if (nbr == 0) continue;
         const int G = (int)std::max<int64_t>(1, std::min<int64_t>(nbr, (int64_t)shape.wgs_per_cu * cu_count));
-        BatchGroup gr{dt, G, T.wg_seg.size()};
+        BatchGroup gr{dt, G, T.wg_seg.size(), pairs};
         const double per = total / G;
         int wg = 0;
         double acc = 0;   // work assigned to workgroups 0..wg-1 plus the current one
         T.wg_seg.push_back((int32_t)T.segs.size());
-        for (int i = 0; i < count; ++i) {
+        for (int i : vols) {
             if (T.images[(size_t)i].dtype != dt) continue;
             int64_t b = 0;
             while (b < bricks[(size_t)i]) {
-                // bricks of image i that still fit in workgroup wg's share
+                // bricks of volume i that still fit in workgroup wg's share
                 const double room = per * (wg + 1) - acc;
                 int64_t take = (int64_t)std::ceil(room / brick_cost[(size_t)i] - 1e-9);
                 if (wg == G - 1) take = bricks[(size_t)i] - b;
@@ -729,14 +770,14 @@ void build_batch_tables(int cu_count, int construction, const std::vector<Job>& 
         T.groups.push_back(gr);
     }
     const int nseg = (int)T.segs.size();
-    // partial rows of every image
+    // partial rows of every image (its volumes' segments)
     T.slot_off.assign((size_t)count + 1, 0);
     T.slots.assign((size_t)nseg, 0);
-    for (const auto& sg : T.segs) T.slot_off[(size_t)sg.image + 1]++;
+    for (const auto& sg : T.segs) T.slot_off[(size_t)T.images[(size_t)sg.image].owner + 1]++;
     for (int i = 0; i < count; ++i) T.slot_off[(size_t)i + 1] += T.slot_off[(size_t)i];
     {
         std::vector<int32_t> fill(T.slot_off.begin(), T.slot_off.end() - 1);
-        for (const auto& sg : T.segs) T.slots[(size_t)fill[(size_t)sg.image]++] = sg.slot;
+        for (const auto& sg : T.segs) T.slots[(size_t)fill[(size_t)T.images[(size_t)sg.image].owner]++] = sg.slot;
     }
     // pieces of the AUTO images for the min/max pass
     const int64_t piece = int64_t(1) << 20;
@@ -806,6 +847,7 @@ ecc_status launch_batch_kernels(ecc_ctx* ctx, const BatchTables& T, char* d, boo
             B.dtype = gr.dtype;
             B.grid = gr.grid;
             B.wg_seg = (const int32_t*)(d + lay.wg_seg) + gr.wg_seg_first;
+            B.pairs = gr.pairs ? 1 : 0;
             if ((e = timed_launch(ctx, stream, [&] { return ecc::launch_ecc_batch(B, ctx->construction, stream); })) !=
                 hipSuccess)
                 return hip_fail(ctx, e, "batch launch");
@@ -1146,7 +1188,7 @@ ecc_status ecc_compute_batch(ecc_ctx* ctx, const ecc_image* imgs, int32_t count,
     for (int32_t i = 0; i < count; ++i) {
         char where[64];
         snprintf(where, sizeof where, "ecc_compute_batch: image %d", i);
-        ecc_status st = validate(ctx, imgs[i], nbins, where, &jobs[i]);
+        ecc_status st = validate(ctx, imgs[i], nbins, where, &jobs[i], 4);
         if (st != ECC_OK) return st;
     }
     DeviceGuard g(ctx->device);
@@ -1178,7 +1220,7 @@ ecc_status ecc_batch_schedule(const ecc_image* imgs, int32_t count, int32_t nbin
     for (int32_t i = 0; i < count; ++i) {
         char where[64];
         snprintf(where, sizeof where, "ecc_batch_schedule: image %d", i);
-        const ecc_status st = validate(&probe, imgs[i], nbins, where, &jobs[(size_t)i]);
+        const ecc_status st = validate(&probe, imgs[i], nbins, where, &jobs[(size_t)i], 4);
         if (st != ECC_OK) {
             g_create_err = probe.err;
             return st;
@@ -1191,13 +1233,12 @@ ecc_status ecc_batch_schedule(const ecc_image* imgs, int32_t count, int32_t nbin
     for (const auto& sg : T.segs) {
         const int64_t v = (sg.b1 - sg.b0) * ecc::batch_brick_voxels(T.images[(size_t)sg.image]);
         mx = std::max(mx, v);
-        cov[(size_t)sg.image] += sg.b1 - sg.b0;
+        cov[(size_t)T.images[(size_t)sg.image].owner] += sg.b1 - sg.b0;
     }
     *segments = (int32_t)T.segs.size();
     *max_segment_voxels = mx;
     for (int32_t i = 0; i < count; ++i) {
-        ecc::BatchImage im = T.images[(size_t)i];
-        if (image_bricks) image_bricks[i] = ecc::batch_bricks(im, construction, ecc::kBatchWaves, sh.depth3, sh.depth2);
+        if (image_bricks) image_bricks[i] = T.owner_bricks[(size_t)i];
         if (covered_bricks) covered_bricks[i] = cov[(size_t)i];
     }
     return ECC_OK;
@@ -1260,7 +1301,7 @@ ecc_status ecc_batch_plan_create(ecc_ctx* ctx, const ecc_image* imgs, int32_t co
     for (int32_t i = 0; i < count; ++i) {
         char where[64];
         snprintf(where, sizeof where, "ecc_batch_plan_create: image %d", i);
-        ecc_status st = validate(ctx, imgs[i], nbins, where, &jobs[i]);
+        ecc_status st = validate(ctx, imgs[i], nbins, where, &jobs[i], 4);
         if (st != ECC_OK) return st;
     }
     DeviceGuard g(ctx->device);

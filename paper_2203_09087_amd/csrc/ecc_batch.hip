@@ -8,6 +8,8 @@
 // merge kernels then give every image the sum of its rows (and its prefix scan)
 // without any atomic operation on the histogram bins, so the result of an image
 // does not depend on the batch it is in.
+#include <algorithm>
+
 #include "ecc_device.h"
 
 namespace ecc {
@@ -54,7 +56,8 @@ __global__ __launch_bounds__(kThreads) void k_minmax_batch(const BatchImage* ima
     }
 }
 
-template <int DT, int CONS, bool WIN>
+// PAIRS: the launch holds pair volumes (their bricks load two hyperplanes).
+template <int DT, int CONS, bool WIN, bool PAIRS>
 __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU_3D)))
 void k_ecc_batch(BatchLaunch B)
 {
@@ -63,37 +66,49 @@ void k_ecc_batch(BatchLaunch B)
     const int W = (int)(blockDim.x >> 6), wave = wave_id();
     const int s_end = B.wg_seg[blockIdx.x + 1];
     for (int si = B.wg_seg[blockIdx.x]; si < s_end; ++si) {
+        // The tables are read with vector loads (the kernel also writes global
+        // memory, so the scalar cache is not used for them): every value the
+        // brick loops depend on is read back from the first lane, so that sizes,
+        // offsets and pointers stay in scalar registers there.
         const BatchSeg S = B.segs[si];
-        const BatchImage& I = B.images[S.image];
+        const int vol = (int)uniform_u32((uint32_t)S.image);
+        const BatchImage& I = B.images[vol];
         const BinParams P = I.auto_range
-                                ? params_from_keys(B.mm[2 * S.image], B.mm[2 * S.image + 1], DT, B.nbins)
+                                ? params_from_keys(B.mm[2 * I.owner], B.mm[2 * I.owner + 1], DT, B.nbins)
                                 : I.params;
         EccLaunch L;   // the fields the brick bodies read
-        L.data = I.data;
-        L.g = I.g;
-        L.depth = I.depth;
-        L.z_own = I.g.n0;
+        L.data = uniform_ptr(I.data);
+        L.data2 = PAIRS ? uniform_ptr(I.data2) : nullptr;
+        L.g = Geom{uniform_i64(I.g.n0), uniform_i64(I.g.n1), uniform_i64(I.g.n2)};
+        L.depth = uniform_i64(I.depth);
+        L.z_own = L.g.n0;
         L.z_base = 0;
-        L.n0_global = I.g.n0;
+        L.n0_global = L.g.n0;
+        const int ndim = (int)uniform_u32((uint32_t)I.ndim);
         zero_hist(hist, B.width);
         // the workgroup's waves form W / wpb teams of wpb waves; team t takes
         // bricks b0 + t, b0 + t + teams, ... (waves beyond the last team idle)
         const int wpb = uniform_u32((uint32_t)I.wpb);
         const int teams = W / wpb, team = wave / wpb, xw = wave - team * wpb;
         const int64_t chunk = kLaneCols * (int64_t)wpb;
-        const uint32_t nxc = (uint32_t)I.nxc, nyb = (uint32_t)I.nyb;
+        const uint32_t nxc = uniform_u32((uint32_t)I.nxc), nyb = uniform_u32((uint32_t)I.nyb);
+        const int64_t b0 = uniform_i64(S.b0), b1 = uniform_i64(S.b1);
         if (team < teams) {
-            for (int64_t b = S.b0 + team; b < S.b1; b += teams) {
+            for (int64_t b = b0 + team; b < b1; b += teams) {
                 // brick coordinates from the 64-bit index; each fits 32 bits
                 const int64_t row = b / nxc;
                 const uint32_t xc = (uint32_t)(b - row * nxc);
-                if (I.ndim == 3)
+                if (PAIRS && L.data2)
+                    run_brick_3d<DT, CONS, WIN, true>(L, P, H, chunk, xc, (uint32_t)(row % nyb), (uint32_t)(row / nyb),
+                                                      xw);
+                else if (ndim == 3)
                     run_brick_3d<DT, CONS, WIN>(L, P, H, chunk, xc, (uint32_t)(row % nyb), (uint32_t)(row / nyb), xw);
                 else
                     run_brick_2d<DT, CONS, WIN>(L, P, H, chunk, xc, (uint32_t)row, xw);
             }
         }
-        flush_hist(hist, B.partials + (size_t)S.slot * (size_t)B.width, B.width);
+        flush_hist(hist, B.partials + (size_t)uniform_u32((uint32_t)S.slot) * (size_t)B.width, B.width, false,
+                   (int)uniform_u32((uint32_t)I.sign));
     }
 }
 
@@ -126,14 +141,20 @@ __global__ __launch_bounds__(kThreads) void k_scan_batch(BatchLaunch B)
     block_scan_inplace(B.images[blockIdx.x].out, B.nbins);
 }
 
+template <int DT, int CONS, bool PAIRS>
+hipError_t launch_batch_p(const BatchLaunch& B, hipStream_t s)
+{
+    if (B.windowed)
+        hipLaunchKernelGGL((k_ecc_batch<DT, CONS, true, PAIRS>), dim3(B.grid), dim3(B.waves * 64), 0, s, B);
+    else
+        hipLaunchKernelGGL((k_ecc_batch<DT, CONS, false, PAIRS>), dim3(B.grid), dim3(B.waves * 64), 0, s, B);
+    return hipGetLastError();
+}
+
 template <int DT, int CONS>
 hipError_t launch_batch_w(const BatchLaunch& B, hipStream_t s)
 {
-    if (B.windowed)
-        hipLaunchKernelGGL((k_ecc_batch<DT, CONS, true>), dim3(B.grid), dim3(B.waves * 64), 0, s, B);
-    else
-        hipLaunchKernelGGL((k_ecc_batch<DT, CONS, false>), dim3(B.grid), dim3(B.waves * 64), 0, s, B);
-    return hipGetLastError();
+    return B.pairs ? launch_batch_p<DT, CONS, true>(B, s) : launch_batch_p<DT, CONS, false>(B, s);
 }
 
 template <int CONS>
@@ -152,7 +173,21 @@ int64_t batch_bricks(BatchImage& im, int construction, int waves, int depth3, in
 {
     const int64_t xpos = axis_positions(im.g.n2, construction);
     const int64_t cols = (xpos + kLaneCols - 1) / kLaneCols;
-    im.wpb = (int32_t)(cols < waves ? cols : waves);
+    // waves per brick: the fraction of the workgroup's lanes that own a column,
+    // (wave columns needed / wave columns covered) x (waves in teams / waves),
+    // is largest (ties: the wider brick).  A 256-wide row takes 1 wave per
+    // brick (9 teams, 81% of the lanes busy) rather than 5 (one team, 45%).
+    int best = 1;
+    double best_eff = -1.0;
+    for (int w = (int)std::min<int64_t>(cols, waves); w >= 1; --w) {
+        const int64_t nx = (cols + w - 1) / w;
+        const double eff = (double)cols / (double)(nx * w) * (double)((waves / w) * w) / (double)waves;
+        if (eff > best_eff + 1e-9) {
+            best_eff = eff;
+            best = w;
+        }
+    }
+    im.wpb = best;
     const int64_t chunk = kLaneCols * (int64_t)im.wpb;
     im.nxc = (int32_t)((xpos + chunk - 1) / chunk);
     if (im.ndim == 3) {

@@ -362,6 +362,12 @@ __device__ __forceinline__ void flush_hist(const int32_t* hist, int32_t* dst, in
 // as divergent and the row masks that depend on them leave scalar registers.
 __device__ __forceinline__ bool uniform_flag(int32_t f) { return __builtin_amdgcn_readfirstlane(f) != 0; }
 __device__ __forceinline__ uint32_t uniform_u32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ int64_t uniform_i64(int64_t v)
+{
+    const uint32_t lo = uniform_u32((uint32_t)v), hi = uniform_u32((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ const void* uniform_ptr(const void* p) { return (const void*)uniform_i64((int64_t)p); }
 
 // Raw buffer loads: one 32-bit per-lane byte offset (the column) plus one scalar
 // byte offset (the row) against a resource whose base is the brick's first row.

@@ -118,23 +118,31 @@ struct EccLaunch {
 
 // ---------------------------------------------------------------- batches
 
-// One image of a batch, as the batched kernels see it.
+// One volume of a batch, as the batched kernels see it.  The first `count`
+// entries are the batch's images (their outputs, ranges and min/max keys); a 2D
+// or 3D image is also the volume that is counted.  A 4D image is counted as
+// signed 3D volumes (its hyperplanes and the max/min of adjacent pairs) listed
+// after the images, each naming its image as `owner`; its own entry is counted
+// by none.
 struct BatchImage {
     const void* data;
+    const void* data2;    // a pair volume: count the max (vertex) or min (top) of data and data2
     Geom g;
     int32_t ndim, dtype;
-    int32_t auto_range;   // parameters come from the min/max keys mm[2*i], mm[2*i+1]
+    int32_t auto_range;   // parameters come from the min/max keys mm[2*owner], mm[2*owner+1]
     int32_t nxc;          // x-chunks of 63 * wpb position columns
     int32_t nyb;          // row blocks (3D: kRows3 rows; 2D: `depth` rows)
     int32_t wpb;          // waves per brick; a workgroup works on kBatchWaves / wpb bricks side by side
+    int32_t sign;         // +1, or -1: the volume's histogram enters its image's rows negated
+    int32_t owner;        // the image whose output, range and partial rows the volume uses
     int64_t depth;        // planes (3D) or rows (2D) per brick
     int64_t nvox;
     BinParams params;     // explicit or default range
     int64_t* out;         // the caller's output, nbins int64
 };
 
-// A run of consecutive bricks [b0, b1) of one image handled by one workgroup; its
-// histogram lands in partial row `slot`.
+// A run of consecutive bricks [b0, b1) of one volume (an index into the images)
+// handled by one workgroup; its histogram lands in partial row `slot`.
 struct BatchSeg {
     int32_t image;
     int32_t slot;
@@ -160,6 +168,7 @@ struct BatchLaunch {
     int32_t* partials;          // [nslots][width]
     int32_t nbins, bin_lo, width, windowed;
     int32_t grid, waves;
+    int32_t pairs;              // the launch counts pair volumes (4D images)
 };
 
 // Launchers (ecc_batch.hip).

@@ -5,9 +5,9 @@ device view to copy from) arrive over time.  The loop admits arrived requests in
 arrival order as long as their device footprint (input copy + int64 output) fits
 the memory budget and a lane is free, gathers the admitted requests of a lane
 into one ``ecc_compute_batch`` call, and records one event per batch.  A request
-may be written on any stream: ``submit`` records an event on the submitting
-(current) stream, and the lane that takes the request waits for it on the device
-before reading the source.  Several
+may be written on any stream: ``submit`` notes the submitting (current) stream,
+and the lane that takes the request waits on the device for the work that stream
+holds at admission (no wait when that stream is already idle).  Several
 lanes (each its own library context and HIP stream) let batches that were
 admitted at different times run on the device at the same time, so requests that
 arrive while others are on the GPU join the next batch instead of waiting for the
@@ -41,8 +41,8 @@ class Request:
     nbytes: int = 0
     lane: int = -1
     batch_size: int = 0
-    device_ms: float = -1.0   # the batch's device time, from its timing events
-    ready: object = None      # event on the submitting stream (set by submit)
+    device_ms: float = -1.0   # the batch's device time, from its timing events (-1: not timed)
+    stream: object = None     # the stream the request was submitted on (set by submit)
     done: object = None       # event after the request's batch (wait on it to read out)
 
     @property
@@ -68,6 +68,8 @@ class Server:
     max_batch:    most requests per library call.
     lanes:        independent (context, stream) pairs; at most ``max_inflight``
                   batches are outstanding per lane.
+    device_timing: time every batch with a pair of events (each request's
+                  ``device_ms``); off, the events only order work.
 
     Every lane's context reserves, at start, the scratch any admissible batch
     needs (up to ``max_batch`` images within the budget, ``max_nbins`` bins), so
@@ -75,13 +77,15 @@ class Server:
     """
 
     def __init__(self, device=0, construction="vertex", budget_bytes=8 << 30, max_batch=64, lanes=2,
-                 max_inflight=2, max_nbins=4096):
+                 max_inflight=2, max_nbins=4096, device_timing=True):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
         self.budget = int(budget_bytes)
         self.max_batch = int(max_batch)
         self.max_inflight = int(max_inflight)
+        self.device_timing = bool(device_timing)
+        self._ready = {}          # one reusable event per submitting stream
         self.lanes = [_Lane(ecc.Context(device, construction), torch.cuda.Stream(self.device))
                       for _ in range(lanes)]
         cus = torch.cuda.get_device_properties(self.device).multi_processor_count
@@ -107,8 +111,7 @@ class Server:
         req.nbytes = src.numel() * src.element_size() + 8 * req.nbins
         if req.nbytes > self.budget:
             raise ValueError(f"request of {req.nbytes} bytes exceeds the budget of {self.budget}")
-        req.ready = self.torch.cuda.Event()
-        req.ready.record(self.torch.cuda.current_stream(self.device))
+        req.stream = self.torch.cuda.current_stream(self.device)
         self.pending.append(req)
 
     def _reap(self, now: float) -> int:
@@ -116,13 +119,13 @@ class Server:
         for ln in self.lanes:
             while ln.inflight and ln.inflight[0][1].query():
                 start, end, reqs = ln.inflight.popleft()
-                dms = start.elapsed_time(end)
+                dms = start.elapsed_time(end) if self.device_timing else -1.0
                 for r in reqs:
                     r.t_done = now
                     r.device_ms = dms
                     self.held -= r.nbytes
                     r.image = None          # the input copy can be released
-                    r.ready = None
+                    r.stream = None
                     self.completed.append(r)
                 done += len(reqs)
         return done
@@ -145,12 +148,19 @@ class Server:
             if not batch:
                 break      # the head request waits for memory to free up
             self.peak_held = max(self.peak_held, self.held)
-            start = torch.cuda.Event(enable_timing=True)
-            end = torch.cuda.Event(enable_timing=True)
+            start = torch.cuda.Event(enable_timing=self.device_timing)
+            end = torch.cuda.Event(enable_timing=self.device_timing)
+            # the sources were written on their submitting streams: the lane waits
+            # for what each of them holds now, unless it is idle already
+            for st in {r.stream.cuda_stream: r.stream for r in batch}.values():
+                if not st.query():
+                    ev = self._ready.get(st.cuda_stream)
+                    if ev is None:
+                        ev = self._ready[st.cuda_stream] = torch.cuda.Event()
+                    ev.record(st)
+                    ln.stream.wait_event(ev)
             with torch.cuda.stream(ln.stream):
                 for r in batch:
-                    # the source was written on the submitting stream
-                    ln.stream.wait_event(r.ready)
                     r.t_admit = now
                     r.lane = li
                     r.batch_size = len(batch)

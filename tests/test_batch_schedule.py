@@ -89,8 +89,30 @@ def test_schedule_rejects_bad_descriptors():
     bad = _img((0, 5))
     st = ecc.ecc_batch_schedule([bad], 256)[0]
     assert st == ecc.ECC_ERR_INVALID_ARG and "dims" in ecc.ecc_last_error(None)
-    st = ecc.ecc_batch_schedule([_img((2, 3, 4, 5))], 256)[0]
-    assert st == ecc.ECC_ERR_UNSUPPORTED
+    five = _img((2, 3, 4, 5))
+    five.ndim = 5
+    st = ecc.ecc_batch_schedule([five], 256)[0]
+    assert st == ecc.ECC_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("nw", [1, 2, 5])
+def test_4d_image_is_scheduled_as_its_signed_3d_passes(nw):
+    """A 4D image in a batch is counted as 3D volumes: the vertex filtration's nw
+    hyperplanes and nw - 1 adjacent pairs; the top filtration's pairs and only its
+    interior hyperplanes (the coefficient -1 + [first] + [last] of an end
+    hyperplane is 0), or the one hyperplane when nw is 1.  Every brick of them is
+    covered, next to 2D and 3D images in the same batch."""
+    hyper = (7, 9, 70)
+    for cons in (ecc.ECC_VERTEX, ecc.ECC_TOP):
+        st, _, _, ib3, _ = ecc.ecc_batch_schedule([_img(hyper)], 256, None, construction=cons)
+        assert st == ecc.ECC_OK
+        passes = 2 * nw - 1 if cons == ecc.ECC_VERTEX else (1 if nw == 1 else 2 * nw - 3)
+        imgs = [_img((40, 50)), _img((nw,) + hyper, ecc.ECC_F32), _img((6, 5, 4), ecc.ECC_U16)]
+        st, segs, mx, ib, cb = ecc.ecc_batch_schedule(imgs, 256, None, construction=cons)
+        assert st == ecc.ECC_OK, ecc.ecc_last_error(None)
+        assert ib == cb
+        assert ib[1] == passes * ib3[0]
+        assert 0 < mx <= CAP
 
 
 @pytest.mark.parametrize("cons", [ecc.ECC_VERTEX, ecc.ECC_TOP])

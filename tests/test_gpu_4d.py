@@ -113,9 +113,69 @@ def test_4d_benchmark_field(ctxs, oracle_mod, cons):
     check(ctxs[cons], oracle_mod, field, 4096, cons, rng=(float(field.min()), float(field.max())), threads=16)
 
 
+@pytest.mark.parametrize("cons", CONS)
+def test_4d_in_batch_and_plan(ctxs, oracle_mod, cons):
+    """4D images in a batch, between 2D and 3D images of every dtype, with every
+    range mode: each result equals the oracle and the image computed alone, in a
+    plain batch call and in a planned batch."""
+    rng = np.random.default_rng(98 + CONS.index(cons))
+    imgs = [rng.integers(0, 9, size=(3, 4, 5, 70)).astype(np.uint8),
+            rng.standard_normal(size=(40, 130)).astype(np.float32),
+            rng.standard_normal(size=(5, 6, 7, 64)).astype(np.float32),
+            rng.integers(0, 3000, size=(9, 10, 11)).astype(np.uint16),
+            rng.integers(0, 3000, size=(1, 5, 6, 200)).astype(np.uint16),
+            rng.integers(0, 200, size=(2, 1, 1, 5)).astype(np.uint8),
+            rng.standard_normal(size=(4, 3, 10, 130)).astype(np.float32)]
+    ranges = [None, "auto", "auto", (100, 2900), "auto", (0, 199), (-1.0, 1.5)]
+    nbins = 512
+    ctx = ctxs[cons]
+    print(f"case: 4d batch {cons} shapes={[a.shape for a in imgs]}", flush=True, file=sys.stderr)
+    devs = [to_dev(a) for a in imgs]
+    outs = ctx.compute_batch(devs, nbins, value_ranges=ranges)
+    pouts = [torch.empty(nbins, dtype=torch.int64, device="cuda") for _ in imgs]
+    plan = ctx.plan_batch(devs, nbins, value_ranges=ranges, outs=pouts)
+    plan.launch()
+    torch.cuda.synchronize()
+    for i, (a, d, r) in enumerate(zip(imgs, devs, ranges)):
+        want = oracle_mod.ecc(a, nbins, cons, value_range=r)
+        alone = ctx.compute(d, nbins, value_range=r)
+        torch.cuda.synchronize()
+        assert np.array_equal(outs[i].cpu().numpy(), want), (i, a.shape)
+        assert np.array_equal(pouts[i].cpu().numpy(), want), (i, a.shape)
+        assert np.array_equal(alone.cpu().numpy(), want), (i, a.shape)
+    plan.close()
+
+
+@pytest.mark.parametrize("cons", CONS)
+def test_4d_in_batch_wide_histogram(ctxs, oracle_mod, cons):
+    """A 4D image in a batch whose histogram spans several LDS windows."""
+    rng = np.random.default_rng(99)
+    imgs = [rng.integers(0, 65536, size=(3, 4, 7, 80)).astype(np.uint16),
+            rng.integers(0, 65536, size=(30, 90)).astype(np.uint16)]
+    print(f"case: 4d batch {cons} 9000 bins", flush=True, file=sys.stderr)
+    outs = ctxs[cons].compute_batch([to_dev(a) for a in imgs], 9000, value_ranges=[(0, 65535)] * 2)
+    torch.cuda.synchronize()
+    for o, a in zip(outs, imgs):
+        assert np.array_equal(o.cpu().numpy(), oracle_mod.ecc(a, 9000, cons, value_range=(0, 65535)))
+
+
+@pytest.mark.parametrize("cons", CONS)
+def test_4d_benchmark_field_in_batch(ctxs, oracle_mod, cons):
+    """The 8 x 256^3 float32 field as a batch of one (its 15 or 13 passes in one
+    launch) equals the oracle."""
+    from paper_2203_09087_amd import synth
+    field = synth.grf((8, 256, 256, 256), seed=9)
+    rng = (float(field.min()), float(field.max()))
+    print(f"case: 4d benchmark field in a batch, {cons}", flush=True, file=sys.stderr)
+    out = ctxs[cons].compute_batch([to_dev(field)], 4096, value_ranges=[rng])[0]
+    torch.cuda.synchronize()
+    want = oracle_mod.ecc(field, 4096, cons, value_range=rng, threads=16)
+    assert np.array_equal(out.cpu().numpy(), want)
+
+
 def test_4d_is_rejected_where_unsupported(ctxs):
     from paper_2203_09087_amd import ecc
     img = torch.zeros((2, 3, 4, 5), dtype=torch.uint8, device="cuda")
     with pytest.raises(ecc.EccError) as e:
-        ctxs["vertex"].compute_batch([img], 16)
+        ctxs["vertex"].autotune(img, 16)
     assert e.value.status == ecc.ECC_ERR_UNSUPPORTED
