@@ -466,6 +466,16 @@ def rotated_leg(ctx, stream, make, shape, copies, nbins, reps, warmup, label):
         one()
     torch.cuda.synchronize()
     per_call = (time.perf_counter() - t0) / reps * 1e3
+    # the histogram kernel alone (HIP events around its launches): what the
+    # device spends per image once the host's call overhead is out of the way
+    ctx.set_kernel_timing(True)
+    one()
+    ctx.kernel_time()
+    for _ in range(min(reps, 200)):
+        one()
+    k_ms, k_n = ctx.kernel_time()
+    ctx.set_kernel_timing(False)
+    k_avg = k_ms / max(1, k_n)
     nv = int(np.prod(shape))
     m = float(np.median(ms))
     res = {"workload": label, "shape": list(shape), "nbins": nbins, "calls": reps,
@@ -474,7 +484,9 @@ def rotated_leg(ctx, stream, make, shape, copies, nbins, reps, warmup, label):
            "p90_ms": round(float(np.percentile(ms, 90)), 4),
            "gvox_s": round(nv / (m * 1e-3) / 1e9, 2),
            "hbm_frac": round(nv * img.itemsize / (m * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-           "back_to_back_ms_per_call": round(per_call, 4), "launch_shape": shape_t}
+           "back_to_back_ms_per_call": round(per_call, 4), "launch_shape": shape_t,
+           "kernel_ms": round(k_avg, 4), "kernel_gvox_s": round(nv / (k_avg * 1e-3) / 1e9, 2),
+           "kernel_hbm_frac": round(nv * img.itemsize / (k_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     del pool
     return res
 
@@ -764,8 +776,10 @@ def config_summary(r):
     from the legs above (None where a leg was skipped)."""
     def pick(d, *keys):
         return {k: d.get(k) for k in keys} if d else None
-    c = {"C1 256^2 u8 uniform, 256 bins": pick(r.get("small_2d_u8"), "p50_ms", "gvox_s", "hbm_frac"),
-         "C2 256^3 u8 smoothed, 256 bins": pick(r.get("small_3d_u8"), "p50_ms", "gvox_s", "hbm_frac"),
+    c = {"C1 256^2 u8 uniform, 256 bins": pick(r.get("small_2d_u8"), "p50_ms", "gvox_s", "hbm_frac", "kernel_ms",
+                                                "kernel_gvox_s", "kernel_hbm_frac"),
+         "C2 256^3 u8 smoothed, 256 bins": pick(r.get("small_3d_u8"), "p50_ms", "gvox_s", "hbm_frac", "kernel_ms",
+                                                "kernel_gvox_s", "kernel_hbm_frac"),
          "C3 512^3 f32 GRF, 4096 bins, explicit range": {"ms": r.get("ms_per_step"), "gvox_s": r.get("value"),
                                                          "kernel_hbm_frac": r["roofline"]["frac"]},
          "C3 16384^2 u16 GRF, 4096 bins": pick(r.get("plain_2d_u16"), "ms", "gvox_s", "hbm_frac", "explicit_range_ms",

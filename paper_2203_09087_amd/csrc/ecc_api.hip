@@ -479,6 +479,7 @@ ecc_status enqueue_hist(ecc_ctx* ctx, char* base, const Job& j, int32_t nbins, h
     L.flush_sign = sign;
     L.out = j.out;
     L.counter = counters;
+    L.fused = 0;
     hipError_t e;
     if (pass_only) {
         // one window, histogram kernel only: its rows are merged by a later call
@@ -490,6 +491,15 @@ ecc_status enqueue_hist(ecc_ctx* ctx, char* base, const Job& j, int32_t nbins, h
     }
     L.flush_add = 0;
     L.flush_sign = 1;
+    if (!accumulate && scan && sign > 0 && sz.window >= nbins && (int64_t)L.grid * nbins <= ecc::kFusedMergeWords) {
+        // few rows: the histogram kernel's last workgroup merges and scans them
+        L.bin_lo = 0;
+        L.width = nbins;
+        L.fused = 1;
+        if ((e = timed_launch(ctx, stream, [&] { return ecc::launch_ecc(L, stream); })) != hipSuccess)
+            return hip_fail(ctx, e, "ecc launch");
+        return ECC_OK;
+    }
     for (int32_t b0 = 0; b0 < nbins; b0 += sz.window) {
         L.bin_lo = b0;
         L.width = std::min<int32_t>(sz.window, nbins - b0);

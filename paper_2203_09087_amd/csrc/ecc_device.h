@@ -306,6 +306,84 @@ __device__ __forceinline__ int32_t step_count(uint32_t cur, uint32_t next, int32
     return c;
 }
 
+// True in every thread of the block that is the last of `total` to arrive.
+__device__ __forceinline__ bool last_to_arrive(uint32_t* counter, uint32_t total)
+{
+    __shared__ bool last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == total - 1;
+    __syncthreads();
+    if (last) __threadfence();
+    return last;
+}
+
+// Inclusive scan of one value per thread across the wave (lanes shift by 1, 2,
+// 4, ... 32).
+__device__ __forceinline__ int64_t wave_scan(int64_t v)
+{
+    const int lane = (int)(threadIdx.x & 63);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t u = __shfl_up(v, off, 64);
+        if (lane >= off) v += u;
+    }
+    return v;
+}
+
+// Merge of a small single-window launch inside the histogram kernel: the last
+// workgroup to finish (all partial rows written and fenced) sums the rows into
+// int64 counts in its LDS (the histogram's space, free after the flush), scans
+// them and writes the ECC to out[0..width), then re-arms the counter.  It saves
+// the two merge launches where the rows are few enough for one workgroup.
+__device__ __forceinline__ void fused_merge_scan(int32_t* hist, const int32_t* partials, int width, int64_t* out,
+                                                 uint32_t* counter)
+{
+    if (!last_to_arrive(counter, gridDim.x)) return;
+    __shared__ int64_t wave_tot[kMaxWaves];
+    const int bd = (int)blockDim.x, t = (int)threadIdx.x;
+    uint64_t* acc = reinterpret_cast<uint64_t*>(hist);
+    for (int j = t; j < width; j += bd) acc[j] = 0;
+    __syncthreads();
+    // the rows as one flat array, 16 loads in flight per thread; element i adds
+    // to bin i mod width (tracked incrementally)
+    constexpr int U = 16;
+    const int64_t total = (int64_t)gridDim.x * width;
+    const int step = bd % width;
+    int j = t % width;
+    for (int64_t i0 = t; i0 < total; i0 += (int64_t)bd * U) {
+        int32_t x[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int64_t i = i0 + (int64_t)k * bd;
+            x[k] = i < total ? partials[i] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (x[k] != 0) atomicAdd((unsigned long long*)&acc[j], (unsigned long long)(int64_t)x[k]);
+            j += step;
+            if (j >= width) j -= width;
+        }
+    }
+    __syncthreads();
+    // each thread scans a contiguous run of bins, then adds the runs before it
+    const int per = (width + bd - 1) / bd;
+    const int j0 = min(t * per, width), j1 = min(j0 + per, width);
+    int64_t run = 0;
+    for (int b = j0; b < j1; ++b) {
+        run += (int64_t)acc[b];
+        acc[b] = (uint64_t)run;
+    }
+    const int64_t inc = wave_scan(run);
+    const int w = t >> 6;
+    if ((t & 63) == 63) wave_tot[w] = inc;
+    __syncthreads();
+    int64_t before = inc - run;
+    for (int k = 0; k < w; ++k) before += wave_tot[k];
+    for (int b = j0; b < j1; ++b) out[b] = (int64_t)acc[b] + before;
+    if (t == 0) atomicExch(counter, 0u);
+}
+
 // ------------------------------------------------------------ main kernels
 
 __device__ __forceinline__ void zero_hist(int32_t* hist, int width)

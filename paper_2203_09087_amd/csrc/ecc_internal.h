@@ -112,9 +112,13 @@ struct EccLaunch {
     int32_t* partials;             // [grid][width] workgroup histograms
     int32_t flush_add;             // add the workgroup histogram to its partial row (else write it)
     int32_t flush_sign;            // +1, or -1: the histogram enters its row negated
-    int64_t* out;                  // the caller's output (VCEC window, zeroed by block 0)
-    uint32_t* counter;             // the merge's counter (unused by the main kernels)
+    int64_t* out;                  // the caller's output
+    uint32_t* counter;             // counters[0]: the merge's; counters[1]: the fused merge's
+    int32_t fused;                 // one window, few rows: the last workgroup merges and scans into out
 };
+// Partial-row words (grid x window) up to which the histogram kernel merges its
+// own rows (fused_merge_scan) instead of launching the two merge kernels.
+constexpr int64_t kFusedMergeWords = int64_t(1) << 16;
 
 // ---------------------------------------------------------------- batches
 

@@ -17,7 +17,7 @@ using namespace dev;
 template <int DT, int CONS, bool WIN, bool PAIR>
 __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU_3D))) void k_ecc_3d(EccLaunch L)
 {
-    __shared__ int32_t hist[kLdsWords];
+    __shared__ __align__(16) int32_t hist[kLdsWords];
     const BinParams P = L.params_dev ? *L.params_dev : L.params;
     const HistRef H = hist_ref(hist, L.bin_lo, L.width);
     zero_hist(hist, L.width);
@@ -30,13 +30,14 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
         run_brick_3d<DT, CONS, WIN, PAIR>(L, P, H, chunk, brick % nxc, (brick / nxc) % nyb, brick / (nxc * nyb),
                                           wave_id());
     flush_hist(hist, L.partials + (size_t)blockIdx.x * (size_t)L.width, L.width, L.flush_add != 0, L.flush_sign);
+    if (L.fused) fused_merge_scan(hist, L.partials, L.width, L.out, L.counter + 1);
 }
 
 // 2D images.  A workgroup brick is a contiguous x-chunk x L.depth rows.
 template <int DT, int CONS, bool WIN>
 __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU_2D))) void k_ecc_2d(EccLaunch L)
 {
-    __shared__ int32_t hist[kLdsWords];
+    __shared__ __align__(16) int32_t hist[kLdsWords];
     const BinParams P = L.params_dev ? *L.params_dev : L.params;
     const HistRef H = hist_ref(hist, L.bin_lo, L.width);
     zero_hist(hist, L.width);
@@ -47,6 +48,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
     for (uint32_t brick = blockIdx.x; brick < nbricks; brick += gridDim.x)
         run_brick_2d<DT, CONS, WIN>(L, P, H, chunk, brick % nxc, brick / nxc, wave_id());
     flush_hist(hist, L.partials + (size_t)blockIdx.x * (size_t)L.width, L.width, L.flush_add != 0, L.flush_sign);
+    if (L.fused) fused_merge_scan(hist, L.partials, L.width, L.out, L.counter + 1);
 }
 
 }  // namespace

@@ -73,31 +73,6 @@ __global__ __launch_bounds__(kThreads) void k_params(const uint32_t* mm, int blo
 //                   block to finish prefix-sums out[0..nbins) and re-arms its
 //                   counter (histograms wider than one LDS window).
 
-// True in every thread of the block that is the last of `total` to arrive.
-__device__ __forceinline__ bool last_to_arrive(uint32_t* counter, uint32_t total)
-{
-    __shared__ bool last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == total - 1;
-    __syncthreads();
-    if (last) __threadfence();
-    return last;
-}
-
-// Inclusive scan of one value per thread across the wave (lanes shift by 1, 2,
-// 4, ... 32).
-__device__ __forceinline__ int64_t wave_scan(int64_t v)
-{
-    const int lane = (int)(threadIdx.x & 63);
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int64_t u = __shfl_up(v, off, 64);
-        if (lane >= off) v += u;
-    }
-    return v;
-}
-
 // Sum of one value per thread across the wave, in every lane.
 __device__ __forceinline__ int64_t wave_sum(int64_t v)
 {
