@@ -204,13 +204,17 @@ ecc_status ecc_smooth13(ecc_ctx* ctx, const float* in, float* out, int64_t n1, i
 
 /* Launch shape of the single-image kernel: waves per workgroup (a workgroup
  * covers waves * 63 consecutive position columns), rows (2D) or planes (3D) per
- * workgroup brick, and resident workgroups per CU aimed for.  `ms` is the mean
- * time of one call measured by ecc_autotune. */
+ * workgroup brick, resident workgroups per CU aimed for, and `window`, the bins
+ * one pass counts in LDS (Sec. 4.3's block-shared histogram; fewer than nbins
+ * makes several passes over the image, each with less LDS; 0: all of nbins up to
+ * 4096).  `ms` is the mean time of one call measured by ecc_autotune. */
 typedef struct {
     int32_t waves;
     int32_t wgs_per_cu;
     int64_t depth;
     double ms;
+    int32_t window;
+    int32_t reserved;   /* 0 */
 } ecc_launch_shape;
 
 /* Times a set of launch shapes for the image `img` on hip_stream (`reps` calls
@@ -233,7 +237,8 @@ ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32
  * ignored.  The result of a call does not depend on the shape.  Enqueues
  * nothing.  img->data and img->out are not read; img->ndim is 2 or 3.
  * Errors: ECC_ERR_INVALID_ARG (null pointer, an invalid descriptor as for
- * ecc_compute_ex, waves above 9, wgs_per_cu above 16, depth above 4096). */
+ * ecc_compute_ex, waves above 9, wgs_per_cu above 16, depth above 4096, window
+ * above 4096). */
 ecc_status ecc_set_launch_shape(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, const ecc_launch_shape* shape);
 
 /* A planned batch (Sec. 5's many-files workload, kept on the device): the

@@ -292,6 +292,7 @@ struct Sizes {
     int waves;
     int64_t depth;
     int32_t window;
+    uint32_t hist_stride, sentinel, lds_bytes;   // LDS layout of the histogram kernel
     size_t off_params, off_counters, off_mm, off_level2, off_partials, total;
 };
 
@@ -343,15 +344,20 @@ Sizes plan_sizes(const ecc_ctx* ctx, const Job& j, int32_t nbins, const ecc_laun
         s.depth = (d + ecc::kChunk2 - 1) / ecc::kChunk2 * ecc::kChunk2;
     }
     const int64_t bricks = ecc::wg_bricks(j.ndim, cons, j.g, s.waves, s.depth);
-    const bool windowed = nbins > ecc::kMaxLdsBins;
+    // bins per LDS pass: all of them up to kMaxLdsBins, or fewer when tuned so
+    s.window = std::min<int32_t>(nbins, ecc::kMaxLdsBins);
+    if (tuned && tuned->window > 0) s.window = std::min<int32_t>(s.window, tuned->window);
+    const bool windowed = s.window < nbins;
+    s.hist_stride = ecc::lds_stride(s.window);
+    s.sentinel = ecc::lds_sentinel(nbins);
+    s.lds_bytes = 4u * ecc::lds_words(s.window, windowed, s.sentinel);
     int want_per_cu = j.ndim == 3 ? ECC_MAX_WGS_PER_CU_3D : ECC_MAX_WGS_PER_CU_2D;
     if (tuned && tuned->wgs_per_cu > 0) want_per_cu = tuned->wgs_per_cu;
-    const int per_cu = std::min(want_per_cu,
-                                ecc::resident_wgs_per_cu(j.ndim, j.dtype, ctx->construction, windowed, s.waves));
+    const int per_cu = std::min(want_per_cu, ecc::resident_wgs_per_cu(j.ndim, j.dtype, ctx->construction, windowed,
+                                                                      s.waves, s.lds_bytes));
     int64_t grid = std::min<int64_t>(bricks, (int64_t)ctx->cu_count * per_cu);
     grid = std::max<int64_t>(grid, std::min<int64_t>(bricks, (j.nvox >> 27) + 1));
     s.grid = (int)std::max<int64_t>(grid, 1);
-    s.window = std::min<int32_t>(nbins, ecc::kMaxLdsBins);
     s.off_counters = 0;   // fixed place, shared with the batch layout (never overwritten)
     s.off_params = kCounterBytes;
     s.off_mm = s.off_params + align_up(sizeof(ecc::BinParams));
@@ -480,6 +486,9 @@ ecc_status enqueue_hist(ecc_ctx* ctx, char* base, const Job& j, int32_t nbins, h
     L.out = j.out;
     L.counter = counters;
     L.fused = 0;
+    L.hist_stride = sz.hist_stride;
+    L.sentinel = sz.sentinel;
+    L.lds_bytes = sz.lds_bytes;
     hipError_t e;
     if (pass_only) {
         // one window, histogram kernel only: its rows are merged by a later call
@@ -842,6 +851,9 @@ ecc_status launch_batch_kernels(ecc_ctx* ctx, const BatchTables& T, char* d, boo
     B.nbins = T.nbins;
     B.waves = ecc::kBatchWaves;
     B.windowed = T.window < T.nbins ? 1 : 0;
+    B.hist_stride = ecc::lds_stride(T.window);
+    B.sentinel = ecc::lds_sentinel(T.nbins);
+    B.lds_bytes = 4u * ecc::lds_words(T.window, B.windowed != 0, B.sentinel);
     hipError_t e;
     if (!T.pieces.empty()) {
         if (reset_mm && (e = ecc::launch_mm_init(B.mm, T.count, stream)) != hipSuccess)
@@ -1414,9 +1426,11 @@ ecc_status ecc_set_launch_shape(ecc_ctx* ctx, const ecc_image* img, int32_t nbin
     if (!ctx) return ECC_ERR_INVALID_ARG;
     ctx->err.clear();
     if (!img || !shape) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_set_launch_shape: null pointer");
-    if (shape->waves > ecc::kMaxWaves || shape->wgs_per_cu > 16 || shape->depth > 4096)
+    if (shape->waves > ecc::kMaxWaves || shape->wgs_per_cu > 16 || shape->depth > 4096 ||
+        shape->window > ecc::kMaxLdsBins)
         return fail(ctx, ECC_ERR_INVALID_ARG,
-                    "ecc_set_launch_shape: waves must be at most 9, wgs_per_cu at most 16, depth at most 4096");
+                    "ecc_set_launch_shape: waves must be at most 9, wgs_per_cu at most 16, depth at most 4096, "
+                    "window at most 4096");
     Job j;
     ecc_status st = validate(ctx, *img, nbins, "ecc_set_launch_shape", &j);
     if (st != ECC_OK) return st;
@@ -1446,13 +1460,15 @@ ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32
     const Sizes def = plan_sizes(ctx, j, nbins);
     const int64_t cols = (ecc::axis_positions(j.g.n2, ctx->construction) + ecc::kLaneCols - 1) / ecc::kLaneCols;
     std::vector<ecc_launch_shape> cand;
-    auto add = [&](int waves, int64_t depth, int wgs) {
+    auto add = [&](int waves, int64_t depth, int wgs, int32_t window = 0) {
         ecc_launch_shape c = {};
         c.waves = (int32_t)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(waves, ecc::kMaxWaves), cols));
         c.depth = std::max<int64_t>(1, depth);
         c.wgs_per_cu = wgs;
+        c.window = window;
         for (const auto& e : cand)
-            if (e.waves == c.waves && e.depth == c.depth && e.wgs_per_cu == c.wgs_per_cu) return;
+            if (e.waves == c.waves && e.depth == c.depth && e.wgs_per_cu == c.wgs_per_cu && e.window == c.window)
+                return;
         cand.push_back(c);
     };
     const int def_wgs = j.ndim == 3 ? ECC_MAX_WGS_PER_CU_3D : ECC_MAX_WGS_PER_CU_2D;
@@ -1462,6 +1478,11 @@ ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32
             add(def.waves, def.depth * dm / 2, wgs);
             if (def.waves > 4) add((def.waves + 1) / 2, def.depth * dm / 2, wgs);
         }
+    // the bins-per-pass split: half the window (two passes, half the LDS each)
+    // at the default shape and with more workgroups per CU, which the smaller
+    // LDS allows
+    if (def.window >= 2048)
+        for (int wgs : {def_wgs, def_wgs + 2}) add(def.waves, def.depth, wgs, def.window / 2);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e;
     if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {

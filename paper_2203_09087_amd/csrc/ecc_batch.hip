@@ -61,8 +61,8 @@ template <int DT, int CONS, bool WIN, bool PAIRS>
 __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU_3D)))
 void k_ecc_batch(BatchLaunch B)
 {
-    __shared__ int32_t hist[kLdsWords];
-    const HistRef H = hist_ref(hist, B.bin_lo, B.width);
+    extern __shared__ __align__(16) int32_t hist[];
+    const HistRef H = hist_ref(hist, B.bin_lo, B.width, B.hist_stride, B.sentinel);
     const int W = (int)(blockDim.x >> 6), wave = wave_id();
     const int s_end = B.wg_seg[blockIdx.x + 1];
     for (int si = B.wg_seg[blockIdx.x]; si < s_end; ++si) {
@@ -85,7 +85,7 @@ void k_ecc_batch(BatchLaunch B)
         L.z_base = 0;
         L.n0_global = L.g.n0;
         const int ndim = (int)uniform_u32((uint32_t)I.ndim);
-        zero_hist(hist, B.width);
+        zero_hist(H, B.width);
         // the workgroup's waves form W / wpb teams of wpb waves; team t takes
         // bricks b0 + t, b0 + t + teams, ... (waves beyond the last team idle)
         const int wpb = uniform_u32((uint32_t)I.wpb);
@@ -107,7 +107,7 @@ void k_ecc_batch(BatchLaunch B)
                     run_brick_2d<DT, CONS, WIN>(L, P, H, chunk, xc, (uint32_t)row, xw);
             }
         }
-        flush_hist(hist, B.partials + (size_t)uniform_u32((uint32_t)S.slot) * (size_t)B.width, B.width, false,
+        flush_hist(H, B.partials + (size_t)uniform_u32((uint32_t)S.slot) * (size_t)B.width, B.width, false,
                    (int)uniform_u32((uint32_t)I.sign));
     }
 }
@@ -145,9 +145,10 @@ template <int DT, int CONS, bool PAIRS>
 hipError_t launch_batch_p(const BatchLaunch& B, hipStream_t s)
 {
     if (B.windowed)
-        hipLaunchKernelGGL((k_ecc_batch<DT, CONS, true, PAIRS>), dim3(B.grid), dim3(B.waves * 64), 0, s, B);
+        hipLaunchKernelGGL((k_ecc_batch<DT, CONS, true, PAIRS>), dim3(B.grid), dim3(B.waves * 64), B.lds_bytes, s, B);
     else
-        hipLaunchKernelGGL((k_ecc_batch<DT, CONS, false, PAIRS>), dim3(B.grid), dim3(B.waves * 64), 0, s, B);
+        hipLaunchKernelGGL((k_ecc_batch<DT, CONS, false, PAIRS>), dim3(B.grid), dim3(B.waves * 64), B.lds_bytes, s,
+                           B);
     return hipGetLastError();
 }
 

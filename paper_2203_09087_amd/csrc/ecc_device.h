@@ -50,15 +50,15 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
 // Sentinel key: above every key, below 2^31, and such that OR-ing it into any
-// key gives the sentinel (keys are bin << 2 with bins below 4096 in one LDS
-// window, below 65535 with windows).  With one window it is also the byte
-// address of a spare LDS word that absorbs the counts of cells that do not
-// exist (a vertex cell reaching outside the image, a top face with no voxel
-// inside), so they need no masking.
+// key gives the sentinel.  With windows it is the constant below (keys are
+// bin << 2 with bins below 65535); with one window it is the launch's
+// (lds_sentinel: bins below nbins), which is also the byte address of a spare
+// LDS word that absorbs the counts of cells that do not exist, so they need no
+// masking.
 template <bool WIN>
-__device__ __forceinline__ constexpr uint32_t sentinel_key()
+__device__ __forceinline__ uint32_t sentinel_key(uint32_t one_window)
 {
-    return WIN ? 0x3FFFCu : 0x7FFCu;
+    return WIN ? 0x3FFFCu : one_window;
 }
 
 // ------------------------------------------------------------------ binning
@@ -264,17 +264,21 @@ __device__ __forceinline__ uint32_t op_right(uint32_t a)
 }
 
 struct HistRef {
-    int32_t* hist;     // LDS: kHistCopies copies of kMaxLdsBins counters and spare words
+    int32_t* hist;     // LDS: kHistCopies copies of the window's counters (`stride` words apart)
+                       // and spare words (lds_words)
     uint32_t key_lo;   // key of the first bin of the window (windowed launches)
     uint32_t key_span; // keys in the window: also the byte offset of the spare word that
                        // absorbs keys outside the window (windowed launches)
     uint32_t copy;     // byte offset of this lane's copy (odd lanes: the second)
+    uint32_t stride;   // words from one copy to the next
+    uint32_t sm;       // the sentinel key of a one-window launch
 };
 
-__device__ __forceinline__ HistRef hist_ref(int32_t* hist, int32_t bin_lo, int32_t width)
+__device__ __forceinline__ HistRef hist_ref(int32_t* hist, int32_t bin_lo, int32_t width, uint32_t stride,
+                                            uint32_t sm)
 {
     return HistRef{hist, (uint32_t)bin_lo << kKeyShift, (uint32_t)width << kKeyShift,
-                   (__lane_id() & (kHistCopies - 1)) * (uint32_t)(kCopyWords * 4)};
+                   (__lane_id() & (kHistCopies - 1)) * stride * 4u, stride, sm};
 }
 
 // Adds v to the counter of `key` in this lane's copy.  One window: the key is the
@@ -386,30 +390,30 @@ __device__ __forceinline__ void fused_merge_scan(int32_t* hist, const int32_t* p
 
 // ------------------------------------------------------------ main kernels
 
-__device__ __forceinline__ void zero_hist(int32_t* hist, int width)
+__device__ __forceinline__ void zero_hist(const HistRef& H, int width)
 {
     for (int c = 0; c < kHistCopies; ++c)
-        for (int j = threadIdx.x; j < width; j += blockDim.x) hist[c * kCopyWords + j] = 0;
+        for (int j = threadIdx.x; j < width; j += blockDim.x) H.hist[c * H.stride + j] = 0;
     __syncthreads();
 }
 
 // The workgroup's count of bin j of the window: the sum of its copies.
-__device__ __forceinline__ int32_t hist_value(const int32_t* hist, int j)
+__device__ __forceinline__ int32_t hist_value(const HistRef& H, int j)
 {
-    int32_t t = hist[j];
-    for (int c = 1; c < kHistCopies; ++c) t += hist[c * kCopyWords + j];
+    int32_t t = H.hist[j];
+    for (int c = 1; c < kHistCopies; ++c) t += H.hist[c * H.stride + j];
     return t;
 }
 
 // Writes the workgroup histogram (negated with sign -1) to dst[0..width), or
 // adds it to what dst holds (add).
-__device__ __forceinline__ void flush_hist(const int32_t* hist, int32_t* dst, int width, bool add = false,
+__device__ __forceinline__ void flush_hist(const HistRef& H, int32_t* dst, int width, bool add = false,
                                            int sign = 1)
 {
     __syncthreads();
     if (!add) {
         for (int j = threadIdx.x; j < width; j += blockDim.x) {
-            const int32_t t = hist_value(hist, j);
+            const int32_t t = hist_value(H, j);
             dst[j] = sign < 0 ? -t : t;
         }
         return;
@@ -426,7 +430,7 @@ __device__ __forceinline__ void flush_hist(const int32_t* hist, int32_t* dst, in
         for (int k = 0; k < R; ++k) {
             const int j = j0 + k * step;
             if (j < width) {
-                const int32_t t = hist_value(hist, j);
+                const int32_t t = hist_value(H, j);
                 dst[j] = old[k] + (sign < 0 ? -t : t);
             }
         }
@@ -506,7 +510,7 @@ __device__ __forceinline__ void brick_3d(const EccLaunch& L, const BinParams& P,
                                          int r_lo, int r_hi)
 {
     constexpr int NR = kRows3;
-    constexpr uint32_t SM = sentinel_key<WIN>();
+    const uint32_t SM = sentinel_key<WIN>(H.sm);
     using T = typename ValT<DT>::T;
     const uint32_t n0 = (uint32_t)L.g.n0;
     const int64_t n1 = L.g.n1, n2 = L.g.n2;
@@ -692,7 +696,7 @@ __device__ __forceinline__ void brick_2d(const void* data, uint32_t n1, int64_t 
     constexpr uint32_t CH = kChunk2;
     constexpr uint32_t kGroup2 = 8;   // rows whose adds share one lane mask
     static_assert(CH % kGroup2 == 0, "row chunks hold whole groups");
-    constexpr uint32_t SM = sentinel_key<WIN>();
+    const uint32_t SM = sentinel_key<WIN>(H.sm);
     constexpr int S0 = CONS == CONS_VERTEX ? 1 : -1;
     using T = typename ValT<DT>::T;
     const T* __restrict__ img = (const T*)data;
@@ -806,14 +810,14 @@ struct WaveCols {
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
 template <bool WIN>
-__device__ __forceinline__ WaveCols wave_cols(int64_t x0, int wave, int64_t n2)
+__device__ __forceinline__ WaveCols wave_cols(int64_t x0, int wave, int64_t n2, uint32_t sm)
 {
     WaveCols w;
     const int64_t first = x0 + (int64_t)wave * kLaneCols;
     w.active = first < n2;
     const int64_t x = first + (int64_t)lane_id();
     const bool x_ok = x >= 0 && x < n2;
-    w.oob = x_ok ? 0u : sentinel_key<WIN>();
+    w.oob = x_ok ? 0u : sentinel_key<WIN>(sm);
     w.own = ballot(x < n2) & kOwnLanes;
     w.xo = (uint32_t)(x < 0 ? 0 : (x >= n2 ? n2 - 1 : x));
     return w;
@@ -833,7 +837,7 @@ __device__ __forceinline__ void run_brick_3d(const EccLaunch& L, const BinParams
     constexpr int64_t org = CONS == CONS_TOP ? -1 : 0;
     using T = typename ValT<DT>::T;
     const int64_t n1 = L.g.n1, n2 = L.g.n2;
-    const WaveCols w = wave_cols<WIN>(org + (int64_t)xc * chunk, xw, n2);
+    const WaveCols w = wave_cols<WIN>(org + (int64_t)xc * chunk, xw, n2, H.sm);
     if (!w.active) return;
     const uint32_t xob = w.xo * (uint32_t)sizeof(T);
     const int64_t ys = org + (int64_t)yb * NR;
@@ -862,7 +866,7 @@ __device__ __forceinline__ void run_brick_2d(const EccLaunch& L, const BinParams
     yb = uniform_u32(yb);
     constexpr int64_t org = CONS == CONS_TOP ? -1 : 0;
     const int64_t n1 = L.g.n1, n2 = L.g.n2;
-    const WaveCols w = wave_cols<WIN>(org + (int64_t)xc * chunk, xw, n2);
+    const WaveCols w = wave_cols<WIN>(org + (int64_t)xc * chunk, xw, n2, H.sm);
     if (!w.active) return;
     const uint32_t y0 = yb * (uint32_t)L.depth;
     const uint32_t yend = (int64_t)y0 + L.depth < n1 ? y0 + (uint32_t)L.depth : (uint32_t)n1;

@@ -70,13 +70,31 @@ constexpr int kKeyShift = 2;
 // odd lanes of every wave: equal keys of neighbouring lanes (frequent in smooth
 // images) then fall into different copies, and the second copy starts 8 words
 // further in the bank cycle, so they do not collide in one LDS bank.  The merge
-// adds the copies.
+// adds the copies.  The LDS a launch takes is sized to its window (dynamic
+// shared memory), so a histogram of few bins leaves room for more workgroups.
 constexpr int kHistCopies = 2;
-constexpr int kCopyWords = kMaxLdsBins + 8;   // stride of the copies, in words
-// LDS words of a workgroup histogram: each copy's counters, then spare words up
-// to the copy's one-window sentinel word (byte 0x7FFC of the copy), which absorbs
-// the counts of cells that do not exist.
-constexpr int kLdsWords = kCopyWords * (kHistCopies - 1) + 8192;
+// Words from one copy to the next for a window of `width` bins (a multiple of 32
+// plus 8: the 8-bank offset; with windows the word after the window is spare).
+inline __host__ __device__ uint32_t lds_stride(int32_t width)
+{
+    return ((uint32_t)width + 31u) / 32u * 32u + 8u;
+}
+// Sentinel key of a one-window launch of nbins bins: 4 (2^k - 1) with 2^k > nbins,
+// so it is above every key (4 * bin, bin < nbins) and OR-ing it into a key gives it.
+inline __host__ __device__ uint32_t lds_sentinel(int32_t nbins)
+{
+    uint32_t p = 1;
+    while (p <= (uint32_t)nbins) p <<= 1;
+    return 4u * (p - 1u);
+}
+// LDS words of a workgroup histogram: the copies and, with one window, spare
+// words up to the second copy's sentinel word, which absorbs the counts of
+// cells that do not exist (4096 bins: 12,296 words).
+inline __host__ __device__ uint32_t lds_words(int32_t width, bool windowed, uint32_t sentinel)
+{
+    const uint32_t stride = lds_stride(width);
+    return windowed ? kHistCopies * stride : stride * (kHistCopies - 1) + sentinel / 4u + 1u;
+}
 // Positions a wave owns along x (lanes 0..62; lane 63 only supplies lane 62's
 // right neighbour).
 constexpr int kLaneCols = 63;
@@ -115,6 +133,9 @@ struct EccLaunch {
     int64_t* out;                  // the caller's output
     uint32_t* counter;             // counters[0]: the merge's; counters[1]: the fused merge's
     int32_t fused;                 // one window, few rows: the last workgroup merges and scans into out
+    uint32_t hist_stride;          // LDS words between the histogram copies (lds_stride(width))
+    uint32_t sentinel;             // one-window sentinel key (lds_sentinel(nbins))
+    uint32_t lds_bytes;            // dynamic LDS of the launch (lds_words * 4)
 };
 // Partial-row words (grid x window) up to which the histogram kernel merges its
 // own rows (fused_merge_scan) instead of launching the two merge kernels.
@@ -173,6 +194,7 @@ struct BatchLaunch {
     int32_t nbins, bin_lo, width, windowed;
     int32_t grid, waves;
     int32_t pairs;              // the launch counts pair volumes (4D images)
+    uint32_t hist_stride, sentinel, lds_bytes;   // LDS layout, as in EccLaunch
 };
 
 // Launchers (ecc_batch.hip).
@@ -229,7 +251,8 @@ hipError_t launch_mm_fold(const uint32_t* mm, int blocks, uint32_t* acc, bool fi
 
 // Workgroup bricks of an image for a launch shape.
 int64_t wg_bricks(int ndim, int construction, const Geom& g, int waves, int64_t depth);
-// Workgroups of the main kernel variant (of `waves` waves) that fit on one CU.
-int resident_wgs_per_cu(int ndim, int dtype, int construction, bool windowed, int waves);
+// Workgroups of the main kernel variant (of `waves` waves, lds_bytes of dynamic
+// LDS) that fit on one CU.
+int resident_wgs_per_cu(int ndim, int dtype, int construction, bool windowed, int waves, uint32_t lds_bytes);
 
 }  // namespace ecc

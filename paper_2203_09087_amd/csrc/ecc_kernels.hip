@@ -2,6 +2,10 @@
 // and 3D) and their launchers.  The method and its mapping to the hardware are
 // described in ecc_device.h; the min/max pass and the merge are in
 // ecc_reduce.hip.
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "ecc_device.h"
 
 namespace ecc {
@@ -17,10 +21,10 @@ using namespace dev;
 template <int DT, int CONS, bool WIN, bool PAIR>
 __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU_3D))) void k_ecc_3d(EccLaunch L)
 {
-    __shared__ __align__(16) int32_t hist[kLdsWords];
+    extern __shared__ __align__(16) int32_t hist[];
     const BinParams P = L.params_dev ? *L.params_dev : L.params;
-    const HistRef H = hist_ref(hist, L.bin_lo, L.width);
-    zero_hist(hist, L.width);
+    const HistRef H = hist_ref(hist, L.bin_lo, L.width, L.hist_stride, L.sentinel);
+    zero_hist(H, L.width);
     const int64_t chunk = (int64_t)(blockDim.x >> 6) * kLaneCols;
     const uint32_t nxc = (uint32_t)((axis_positions(L.g.n2, CONS) + chunk - 1) / chunk);
     const uint32_t nyb = (uint32_t)((axis_positions(L.g.n1, CONS) + kRows3 - 1) / kRows3);
@@ -29,7 +33,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
     for (uint32_t brick = blockIdx.x; brick < nbricks; brick += gridDim.x)
         run_brick_3d<DT, CONS, WIN, PAIR>(L, P, H, chunk, brick % nxc, (brick / nxc) % nyb, brick / (nxc * nyb),
                                           wave_id());
-    flush_hist(hist, L.partials + (size_t)blockIdx.x * (size_t)L.width, L.width, L.flush_add != 0, L.flush_sign);
+    flush_hist(H, L.partials + (size_t)blockIdx.x * (size_t)L.width, L.width, L.flush_add != 0, L.flush_sign);
     if (L.fused) fused_merge_scan(hist, L.partials, L.width, L.out, L.counter + 1);
 }
 
@@ -37,17 +41,17 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
 template <int DT, int CONS, bool WIN>
 __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU_2D))) void k_ecc_2d(EccLaunch L)
 {
-    __shared__ __align__(16) int32_t hist[kLdsWords];
+    extern __shared__ __align__(16) int32_t hist[];
     const BinParams P = L.params_dev ? *L.params_dev : L.params;
-    const HistRef H = hist_ref(hist, L.bin_lo, L.width);
-    zero_hist(hist, L.width);
+    const HistRef H = hist_ref(hist, L.bin_lo, L.width, L.hist_stride, L.sentinel);
+    zero_hist(H, L.width);
     const int64_t chunk = (int64_t)(blockDim.x >> 6) * kLaneCols;
     const uint32_t nxc = (uint32_t)((axis_positions(L.g.n2, CONS) + chunk - 1) / chunk);
     const uint32_t nyb = (uint32_t)((L.g.n1 + L.depth - 1) / L.depth);
     const uint32_t nbricks = nxc * nyb;
     for (uint32_t brick = blockIdx.x; brick < nbricks; brick += gridDim.x)
         run_brick_2d<DT, CONS, WIN>(L, P, H, chunk, brick % nxc, brick / nxc, wave_id());
-    flush_hist(hist, L.partials + (size_t)blockIdx.x * (size_t)L.width, L.width, L.flush_add != 0, L.flush_sign);
+    flush_hist(H, L.partials + (size_t)blockIdx.x * (size_t)L.width, L.width, L.flush_add != 0, L.flush_sign);
     if (L.fused) fused_merge_scan(hist, L.partials, L.width, L.out, L.counter + 1);
 }
 
@@ -68,11 +72,11 @@ template <int NDIM, int DT, int CONS, bool WIN>
 static hipError_t launch_t(const EccLaunch& L, hipStream_t s)
 {
     if constexpr (NDIM == 2)
-        hipLaunchKernelGGL((k_ecc_2d<DT, CONS, WIN>), dim3(L.grid), dim3(L.waves * 64), 0, s, L);
+        hipLaunchKernelGGL((k_ecc_2d<DT, CONS, WIN>), dim3(L.grid), dim3(L.waves * 64), L.lds_bytes, s, L);
     else if (L.data2)
-        hipLaunchKernelGGL((k_ecc_3d<DT, CONS, WIN, true>), dim3(L.grid), dim3(L.waves * 64), 0, s, L);
+        hipLaunchKernelGGL((k_ecc_3d<DT, CONS, WIN, true>), dim3(L.grid), dim3(L.waves * 64), L.lds_bytes, s, L);
     else
-        hipLaunchKernelGGL((k_ecc_3d<DT, CONS, WIN, false>), dim3(L.grid), dim3(L.waves * 64), 0, s, L);
+        hipLaunchKernelGGL((k_ecc_3d<DT, CONS, WIN, false>), dim3(L.grid), dim3(L.waves * 64), L.lds_bytes, s, L);
     return hipGetLastError();
 }
 
@@ -133,18 +137,21 @@ static const void* kernel_d(int dtype, int cons, bool win)
     }
 }
 
-int resident_wgs_per_cu(int ndim, int dtype, int construction, bool windowed, int waves)
+int resident_wgs_per_cu(int ndim, int dtype, int construction, bool windowed, int waves, uint32_t lds_bytes)
 {
-    static int cache[2][3][2][2][kMaxWaves + 1];   // 0 = not yet queried
-    int& c = cache[ndim == 3][dtype][construction == CONS_TOP][windowed][waves];
-    if (c == 0) {
-        const void* k = ndim == 2 ? kernel_d<2>(dtype, construction, windowed)
-                                  : kernel_d<3>(dtype, construction, windowed);
-        int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, waves * 64, 0) != hipSuccess || n < 1) n = 1;
-        c = n;
-    }
-    return c;
+    // the answer only depends on the LDS in steps of the allocation granule
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int, int, uint32_t>, int> cache;
+    const uint32_t lds = (lds_bytes + 511u) / 512u * 512u;
+    const auto key = std::make_tuple(ndim == 3, dtype, construction == CONS_TOP, windowed ? 1 : 0, waves, lds);
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    const void* k = ndim == 2 ? kernel_d<2>(dtype, construction, windowed) : kernel_d<3>(dtype, construction, windowed);
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, waves * 64, lds) != hipSuccess || n < 1) n = 1;
+    cache[key] = n;
+    return n;
 }
 
 

@@ -477,12 +477,37 @@ def test_set_launch_shape(oracle_mod):
             got = ctx.compute(d, 4096, value_range=(-2.0, 2.0))
             torch.cuda.synchronize()
             assert np.array_equal(got.cpu().numpy(), want), (waves, wgs, depth)
-        for bad in ({"waves": 10}, {"wgs_per_cu": 17}, {"depth": 4097}):
+        for bad in ({"waves": 10}, {"wgs_per_cu": 17}, {"depth": 4097}, {"window": 4097}):
             with pytest.raises(ecc.EccError):
                 ctx.set_launch_shape(d, 4096, **bad)
         got = ctx.compute(d, 4096, value_range=(-2.0, 2.0))
         torch.cuda.synchronize()
         assert np.array_equal(got.cpu().numpy(), want)
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("cons", CONS)
+def test_bins_per_pass_split(oracle_mod, cons):
+    """A launch shape whose window holds fewer bins than the histogram (several
+    passes over the image, each with a smaller LDS histogram) gives the oracle's
+    ECC, in 2D and 3D, for the default and the fused single-launch merge."""
+    from paper_2203_09087_amd import ecc
+    rng = np.random.default_rng(52)
+    cases = [(rng.standard_normal((20, 70, 300)).astype(np.float32), 4096, (-2.0, 2.0), (2048, 1000, 4096, 1)),
+             (rng.integers(0, 60000, size=(300, 700)).astype(np.uint16), 2500, (0, 59999), (1000, 2048, 64)),
+             (rng.integers(0, 256, size=(9, 40, 50)).astype(np.uint8), 256, (0, 255), (100, 255, 256))]
+    ctx = ecc.Context(0, cons)
+    try:
+        for img, nbins, r, windows in cases:
+            want = oracle_mod.ecc(img, nbins, cons, value_range=r)
+            d = to_dev(img)
+            for w in windows:
+                say(f"case: {cons} window={w} nbins={nbins} shape={img.shape}")
+                ctx.set_launch_shape(d, nbins, window=w)
+                got = ctx.compute(d, nbins, value_range=r)
+                torch.cuda.synchronize()
+                assert np.array_equal(got.cpu().numpy(), want), (img.shape, nbins, w)
     finally:
         ctx.close()
 
