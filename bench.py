@@ -65,6 +65,9 @@ PROFILES = {
     "batch": {"kernel": "k_ecc_batch", "file": "k_ecc_batch_u8_512images", "per_call": 1,
               "what": "the uneven 512-image uint8 batch (seed 5), vertex filtration, 256 bins, default batch shape",
               "shape": None},
+    "c2": {"kernel": "k_ecc_3d<0, 0, false, false>", "file": "k_ecc_3d_u8_256cubed", "per_call": 1,
+           "what": "256^3 uint8 smoothed noise (sigma 2, seed 2), vertex filtration, 256 bins over [0, 255]",
+           "shape": {"waves": 5, "wgs_per_cu": 4, "depth": 16}},
     "4d": {"kernel": "k_ecc_3d<2, 0, false, true>", "file": "k_ecc_3d_pair_f32_8x256cubed", "per_call": 7,
            "what": "the 7 pair passes (elementwise max of two neighbouring 256^3 hyperplanes) of one call on the "
                    "8 x 256^3 float32 GRF (seed 9), vertex filtration, 4096 bins over [min, max]",
@@ -122,6 +125,12 @@ def profile_input(which):
         a = synth.quantize_u16(synth.grf((16384, 16384), seed=4), 4096)
         rng = (int(a.min()), int(a.max()))
         t = torch.from_numpy(a.view(np.int16)).to(dev)
+    elif which == "c2":
+        a = synth.smoothed_noise_u8((256, 256, 256), sigma=2.0, seed=2)
+        t = torch.from_numpy(a).to(dev)
+        out = torch.empty(256, dtype=torch.int64, device=dev)
+        ctx.set_launch_shape(t, 256, **spec["shape"])
+        return ctx, (lambda: ctx.compute(t, 256, value_range=(0, 255), out=out)), int(a.nbytes)
     else:
         a = synth.grf((8, 256, 256, 256), seed=9)
         rng = (float(a.min()), float(a.max()))
@@ -229,6 +238,8 @@ def _alg_bytes(which):
         return 512 ** 3 * 4
     if which == "2d":
         return 16384 ** 2 * 2
+    if which == "c2":
+        return 256 ** 3
     if which == "4d":
         return 7 * 2 * 256 ** 3 * 4   # each pair pass reads two hyperplanes
     from paper_2203_09087_amd import synth
@@ -316,7 +327,7 @@ def write_sq_summary(which, csv_a, csv_b):
     cyc = m["GRBM_GUI_ACTIVE"] / xcds
     slots = cyc / 4
     alg = _alg_bytes(which)
-    esize = {"3d": 4, "2d": 2, "4d": 4, "batch": 1}[which]
+    esize = {"3d": 4, "2d": 2, "4d": 4, "batch": 1, "c2": 1}[which]
     kvox = alg / esize / 1000.0
     out = [f"# SQ counters: `{spec['kernel']}`, {spec['what']}", "",
            "Commands (one pass each, from /tmp, $REPO the repository root):", "",
@@ -428,6 +439,7 @@ def fourd_leg(ctx, stream, nbins=4096):
     d = torch.from_numpy(vol).cuda()
     del vol
     out = torch.empty(nbins, dtype=torch.int64, device=d.device)
+    shape_t = ctx.autotune(d, nbins, value_range=(lo, hi), reps=3, stream=stream)
     ms, _ = timed_calls(lambda: ctx.compute(d, nbins, value_range=(lo, hi), out=out, stream=stream), stream, 20, 3)
     # the same image as a batch of one: its passes share one persistent launch
     ms_b, _ = timed_calls(lambda: ctx.compute_batch([d], nbins, value_ranges=[(lo, hi)], outs=[out], stream=stream),
@@ -437,9 +449,42 @@ def fourd_leg(ctx, stream, nbins=4096):
     gbs = nv * 4 / (m * 1e-3) / 1e9
     return {"shape": list(shape), "nbins": nbins, "ms": round(m, 3), "gvox_s": round(nv / (m * 1e-3) / 1e9, 2),
             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-            "passes": 2 * shape[0] - 1,
+            "passes": 2 * shape[0] - 1, "launch_shape": shape_t,
             "batched_ms": round(mb, 3), "batched_gvox_s": round(nv / (mb * 1e-3) / 1e9, 2),
             "batched_hbm_frac": round(nv * 4 / (mb * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def streamed_large_leg(ctx, stream, n=2048):
+    """A 2048^3 uint8 volume (8 GiB) in pinned host memory streamed in 256 MiB
+    slabs (33 slab copies, the copies overlapping the counting), 256 bins; its
+    result is checked against the same volume counted resident on the device.
+    The volume tiles the 256^3 smoothed-noise block of C2 (sigma 2, seed 2)
+    8 x 8 x 8 times."""
+    import torch
+    from paper_2203_09087_amd import synth
+    log("streaming a 2048^3 u8 volume from pinned host memory ...")
+    b = 256
+    block = synth.smoothed_noise_u8((b, b, b), sigma=2.0, seed=2)
+    host = torch.empty((n, n, n), dtype=torch.uint8, pin_memory=True)
+    hv = host.numpy()
+    for z in range(0, n, b):
+        for y in range(0, n, b):
+            for x in range(0, n, b):
+                hv[z:z + b, y:y + b, x:x + b] = block
+    del block
+    out = torch.empty(256, dtype=torch.int64, device=stream.device)
+    ms, _ = timed_calls(lambda: ctx.compute_streamed(host, 256, value_range=(0, 255), out=out, stream=stream),
+                        stream, 3, 1)
+    dev = host.to(stream.device)
+    ref = ctx.compute(dev, 256, value_range=(0, 255), stream=stream)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(out, ref))
+    del dev, host
+    m = float(np.mean(ms))
+    nv = n ** 3
+    return {"shape": [n, n, n], "dtype": "u8", "slab_planes": "auto (256 MiB)", "ms": round(m, 2),
+            "gvox_s": round(nv / (m * 1e-3) / 1e9, 2), "host_to_device_gb_s": round(nv / (m * 1e-3) / 1e9, 1),
+            "equals_device_resident_call": same}
 
 
 def rotated_leg(ctx, stream, make, shape, copies, nbins, reps, warmup, label):
@@ -660,19 +705,25 @@ def main():
 
     if not args.no_side:
         log("timing AUTO range ...")
-        ms_a, _ = timed_calls(lambda: ctx.compute(vol_d, nbins, value_range="auto", out=out,
-                                                  stream=stream), stream, 20, 3)
-        result["auto_range_ms"] = round(float(np.mean(ms_a)), 4)
-        # the min/max pass alone: the AUTO call minus the explicit one
-        mm_ms = max(1e-6, float(np.mean(ms_a)) - ms_mean)
+        # AUTO and explicit calls alternate, so both see the same state of the
+        # device; the min/max pass alone is the difference of their medians
+        pair = [0]
+
+        def alternate():
+            ctx.compute(vol_d, nbins, value_range="auto" if pair[0] % 2 == 0 else (lo, hi), out=out, stream=stream)
+            pair[0] += 1
+        ms_ae, _ = timed_calls(alternate, stream, 40, 4)
+        ms_a, ms_e = ms_ae[0::2], ms_ae[1::2]
+        result["auto_range_ms"] = round(float(np.median(ms_a)), 4)
+        mm_ms = max(1e-6, float(np.median(ms_a)) - float(np.median(ms_e)))
         mm_rate = alg_bytes / (mm_ms * 1e-3) / 1e9
         torch_rate = read_ceiling(vol_d, stream)
         result["roofline"]["minmax_pass_gb_s"] = round(mm_rate, 1)
         result["roofline"]["torch_amax_gb_s"] = round(torch_rate, 1)
         result["roofline"]["read_ceiling_gb_s"] = round(max(mm_rate, torch_rate), 1)
         result["roofline"]["read_ceiling_how"] = ("the faster of two read-only passes over the same 512 MiB: the "
-                                                  "library's AUTO-range min/max pass (the AUTO step minus the "
-                                                  "explicit step) and torch.amax (best of 10)")
+                                                  "library's AUTO-range min/max pass (median AUTO step minus median "
+                                                  "explicit step, the two alternating) and torch.amax (best of 10)")
         result["roofline"]["frac_of_read_ceiling"] = round(achieved / result["roofline"]["read_ceiling_gb_s"], 4)
         del vol_d
         log("generating 16384^2 u16 GRF ...")
@@ -754,6 +805,7 @@ def main():
                                         "ms": round(msv, 3), "gvox_s": round(nvox / (msv * 1e-3) / 1e9, 2),
                                         "host_to_device_gb_s": round(nvox * 4 / (msv * 1e-3) / 1e9, 1)}
         del host
+        result["streamed_large"] = streamed_large_leg(ctx, stream)
 
     if not args.no_side:
         result["pipeline"] = pipeline_leg(ctx, stream)

@@ -35,10 +35,9 @@
  *
  * Conventions shared by every entry point:
  *   - Images are DEVICE pointers, contiguous, row-major, dims[0] slowest.  Any
- *     alignment is accepted.  ndim is 2 or 3 (also 4 for ecc_compute,
- *     ecc_compute_ex, ecc_compute_noalloc, ecc_compute_batch, the batch plans and
- *     ecc_batch_schedule, see ecc_compute; the other entry points return
- *     ECC_ERR_UNSUPPORTED for a 4D image); every dim is >= 1.
+ *     alignment is accepted.  ndim is 2, 3 or 4 (see ecc_compute for 4D images;
+ *     ecc_compute_streamed returns ECC_ERR_UNSUPPORTED for a 4D image); every
+ *     dim is >= 1.
  *   - `out` is a DEVICE pointer to nbins int64 values, overwritten (not
  *     accumulated) with the ECC.  1 <= nbins <= 65535.
  *   - Every call validates all of its arguments on the host before anything is
@@ -221,7 +220,9 @@ typedef struct {
  * each, after one warm-up; the calls overwrite img->out) and makes `ctx` use the
  * fastest for every later call on an image with the same ndim, dims, dtype and
  * filtration and nbins on the same side of 4096.  Every shape gives the same
- * ECC; only the time differs.  Blocks until the timing runs have finished.
+ * ECC; only the time differs.  A 4D image is tuned for the shape of its 3D
+ * passes (the launches of ecc_compute on it).  Blocks until the timing runs have
+ * finished.
  * chosen (HOST pointer, may be null) receives the chosen shape.  Not for use
  * during graph capture.
  * Errors: as ecc_compute_ex, plus ECC_ERR_INVALID_ARG for reps outside
@@ -235,7 +236,7 @@ ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32
  * tuned in another process, e.g. in a run under a profiler, whose timings the
  * profiler distorts.  A field <= 0 keeps the default for that field; `ms` is
  * ignored.  The result of a call does not depend on the shape.  Enqueues
- * nothing.  img->data and img->out are not read; img->ndim is 2 or 3.
+ * nothing.  img->data and img->out are not read; img->ndim is 2, 3 or 4.
  * Errors: ECC_ERR_INVALID_ARG (null pointer, an invalid descriptor as for
  * ecc_compute_ex, waves above 9, wgs_per_cu above 16, depth above 4096, window
  * above 4096). */

@@ -177,8 +177,7 @@ struct Job {
     int64_t* out;
 };
 
-// max_ndim: 4 for the compute, batch and plan calls, 3 where 4D images are not
-// taken (launch shapes, tuning, streaming).
+// max_ndim: 4 for every call but streaming (3).
 ecc_status validate(ecc_ctx* ctx, const ecc_image& im, int32_t nbins, const char* where, Job* job,
                     int max_ndim = 3)
 {
@@ -186,7 +185,7 @@ ecc_status validate(ecc_ctx* ctx, const ecc_image& im, int32_t nbins, const char
     if (!im.data) { snprintf(buf, sizeof buf, "%s: null image pointer", where); return fail(ctx, ECC_ERR_INVALID_ARG, buf); }
     if (!im.out) { snprintf(buf, sizeof buf, "%s: null output pointer", where); return fail(ctx, ECC_ERR_INVALID_ARG, buf); }
     if (im.ndim == 4 && max_ndim < 4) {
-        snprintf(buf, sizeof buf, "%s: 4D images are taken by the compute, batch and plan calls only", where);
+        snprintf(buf, sizeof buf, "%s: 4D images are not taken by streaming", where);
         return fail(ctx, ECC_ERR_UNSUPPORTED, buf);
     }
     if (im.ndim < 2 || im.ndim > 4) {
@@ -551,7 +550,8 @@ ecc_status enqueue_one(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t st
 // A pair pass reads both hyperplanes and counts the max (min) of their keys.
 // Every pass adds into (or subtracts from) the caller's output, the last one
 // scans it.  The binning parameters are the whole image's.
-ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t stream, bool no_alloc = false)
+ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t stream, bool no_alloc = false,
+                      const ecc_launch_shape* force = nullptr)
 {
     const int64_t nw = j4.nw;
     const int64_t hv = j4.g.n0 * j4.g.n1 * j4.g.n2;
@@ -560,7 +560,12 @@ ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t st
     h.ndim = 3;
     h.nw = 1;
     h.nvox = hv;
-    Sizes sz = plan_sizes(ctx, h, nbins);
+    // the passes' launch shape: forced, tuned for this 4D shape, or the default
+    if (!force) {
+        auto it = ctx->tuned.find(tune_key(ctx, j4, nbins));
+        if (it != ctx->tuned.end()) force = &it->second;
+    }
+    Sizes sz = plan_sizes(ctx, h, nbins, force);
     char* base = nullptr;
     ecc_status st = call_scratch(ctx, h, no_alloc, sz, &base);
     if (st != ECC_OK) return st;
@@ -1432,7 +1437,7 @@ ecc_status ecc_set_launch_shape(ecc_ctx* ctx, const ecc_image* img, int32_t nbin
                     "ecc_set_launch_shape: waves must be at most 9, wgs_per_cu at most 16, depth at most 4096, "
                     "window at most 4096");
     Job j;
-    ecc_status st = validate(ctx, *img, nbins, "ecc_set_launch_shape", &j);
+    ecc_status st = validate(ctx, *img, nbins, "ecc_set_launch_shape", &j, 4);
     if (st != ECC_OK) return st;
     ecc_launch_shape c = *shape;
     c.ms = 0.0;
@@ -1448,7 +1453,7 @@ ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32
     if (!img) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_autotune: null descriptor");
     if (reps < 1 || reps > 1000) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_autotune: reps must be in [1, 1000]");
     Job j;
-    ecc_status st = validate(ctx, *img, nbins, "ecc_autotune", &j);
+    ecc_status st = validate(ctx, *img, nbins, "ecc_autotune", &j, 4);
     if (st != ECC_OK) return st;
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed");
@@ -1456,8 +1461,18 @@ ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32
     const TuneKey key = tune_key(ctx, j, nbins);
     ctx->tuned.erase(key);
     // candidates: the default shape, then waves, depth and workgroups per CU
-    // around it (every shape gives the same result; only the time differs)
-    const Sizes def = plan_sizes(ctx, j, nbins);
+    // around it (every shape gives the same result; only the time differs); a
+    // 4D image is tuned for its 3D passes (one hyperplane's shape)
+    Job shape_job = j;
+    if (j.ndim == 4) {
+        shape_job.ndim = 3;
+        shape_job.nw = 1;
+        shape_job.nvox = j.g.n0 * j.g.n1 * j.g.n2;
+    }
+    const Sizes def = plan_sizes(ctx, shape_job, nbins);
+    auto run = [&](const ecc_launch_shape* c) {
+        return j.ndim == 4 ? enqueue_4d(ctx, j, nbins, stream, false, c) : enqueue_one(ctx, j, nbins, stream, c);
+    };
     const int64_t cols = (ecc::axis_positions(j.g.n2, ctx->construction) + ecc::kLaneCols - 1) / ecc::kLaneCols;
     std::vector<ecc_launch_shape> cand;
     auto add = [&](int waves, int64_t depth, int wgs, int32_t window = 0) {
@@ -1471,7 +1486,7 @@ ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32
                 return;
         cand.push_back(c);
     };
-    const int def_wgs = j.ndim == 3 ? ECC_MAX_WGS_PER_CU_3D : ECC_MAX_WGS_PER_CU_2D;
+    const int def_wgs = j.ndim == 2 ? ECC_MAX_WGS_PER_CU_2D : ECC_MAX_WGS_PER_CU_3D;
     add(def.waves, def.depth, def_wgs);
     for (int wgs : {1, 2, 3, 4})
         for (int64_t dm : {1, 2, 4}) {
@@ -1492,9 +1507,9 @@ ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32
     ecc_launch_shape best = cand[0];
     best.ms = HUGE_VAL;
     for (auto& c : cand) {
-        if ((st = enqueue_one(ctx, j, nbins, stream, &c)) != ECC_OK) break;   // warm-up, sizes the scratch
+        if ((st = run(&c)) != ECC_OK) break;   // warm-up, sizes the scratch
         if ((e = hipEventRecord(e0, stream)) != hipSuccess) { st = hip_fail(ctx, e, "hipEventRecord"); break; }
-        for (int r = 0; r < reps && st == ECC_OK; ++r) st = enqueue_one(ctx, j, nbins, stream, &c);
+        for (int r = 0; r < reps && st == ECC_OK; ++r) st = run(&c);
         if (st != ECC_OK) break;
         if ((e = hipEventRecord(e1, stream)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) {
             st = hip_fail(ctx, e, "hipEventSynchronize(autotune)");

@@ -19,6 +19,10 @@ torch = pytest.importorskip("torch")
 CONS = ("vertex", "top")
 
 
+def say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
 @pytest.fixture(scope="module")
 def ctxs():
     if not torch.cuda.is_available():
@@ -175,7 +179,32 @@ def test_4d_benchmark_field_in_batch(ctxs, oracle_mod, cons):
 
 def test_4d_is_rejected_where_unsupported(ctxs):
     from paper_2203_09087_amd import ecc
-    img = torch.zeros((2, 3, 4, 5), dtype=torch.uint8, device="cuda")
+    img = torch.zeros((2, 3, 4, 5), dtype=torch.uint8)
     with pytest.raises(ecc.EccError) as e:
-        ctxs["vertex"].autotune(img, 16)
+        ctxs["vertex"].compute_streamed(img, 16)
     assert e.value.status == ecc.ECC_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("cons", CONS)
+def test_4d_autotune_and_pinned_shapes_keep_results(oracle_mod, cons):
+    """Tuning a 4D image (the shape of its 3D passes) and pinning shapes for it
+    change only the time: every shape gives the oracle's ECC."""
+    from paper_2203_09087_amd import ecc
+    rng = np.random.default_rng(97)
+    img = rng.standard_normal(size=(5, 12, 30, 140)).astype(np.float32)
+    want = oracle_mod.ecc(img, 1024, cons, value_range=(-2.0, 2.0))
+    ctx = ecc.Context(0, cons)
+    try:
+        d = to_dev(img)
+        say(f"case: 4d autotune {cons}")
+        ctx.autotune(d, 1024, value_range=(-2.0, 2.0), reps=1)
+        got = ctx.compute(d, 1024, value_range=(-2.0, 2.0))
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy(), want)
+        for waves, wgs, depth, window in ((1, 1, 2, 0), (3, 4, 5, 300), (0, 0, 0, 0)):
+            ctx.set_launch_shape(d, 1024, waves=waves, wgs_per_cu=wgs, depth=depth, window=window)
+            got = ctx.compute(d, 1024, value_range=(-2.0, 2.0))
+            torch.cuda.synchronize()
+            assert np.array_equal(got.cpu().numpy(), want), (waves, wgs, depth, window)
+    finally:
+        ctx.close()

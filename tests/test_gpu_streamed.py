@@ -88,6 +88,21 @@ def test_streamed_equals_device_call_on_a_large_volume(ctxs):
     assert torch.equal(got, dev) and torch.equal(got_auto, dev_auto)
 
 
+@pytest.mark.parametrize("cons", CONS)
+def test_streamed_many_slabs_matches_oracle(ctxs, oracle_mod, cons):
+    """A 640 x 256 x 256 uint8 volume (40 MiB, smoothed noise) streamed in 320 slabs
+    of 2 planes and in 13 slabs of 50, so the two slab buffers and their events
+    are reused hundreds of times: equal to the oracle."""
+    from paper_2203_09087_amd import synth
+    vol = np.concatenate([synth.smoothed_noise_u8((64, 256, 256), sigma=2.0, seed=70 + k) for k in range(10)])
+    want = oracle_mod.ecc(vol, 256, cons, value_range=(0, 255), threads=16)
+    for slab in (2, 50):
+        say(f"case: streamed {cons} {vol.shape} uint8, slabs of {slab}")
+        got = ctxs[cons].compute_streamed(_host(vol, True), 256, value_range=(0, 255), slab_planes=slab)
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy(), want), slab
+
+
 def test_streamed_rejects_device_tensors_and_bad_slabs(ctxs):
     from paper_2203_09087_amd import ecc
     ctx = ctxs["vertex"]
