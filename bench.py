@@ -68,6 +68,12 @@ PROFILES = {
     "c2": {"kernel": "k_ecc_3d<0, 0, false, false>", "file": "k_ecc_3d_u8_256cubed", "per_call": 1,
            "what": "256^3 uint8 smoothed noise (sigma 2, seed 2), vertex filtration, 256 bins over [0, 255]",
            "shape": {"waves": 5, "wgs_per_cu": 4, "depth": 16}},
+    "minmax": {"kernel": "k_minmax", "file": "k_minmax_f32_512cubed", "per_call": 1,
+               "what": "the AUTO-range min/max pass over the 512^3 float32 GRF (seed 3), 4096 bins",
+               "shape": {"waves": 9, "wgs_per_cu": 3, "depth": 32}},
+    "smooth": {"kernel": "k_smooth", "file": "k_smooth13_f32_8192sq", "per_call": 2,
+               "what": "one 13-tap smoothing pass (rows, then columns) of an 8192^2 float32 GRF (seed 8)",
+               "shape": None},
     "4d": {"kernel": "k_ecc_3d<2, 0, false, true>", "file": "k_ecc_3d_pair_f32_8x256cubed", "per_call": 7,
            "what": "the 7 pair passes (elementwise max of two neighbouring 256^3 hyperplanes) of one call on the "
                    "8 x 256^3 float32 GRF (seed 9), vertex filtration, 4096 bins over [min, max]",
@@ -113,13 +119,20 @@ def profile_input(which):
     dev = torch.device("cuda", 0)
     spec = PROFILES[which]
     ctx = ecc.Context(0, "vertex")
+    if which == "smooth":
+        a = synth.grf((8192, 8192), seed=8)
+        t = torch.from_numpy(a).to(dev)
+        o = torch.empty_like(t)
+        taps = np.exp(-0.5 * (np.arange(13) - 6.0) ** 2 / 4.0)
+        taps = (taps / taps.sum()).astype(np.float32)
+        return ctx, (lambda: ctx.smooth13(t, taps, out=o)), 16 * int(a.size)
     if which == "batch":
         imgs = [torch.from_numpy(a).to(dev) for a in synth.batch_images(count=512, seed=5)]
         outs = [torch.empty(256, dtype=torch.int64, device=dev) for _ in imgs]
         return ctx, (lambda: ctx.compute_batch(imgs, 256, outs=outs)), int(sum(t.numel() for t in imgs))
-    if which == "3d":
+    if which in ("3d", "minmax"):
         a = synth.grf((512, 512, 512), seed=3)
-        rng = (float(a.min()), float(a.max()))
+        rng = (float(a.min()), float(a.max())) if which == "3d" else "auto"
         t = torch.from_numpy(a).to(dev)
     elif which == "2d":
         a = synth.quantize_u16(synth.grf((16384, 16384), seed=4), 4096)
@@ -238,6 +251,10 @@ def _alg_bytes(which):
         return 512 ** 3 * 4
     if which == "2d":
         return 16384 ** 2 * 2
+    if which == "minmax":
+        return 512 ** 3 * 4
+    if which == "smooth":
+        return 16 * 8192 ** 2   # rows and columns each read and write every pixel
     if which == "c2":
         return 256 ** 3
     if which == "4d":
@@ -327,7 +344,7 @@ def write_sq_summary(which, csv_a, csv_b):
     cyc = m["GRBM_GUI_ACTIVE"] / xcds
     slots = cyc / 4
     alg = _alg_bytes(which)
-    esize = {"3d": 4, "2d": 2, "4d": 4, "batch": 1, "c2": 1}[which]
+    esize = {"3d": 4, "2d": 2, "4d": 4, "batch": 1, "c2": 1, "minmax": 4, "smooth": 16}[which]
     kvox = alg / esize / 1000.0
     out = [f"# SQ counters: `{spec['kernel']}`, {spec['what']}", "",
            "Commands (one pass each, from /tmp, $REPO the repository root):", "",
