@@ -203,17 +203,19 @@ ecc_status ecc_smooth13(ecc_ctx* ctx, const float* in, float* out, int64_t n1, i
 
 /* Launch shape of the single-image kernel: waves per workgroup (a workgroup
  * covers waves * 63 consecutive position columns), rows (2D) or planes (3D) per
- * workgroup brick, resident workgroups per CU aimed for, and `window`, the bins
+ * workgroup brick, resident workgroups per CU aimed for, `window`, the bins
  * one pass counts in LDS (Sec. 4.3's block-shared histogram; fewer than nbins
  * makes several passes over the image, each with less LDS; 0: all of nbins up to
- * 4096).  `ms` is the mean time of one call measured by ecc_autotune. */
+ * 4096), and `copies`, the copies of that histogram the lanes of a wave spread
+ * their adds over (2, 4 or 8; 0: 8 up to 256 bins, 4 up to 1024, else 2).  `ms`
+ * is the mean time of one call measured by ecc_autotune. */
 typedef struct {
     int32_t waves;
     int32_t wgs_per_cu;
     int64_t depth;
     double ms;
     int32_t window;
-    int32_t reserved;   /* 0 */
+    int32_t copies;
 } ecc_launch_shape;
 
 /* Times a set of launch shapes for the image `img` on hip_stream (`reps` calls
@@ -239,7 +241,7 @@ ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32
  * nothing.  img->data and img->out are not read; img->ndim is 2, 3 or 4.
  * Errors: ECC_ERR_INVALID_ARG (null pointer, an invalid descriptor as for
  * ecc_compute_ex, waves above 9, wgs_per_cu above 16, depth above 4096, window
- * above 4096). */
+ * above 4096, copies other than 0, 2, 4 or 8). */
 ecc_status ecc_set_launch_shape(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, const ecc_launch_shape* shape);
 
 /* A planned batch (Sec. 5's many-files workload, kept on the device): the

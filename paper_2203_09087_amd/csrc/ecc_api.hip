@@ -291,7 +291,7 @@ struct Sizes {
     int waves;
     int64_t depth;
     int32_t window;
-    uint32_t hist_stride, sentinel, lds_bytes;   // LDS layout of the histogram kernel
+    uint32_t hist_stride, hist_copies, sentinel, lds_bytes;   // LDS layout of the histogram kernel
     size_t off_params, off_counters, off_mm, off_level2, off_partials, total;
 };
 
@@ -348,8 +348,10 @@ Sizes plan_sizes(const ecc_ctx* ctx, const Job& j, int32_t nbins, const ecc_laun
     if (tuned && tuned->window > 0) s.window = std::min<int32_t>(s.window, tuned->window);
     const bool windowed = s.window < nbins;
     s.hist_stride = ecc::lds_stride(s.window);
+    s.hist_copies = ecc::hist_copies(s.window);
+    if (tuned && tuned->copies > 0) s.hist_copies = (uint32_t)tuned->copies;
     s.sentinel = ecc::lds_sentinel(nbins);
-    s.lds_bytes = 4u * ecc::lds_words(s.window, windowed, s.sentinel);
+    s.lds_bytes = 4u * ecc::lds_words(s.window, windowed, s.sentinel, s.hist_copies);
     int want_per_cu = j.ndim == 3 ? ECC_MAX_WGS_PER_CU_3D : ECC_MAX_WGS_PER_CU_2D;
     if (tuned && tuned->wgs_per_cu > 0) want_per_cu = tuned->wgs_per_cu;
     const int per_cu = std::min(want_per_cu, ecc::resident_wgs_per_cu(j.ndim, j.dtype, ctx->construction, windowed,
@@ -486,6 +488,7 @@ ecc_status enqueue_hist(ecc_ctx* ctx, char* base, const Job& j, int32_t nbins, h
     L.counter = counters;
     L.fused = 0;
     L.hist_stride = sz.hist_stride;
+    L.hist_copies = sz.hist_copies;
     L.sentinel = sz.sentinel;
     L.lds_bytes = sz.lds_bytes;
     hipError_t e;
@@ -857,8 +860,9 @@ ecc_status launch_batch_kernels(ecc_ctx* ctx, const BatchTables& T, char* d, boo
     B.waves = ecc::kBatchWaves;
     B.windowed = T.window < T.nbins ? 1 : 0;
     B.hist_stride = ecc::lds_stride(T.window);
+    B.hist_copies = ecc::hist_copies(T.window);
     B.sentinel = ecc::lds_sentinel(T.nbins);
-    B.lds_bytes = 4u * ecc::lds_words(T.window, B.windowed != 0, B.sentinel);
+    B.lds_bytes = 4u * ecc::lds_words(T.window, B.windowed != 0, B.sentinel, B.hist_copies);
     hipError_t e;
     if (!T.pieces.empty()) {
         if (reset_mm && (e = ecc::launch_mm_init(B.mm, T.count, stream)) != hipSuccess)
@@ -1432,10 +1436,11 @@ ecc_status ecc_set_launch_shape(ecc_ctx* ctx, const ecc_image* img, int32_t nbin
     ctx->err.clear();
     if (!img || !shape) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_set_launch_shape: null pointer");
     if (shape->waves > ecc::kMaxWaves || shape->wgs_per_cu > 16 || shape->depth > 4096 ||
-        shape->window > ecc::kMaxLdsBins)
+        shape->window > ecc::kMaxLdsBins ||
+        (shape->copies != 0 && shape->copies != 2 && shape->copies != 4 && shape->copies != 8))
         return fail(ctx, ECC_ERR_INVALID_ARG,
                     "ecc_set_launch_shape: waves must be at most 9, wgs_per_cu at most 16, depth at most 4096, "
-                    "window at most 4096");
+                    "window at most 4096, copies 0, 2, 4 or 8");
     Job j;
     ecc_status st = validate(ctx, *img, nbins, "ecc_set_launch_shape", &j, 4);
     if (st != ECC_OK) return st;
@@ -1475,14 +1480,16 @@ ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32
     };
     const int64_t cols = (ecc::axis_positions(j.g.n2, ctx->construction) + ecc::kLaneCols - 1) / ecc::kLaneCols;
     std::vector<ecc_launch_shape> cand;
-    auto add = [&](int waves, int64_t depth, int wgs, int32_t window = 0) {
+    auto add = [&](int waves, int64_t depth, int wgs, int32_t window = 0, int32_t copies = 0) {
         ecc_launch_shape c = {};
         c.waves = (int32_t)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(waves, ecc::kMaxWaves), cols));
         c.depth = std::max<int64_t>(1, depth);
         c.wgs_per_cu = wgs;
         c.window = window;
+        c.copies = copies;
         for (const auto& e : cand)
-            if (e.waves == c.waves && e.depth == c.depth && e.wgs_per_cu == c.wgs_per_cu && e.window == c.window)
+            if (e.waves == c.waves && e.depth == c.depth && e.wgs_per_cu == c.wgs_per_cu && e.window == c.window &&
+                e.copies == c.copies)
                 return;
         cand.push_back(c);
     };
@@ -1498,6 +1505,9 @@ ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32
     // LDS allows
     if (def.window >= 2048)
         for (int wgs : {def_wgs, def_wgs + 2}) add(def.waves, def.depth, wgs, def.window / 2);
+    // histogram copies for narrow windows (few bins leave LDS for more)
+    if (def.window <= 1024)
+        for (int copies : {2, 4, 8}) add(def.waves, def.depth, def_wgs, 0, copies);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e;
     if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {

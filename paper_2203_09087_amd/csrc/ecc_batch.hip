@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
 void k_ecc_batch(BatchLaunch B)
 {
     extern __shared__ __align__(16) int32_t hist[];
-    const HistRef H = hist_ref(hist, B.bin_lo, B.width, B.hist_stride, B.sentinel);
+    const HistRef H = hist_ref(hist, B.bin_lo, B.width, B.hist_stride, B.sentinel, B.hist_copies);
     const int W = (int)(blockDim.x >> 6), wave = wave_id();
     const int s_end = B.wg_seg[blockIdx.x + 1];
     for (int si = B.wg_seg[blockIdx.x]; si < s_end; ++si) {

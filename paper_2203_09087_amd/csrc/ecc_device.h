@@ -264,7 +264,7 @@ __device__ __forceinline__ uint32_t op_right(uint32_t a)
 }
 
 struct HistRef {
-    int32_t* hist;     // LDS: kHistCopies copies of the window's counters (`stride` words apart)
+    int32_t* hist;     // LDS: `copies` copies of the window's counters (`stride` words apart)
                        // and spare words (lds_words)
     uint32_t key_lo;   // key of the first bin of the window (windowed launches)
     uint32_t key_span; // keys in the window: also the byte offset of the spare word that
@@ -272,13 +272,14 @@ struct HistRef {
     uint32_t copy;     // byte offset of this lane's copy (odd lanes: the second)
     uint32_t stride;   // words from one copy to the next
     uint32_t sm;       // the sentinel key of a one-window launch
+    uint32_t copies;   // copies (a power of two; lane l adds to copy l mod copies)
 };
 
 __device__ __forceinline__ HistRef hist_ref(int32_t* hist, int32_t bin_lo, int32_t width, uint32_t stride,
-                                            uint32_t sm)
+                                            uint32_t sm, uint32_t copies)
 {
     return HistRef{hist, (uint32_t)bin_lo << kKeyShift, (uint32_t)width << kKeyShift,
-                   (__lane_id() & (kHistCopies - 1)) * stride * 4u, stride, sm};
+                   (__lane_id() & (copies - 1u)) * stride * 4u, stride, sm, copies};
 }
 
 // Adds v to the counter of `key` in this lane's copy.  One window: the key is the
@@ -392,7 +393,7 @@ __device__ __forceinline__ void fused_merge_scan(int32_t* hist, const int32_t* p
 
 __device__ __forceinline__ void zero_hist(const HistRef& H, int width)
 {
-    for (int c = 0; c < kHistCopies; ++c)
+    for (uint32_t c = 0; c < H.copies; ++c)
         for (int j = threadIdx.x; j < width; j += blockDim.x) H.hist[c * H.stride + j] = 0;
     __syncthreads();
 }
@@ -401,7 +402,7 @@ __device__ __forceinline__ void zero_hist(const HistRef& H, int width)
 __device__ __forceinline__ int32_t hist_value(const HistRef& H, int j)
 {
     int32_t t = H.hist[j];
-    for (int c = 1; c < kHistCopies; ++c) t += H.hist[c * H.stride + j];
+    for (uint32_t c = 1; c < H.copies; ++c) t += H.hist[c * H.stride + j];
     return t;
 }
 

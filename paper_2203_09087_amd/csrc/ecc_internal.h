@@ -66,13 +66,21 @@ constexpr int kMaxLdsBins = 4096;
 #endif
 // A key is 4 * bin: the LDS byte address of its counter.
 constexpr int kKeyShift = 2;
-// A workgroup histogram is kept in two copies, one for the even and one for the
-// odd lanes of every wave: equal keys of neighbouring lanes (frequent in smooth
-// images) then fall into different copies, and the second copy starts 8 words
-// further in the bank cycle, so they do not collide in one LDS bank.  The merge
-// adds the copies.  The LDS a launch takes is sized to its window (dynamic
-// shared memory), so a histogram of few bins leaves room for more workgroups.
-constexpr int kHistCopies = 2;
+// A workgroup histogram is kept in several copies, lane l of every wave adding to
+// copy l mod copies: equal keys of neighbouring lanes (frequent in smooth images)
+// then fall into different copies, each starting 8 words further in the bank
+// cycle than the one before, so they do not collide in one LDS bank.  The merge
+// adds the copies.  Two copies for wide windows; a narrow window affords more
+// (hist_copies), which smooth data with few bins needs.  The LDS a launch takes
+// is sized to its window and copies (dynamic shared memory), so a histogram of
+// few bins leaves room for more workgroups.
+constexpr int kHistCopies = 2;   // copies of a window wider than 1024 bins
+constexpr int kMaxHistCopies = 8;
+// Default copies for a window of `width` bins: 8 up to 256 bins, 4 up to 1024.
+inline __host__ __device__ uint32_t hist_copies(int32_t width)
+{
+    return width <= 256 ? 8u : (width <= 1024 ? 4u : (uint32_t)kHistCopies);
+}
 // Words from one copy to the next for a window of `width` bins (a multiple of 32
 // plus 8: the 8-bank offset; with windows the word after the window is spare).
 inline __host__ __device__ uint32_t lds_stride(int32_t width)
@@ -90,10 +98,10 @@ inline __host__ __device__ uint32_t lds_sentinel(int32_t nbins)
 // LDS words of a workgroup histogram: the copies and, with one window, spare
 // words up to the second copy's sentinel word, which absorbs the counts of
 // cells that do not exist (4096 bins: 12,296 words).
-inline __host__ __device__ uint32_t lds_words(int32_t width, bool windowed, uint32_t sentinel)
+inline __host__ __device__ uint32_t lds_words(int32_t width, bool windowed, uint32_t sentinel, uint32_t copies)
 {
     const uint32_t stride = lds_stride(width);
-    return windowed ? kHistCopies * stride : stride * (kHistCopies - 1) + sentinel / 4u + 1u;
+    return windowed ? copies * stride : stride * (copies - 1) + sentinel / 4u + 1u;
 }
 // Positions a wave owns along x (lanes 0..62; lane 63 only supplies lane 62's
 // right neighbour).
@@ -134,6 +142,7 @@ struct EccLaunch {
     uint32_t* counter;             // counters[0]: the merge's; counters[1]: the fused merge's
     int32_t fused;                 // one window, few rows: the last workgroup merges and scans into out
     uint32_t hist_stride;          // LDS words between the histogram copies (lds_stride(width))
+    uint32_t hist_copies;          // copies of the histogram (a power of two up to kMaxHistCopies)
     uint32_t sentinel;             // one-window sentinel key (lds_sentinel(nbins))
     uint32_t lds_bytes;            // dynamic LDS of the launch (lds_words * 4)
 };
@@ -194,7 +203,7 @@ struct BatchLaunch {
     int32_t nbins, bin_lo, width, windowed;
     int32_t grid, waves;
     int32_t pairs;              // the launch counts pair volumes (4D images)
-    uint32_t hist_stride, sentinel, lds_bytes;   // LDS layout, as in EccLaunch
+    uint32_t hist_stride, hist_copies, sentinel, lds_bytes;   // LDS layout, as in EccLaunch
 };
 
 // Launchers (ecc_batch.hip).

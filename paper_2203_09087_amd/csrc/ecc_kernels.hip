@@ -23,7 +23,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
 {
     extern __shared__ __align__(16) int32_t hist[];
     const BinParams P = L.params_dev ? *L.params_dev : L.params;
-    const HistRef H = hist_ref(hist, L.bin_lo, L.width, L.hist_stride, L.sentinel);
+    const HistRef H = hist_ref(hist, L.bin_lo, L.width, L.hist_stride, L.sentinel, L.hist_copies);
     zero_hist(H, L.width);
     const int64_t chunk = (int64_t)(blockDim.x >> 6) * kLaneCols;
     const uint32_t nxc = (uint32_t)((axis_positions(L.g.n2, CONS) + chunk - 1) / chunk);
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
 {
     extern __shared__ __align__(16) int32_t hist[];
     const BinParams P = L.params_dev ? *L.params_dev : L.params;
-    const HistRef H = hist_ref(hist, L.bin_lo, L.width, L.hist_stride, L.sentinel);
+    const HistRef H = hist_ref(hist, L.bin_lo, L.width, L.hist_stride, L.sentinel, L.hist_copies);
     zero_hist(H, L.width);
     const int64_t chunk = (int64_t)(blockDim.x >> 6) * kLaneCols;
     const uint32_t nxc = (uint32_t)((axis_positions(L.g.n2, CONS) + chunk - 1) / chunk);

@@ -71,7 +71,7 @@ class ecc_launch_shape(ctypes.Structure):
         ("depth", ctypes.c_int64),
         ("ms", ctypes.c_double),
         ("window", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("copies", ctypes.c_int32),
     ]
 
 
@@ -243,8 +243,8 @@ def ecc_autotune(ctx: int, img: ecc_image, nbins: int, reps: int, stream: int = 
 
 
 def ecc_set_launch_shape(ctx: int, img: ecc_image, nbins: int, waves: int, wgs_per_cu: int, depth: int,
-                         window: int = 0) -> int:
-    shape = ecc_launch_shape(int(waves), int(wgs_per_cu), int(depth), 0.0, int(window), 0)
+                         window: int = 0, copies: int = 0) -> int:
+    shape = ecc_launch_shape(int(waves), int(wgs_per_cu), int(depth), 0.0, int(window), int(copies))
     return load_library().ecc_set_launch_shape(ctx, ctypes.byref(img), int(nbins), ctypes.byref(shape))
 
 
@@ -457,16 +457,16 @@ class Context:
                                  self._stream(stream))
         self._check(st)
         return {"waves": shape.waves, "wgs_per_cu": shape.wgs_per_cu, "depth": shape.depth, "window": shape.window,
-                "ms": shape.ms}
+                "copies": shape.copies, "ms": shape.ms}
 
     def set_launch_shape(self, image, nbins: int, waves: int = 0, wgs_per_cu: int = 0, depth: int = 0,
-                         window: int = 0, ms=None):
+                         window: int = 0, copies: int = 0, ms=None):
         """Uses the given launch shape (0: default for that field) for later calls
         on images shaped like `image` (a tuned shape from another run)."""
         import torch
         out = torch.empty(1, dtype=torch.int64, device=image.device)
         self._check(ecc_set_launch_shape(self.handle, make_image(image, out, None), nbins, waves, wgs_per_cu,
-                                         depth, window))
+                                         depth, window, copies))
 
     def plan_batch(self, images, nbins: int, value_ranges=None, outs=None):
         """A BatchPlan over device tensors (kept alive by the plan object)."""

@@ -477,7 +477,8 @@ def test_set_launch_shape(oracle_mod):
             got = ctx.compute(d, 4096, value_range=(-2.0, 2.0))
             torch.cuda.synchronize()
             assert np.array_equal(got.cpu().numpy(), want), (waves, wgs, depth)
-        for bad in ({"waves": 10}, {"wgs_per_cu": 17}, {"depth": 4097}, {"window": 4097}):
+        for bad in ({"waves": 10}, {"wgs_per_cu": 17}, {"depth": 4097}, {"window": 4097}, {"copies": 3},
+                    {"copies": 16}):
             with pytest.raises(ecc.EccError):
                 ctx.set_launch_shape(d, 4096, **bad)
         got = ctx.compute(d, 4096, value_range=(-2.0, 2.0))
@@ -508,6 +509,30 @@ def test_bins_per_pass_split(oracle_mod, cons):
                 got = ctx.compute(d, nbins, value_range=r)
                 torch.cuda.synchronize()
                 assert np.array_equal(got.cpu().numpy(), want), (img.shape, nbins, w)
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("cons", CONS)
+def test_histogram_copies(oracle_mod, cons):
+    """2, 4 or 8 copies of the LDS histogram (lane l adds to copy l mod copies),
+    one window or several, smooth data with many equal neighbours: the oracle's
+    ECC every time."""
+    from paper_2203_09087_amd import ecc, synth
+    vol = synth.smoothed_noise_u8((30, 70, 140), sigma=2.0, seed=53)
+    img2 = synth.smoothed_noise_u8((200, 330), sigma=2.0, seed=54)
+    ctx = ecc.Context(0, cons)
+    try:
+        for img, nbins in ((vol, 256), (img2, 256), (vol, 1000), (img2, 100)):
+            d = to_dev(img)
+            want = oracle_mod.ecc(img, nbins, cons, value_range=(0, 255))
+            for copies in (2, 4, 8, 0):
+                for window in (0, 64):
+                    say(f"case: {cons} copies={copies} window={window} nbins={nbins} shape={img.shape}")
+                    ctx.set_launch_shape(d, nbins, copies=copies, window=window)
+                    got = ctx.compute(d, nbins, value_range=(0, 255))
+                    torch.cuda.synchronize()
+                    assert np.array_equal(got.cpu().numpy(), want), (img.shape, nbins, copies, window)
     finally:
         ctx.close()
 
