@@ -504,7 +504,7 @@ def streamed_large_leg(ctx, stream, n=2048):
             "equals_device_resident_call": same}
 
 
-def rotated_leg(ctx, stream, make, shape, copies, nbins, reps, warmup, label):
+def rotated_leg(ctx, stream, make, shape, copies, nbins, reps, warmup, label, batch_n=0):
     """One small workload timed call by call over `copies` device copies of the
     input (at least 1 GiB in all, more than the 256 MB Infinity Cache), each call
     on the next copy, so no call reads an input a recent call left in cache."""
@@ -538,6 +538,27 @@ def rotated_leg(ctx, stream, make, shape, copies, nbins, reps, warmup, label):
     k_ms, k_n = ctx.kernel_time()
     ctx.set_kernel_timing(False)
     k_avg = k_ms / max(1, k_n)
+    batched = None
+    if batch_n:
+        # the same images as planned batches of batch_n distinct copies (tables
+        # built once, so the host does not pace the launches), one launch each
+        groups = [[pool[(g * batch_n + i) % copies] for i in range(batch_n)] for g in range(8)]
+        bouts = [torch.empty(nbins, dtype=torch.int64, device=pool.device) for _ in range(batch_n)]
+        plans = [ctx.plan_batch(g, nbins, outs=bouts) for g in groups]
+        k = [0]
+
+        def one_batch():
+            plans[k[0] % len(plans)].launch(stream=stream)
+            k[0] += 1
+        ms_b, _ = timed_calls(one_batch, stream, 40, 8)
+        torch.cuda.synchronize()
+        for pl in plans:
+            pl.close()
+        mb = float(np.median(ms_b))
+        nvb = batch_n * int(np.prod(shape))
+        batched = {"images_per_launch": batch_n, "how": "planned batches over the rotated copies", "ms": round(mb, 4), "images_per_s": round(batch_n / (mb * 1e-3), 1),
+                   "gvox_s": round(nvb / (mb * 1e-3) / 1e9, 2),
+                   "hbm_frac": round(nvb * img.itemsize / (mb * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     nv = int(np.prod(shape))
     m = float(np.median(ms))
     res = {"workload": label, "shape": list(shape), "nbins": nbins, "calls": reps,
@@ -549,6 +570,8 @@ def rotated_leg(ctx, stream, make, shape, copies, nbins, reps, warmup, label):
            "back_to_back_ms_per_call": round(per_call, 4), "launch_shape": shape_t,
            "kernel_ms": round(k_avg, 4), "kernel_gvox_s": round(nv / (k_avg * 1e-3) / 1e9, 2),
            "kernel_hbm_frac": round(nv * img.itemsize / (k_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if batched:
+        res["as_batches"] = batched
     del pool
     return res
 
@@ -791,7 +814,8 @@ def main():
 
         log("small configs (inputs rotated over 1 GiB) ...")
         result["small_2d_u8"] = rotated_leg(ctx, stream, lambda: synth.uniform_u8((256, 256), seed=1), (256, 256),
-                                            16384, 256, 1000, 20, "256^2 uint8 uniform noise (seed 1), 256 bins")
+                                            16384, 256, 1000, 20, "256^2 uint8 uniform noise (seed 1), 256 bins",
+                                            batch_n=1024)
         result["small_3d_u8"] = rotated_leg(ctx, stream,
                                             lambda: synth.smoothed_noise_u8((256, 256, 256), sigma=2.0, seed=2),
                                             (256, 256, 256), 64, 256, 200, 10,
@@ -869,7 +893,7 @@ def config_summary(r):
     def pick(d, *keys):
         return {k: d.get(k) for k in keys} if d else None
     c = {"C1 256^2 u8 uniform, 256 bins": pick(r.get("small_2d_u8"), "p50_ms", "gvox_s", "hbm_frac", "kernel_ms",
-                                                "kernel_gvox_s", "kernel_hbm_frac"),
+                                                "kernel_gvox_s", "kernel_hbm_frac", "as_batches"),
          "C2 256^3 u8 smoothed, 256 bins": pick(r.get("small_3d_u8"), "p50_ms", "gvox_s", "hbm_frac", "kernel_ms",
                                                 "kernel_gvox_s", "kernel_hbm_frac"),
          "C3 512^3 f32 GRF, 4096 bins, explicit range": {"ms": r.get("ms_per_step"), "gvox_s": r.get("value"),
