@@ -35,6 +35,7 @@ def log(*a):
 def timed_calls(fn, stream, steps, warmup):
     """Runs fn() warmup+steps times on `stream`; returns per-call ms (HIP events)."""
     import torch
+    spin_up(fn)
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -91,6 +92,44 @@ def kernel_sources_sha256():
     for name in ("ecc_internal.h", "ecc_device.h", "ecc_kernels.hip", "ecc_batch.hip"):
         h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()
+
+
+def spin_up(fn, seconds=0.15):
+    """Calls fn back to back for `seconds` of wall time before a measurement: the
+    device runs its first ~150 steps of the 512^3 workload up to 15% slower (its
+    clocks ramp up under load, and drop again within half a second of idling)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    if time.perf_counter() - t0 >= seconds / 8:   # a long call is its own warm-up
+        return
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(8):
+            fn()
+        torch.cuda.synchronize()
+
+
+def region_ms(fn, stream, steps, warmup):
+    """Mean milliseconds per call of `steps` calls timed as one region: a HIP
+    event before the first and one after the last (per-call events would add
+    their own packets between the calls), after `warmup` untimed calls, with a
+    synchronisation on both sides.  Also returns the region's wall time (s)."""
+    import torch
+    spin_up(fn)
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, time.perf_counter() - t0
 
 
 def traffic_bytes():
@@ -437,12 +476,12 @@ def pipeline_leg(ctx, stream, iters=1000):
     def only_smooth():
         ctx.smooth13(img, taps, out=img, stream=stream)
 
-    ms, wall = timed_calls(one, stream, iters, 10)
-    ms_e, _ = timed_calls(only_ecc, stream, 200, 5)
-    ms_s, _ = timed_calls(only_smooth, stream, 200, 5)
+    m_one, wall = region_ms(one, stream, iters, 10)
+    m_e, _ = region_ms(only_ecc, stream, 200, 5)
+    m_s, _ = region_ms(only_smooth, stream, 200, 5)
     return {"image": [1024, 1024], "iterations": iters, "nbins": 1024, "range": "auto",
-            "ms_per_iteration": round(float(np.mean(ms)), 4), "ecc_ms": round(float(np.mean(ms_e)), 4),
-            "smooth_ms": round(float(np.mean(ms_s)), 4), "wall_s": round(wall, 3)}
+            "ms_per_iteration": round(m_one, 4), "ecc_ms": round(m_e, 4),
+            "smooth_ms": round(m_s, 4), "wall_s": round(wall, 3)}
 
 
 def fourd_leg(ctx, stream, nbins=4096):
@@ -457,11 +496,10 @@ def fourd_leg(ctx, stream, nbins=4096):
     del vol
     out = torch.empty(nbins, dtype=torch.int64, device=d.device)
     shape_t = ctx.autotune(d, nbins, value_range=(lo, hi), reps=3, stream=stream)
-    ms, _ = timed_calls(lambda: ctx.compute(d, nbins, value_range=(lo, hi), out=out, stream=stream), stream, 20, 3)
+    m, _ = region_ms(lambda: ctx.compute(d, nbins, value_range=(lo, hi), out=out, stream=stream), stream, 20, 3)
     # the same image as a batch of one: its passes share one persistent launch
-    ms_b, _ = timed_calls(lambda: ctx.compute_batch([d], nbins, value_ranges=[(lo, hi)], outs=[out], stream=stream),
-                          stream, 20, 3)
-    m, mb = float(np.mean(ms)), float(np.mean(ms_b))
+    mb, _ = region_ms(lambda: ctx.compute_batch([d], nbins, value_ranges=[(lo, hi)], outs=[out], stream=stream),
+                      stream, 20, 3)
     nv = int(np.prod(shape))
     gbs = nv * 4 / (m * 1e-3) / 1e9
     return {"shape": list(shape), "nbins": nbins, "ms": round(m, 3), "gvox_s": round(nv / (m * 1e-3) / 1e9, 2),
@@ -550,11 +588,10 @@ def rotated_leg(ctx, stream, make, shape, copies, nbins, reps, warmup, label, ba
         def one_batch():
             plans[k[0] % len(plans)].launch(stream=stream)
             k[0] += 1
-        ms_b, _ = timed_calls(one_batch, stream, 40, 8)
+        mb, _ = region_ms(one_batch, stream, 40, 8)
         torch.cuda.synchronize()
         for pl in plans:
             pl.close()
-        mb = float(np.median(ms_b))
         nvb = batch_n * int(np.prod(shape))
         batched = {"images_per_launch": batch_n, "how": "planned batches over the rotated copies", "ms": round(mb, 4), "images_per_s": round(batch_n / (mb * 1e-3), 1),
                    "gvox_s": round(nvb / (mb * 1e-3) / 1e9, 2),
@@ -713,7 +750,10 @@ def main():
         log("autotuning the launch shape ...")
         shape = ctx.autotune(vol_d, nbins, value_range=(lo, hi), reps=3, stream=stream)
     log("timing plain 512^3 ...")
-    ms, wall = timed_calls(step, stream, args.steps, args.warmup)
+    ms_mean, wall = region_ms(step, stream, args.steps, args.warmup)
+    # per-step times for the percentiles: the same steps again, an event pair
+    # around each (kept out of the region above, whose mean they would lengthen)
+    ms, _ = timed_calls(step, stream, args.steps, 0)
     # The dominant kernel alone: the same steps again with HIP events recorded
     # around every launch of the histogram kernel on the call's stream (kept out
     # of the run above, whose step time they would lengthen).
@@ -724,7 +764,6 @@ def main():
     k_ms, k_launches = ctx.kernel_time()
     ctx.set_kernel_timing(False)
     k_avg = k_ms / max(1, k_launches)
-    ms_mean = float(np.mean(ms))
     nvox = vol.size
     gvox = nvox / (ms_mean * 1e-3) / 1e9
     alg_bytes = nvox * 4            # each f32 voxel read once
@@ -770,13 +809,16 @@ def main():
         log("timing AUTO range ...")
         # AUTO and explicit calls alternate, so both see the same state of the
         # device; the min/max pass alone is the difference of their medians
-        pair = [0]
+        modes = []
 
         def alternate():
-            ctx.compute(vol_d, nbins, value_range="auto" if pair[0] % 2 == 0 else (lo, hi), out=out, stream=stream)
-            pair[0] += 1
+            auto = len(modes) % 2 == 0
+            ctx.compute(vol_d, nbins, value_range="auto" if auto else (lo, hi), out=out, stream=stream)
+            modes.append(auto)
         ms_ae, _ = timed_calls(alternate, stream, 40, 4)
-        ms_a, ms_e = ms_ae[0::2], ms_ae[1::2]
+        timed_modes = modes[-40:]   # the calls the 40 timings belong to
+        ms_a = [m for m, a in zip(ms_ae, timed_modes) if a]
+        ms_e = [m for m, a in zip(ms_ae, timed_modes) if not a]
         result["auto_range_ms"] = round(float(np.median(ms_a)), 4)
         mm_ms = max(1e-6, float(np.median(ms_a)) - float(np.median(ms_e)))
         mm_rate = alg_bytes / (mm_ms * 1e-3) / 1e9
@@ -795,13 +837,11 @@ def main():
         shape2 = None
         if not args.no_autotune:
             shape2 = ctx.autotune(img2_d, nbins, value_range="auto", reps=3, stream=stream)
-        ms2, _ = timed_calls(lambda: ctx.compute(img2_d, nbins, value_range="auto", out=out,
-                                                 stream=stream), stream, 20, 3)
-        m2 = float(np.mean(ms2))
+        m2, _ = region_ms(lambda: ctx.compute(img2_d, nbins, value_range="auto", out=out,
+                                              stream=stream), stream, 20, 3)
         lo2, hi2 = int(img2.min()), int(img2.max())
-        ms2e, _ = timed_calls(lambda: ctx.compute(img2_d, nbins, value_range=(lo2, hi2), out=out,
-                                                  stream=stream), stream, 20, 3)
-        m2e = float(np.mean(ms2e))
+        m2e, _ = region_ms(lambda: ctx.compute(img2_d, nbins, value_range=(lo2, hi2), out=out,
+                                               stream=stream), stream, 20, 3)
         result["plain_2d_u16"] = {"shape": [16384, 16384], "ms": round(m2, 4),
                                   "gvox_s": round(img2.size / (m2 * 1e-3) / 1e9, 2),
                                   "hbm_frac": round(img2.size * 2 / (m2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -825,18 +865,17 @@ def main():
         nv = int(sum(a.size for a in imgs))
         dev_imgs = [torch.from_numpy(a).to(dev) for a in imgs]
         outs = [torch.empty(256, dtype=torch.int64, device=dev) for _ in imgs]
-        ms_b, _ = timed_calls(lambda: ctx.compute_batch(dev_imgs, 256, outs=outs, stream=stream),
-                              stream, 5, 2)
+        mb, _ = region_ms(lambda: ctx.compute_batch(dev_imgs, 256, outs=outs, stream=stream), stream, 5, 2)
 
         def per_image():
             for a, o in zip(dev_imgs, outs):
                 ctx.compute(a, 256, out=o, stream=stream)
-        ms_p, _ = timed_calls(per_image, stream, 5, 2)
+        mp, _ = region_ms(per_image, stream, 5, 2)
         # the same batch planned once, its launch shape tuned, and replayed from a
         # captured HIP graph
         plan = ctx.plan_batch(dev_imgs, 256, outs=outs)
         plan_shape = plan.autotune(reps=3, stream=stream)
-        ms_l, _ = timed_calls(lambda: plan.launch(stream=stream), stream, 5, 2)
+        ml, _ = region_ms(lambda: plan.launch(stream=stream), stream, 5, 2)
         gs = torch.cuda.Stream(dev)
         gs.wait_stream(stream)
         with torch.cuda.stream(gs):
@@ -845,15 +884,14 @@ def main():
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph, stream=gs):
             plan.launch(stream=gs)
-        ms_g, _ = timed_calls(graph.replay, stream, 5, 2)
+        mg, _ = region_ms(graph.replay, stream, 5, 2)
         torch.cuda.synchronize()
         plan.close()
-        mb, mp, mg = float(np.mean(ms_b)), float(np.mean(ms_p)), float(np.mean(ms_g))
         result["batched"] = {"images": len(imgs), "voxels": nv, "ms": round(mb, 3),
                              "images_per_s": round(len(imgs) / (mb * 1e-3), 1),
                              "gvox_s": round(nv / (mb * 1e-3) / 1e9, 2),
                              "hbm_frac": round(nv / (mb * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                             "planned_ms": round(float(np.mean(ms_l)), 3), "plan_shape": plan_shape,
+                             "planned_ms": round(ml, 3), "plan_shape": plan_shape,
                              "graph_replay_ms": round(mg, 3),
                              "per_image_calls_ms": round(mp, 3),
                              "speedup_vs_per_image": round(mp / mb, 3)}
