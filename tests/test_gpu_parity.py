@@ -513,6 +513,29 @@ def test_bins_per_pass_split(oracle_mod, cons):
         ctx.close()
 
 
+def test_reserve_then_calls_fit(oracle_mod):
+    """ecc_reserve grows the scratch and table buffers ahead of the calls (which
+    then give the oracle's ECC as before); sizes beyond its limits are refused
+    and leave the context usable."""
+    from paper_2203_09087_amd import ecc
+    rng = np.random.default_rng(55)
+    imgs = [rng.integers(0, 256, size=s).astype(np.uint8) for s in ((40, 50), (6, 30, 70), (300, 200))]
+    ctx = ecc.Context(0, "vertex")
+    try:
+        scratch, tables = ecc.batch_reserve_bytes(len(imgs), sum(a.size for a in imgs), 256, 256)
+        ctx.reserve(scratch, tables)
+        with pytest.raises(ecc.EccError):
+            ctx.reserve(1 << 41, 0)
+        with pytest.raises(ecc.EccError):
+            ctx.reserve(0, 1 << 31)
+        outs = ctx.compute_batch([to_dev(a) for a in imgs], 256)
+        torch.cuda.synchronize()
+        for a, o in zip(imgs, outs):
+            assert np.array_equal(o.cpu().numpy(), oracle_mod.ecc(a, 256, "vertex", value_range=(0, 255)))
+    finally:
+        ctx.close()
+
+
 @pytest.mark.parametrize("cons", CONS)
 def test_histogram_copies(oracle_mod, cons):
     """2, 4 or 8 copies of the LDS histogram (lane l adds to copy l mod copies),
