@@ -35,9 +35,11 @@
  *
  * Conventions shared by every entry point:
  *   - Images are DEVICE pointers, contiguous, row-major, dims[0] slowest.  Any
- *     alignment is accepted.  ndim is 2, 3 or 4 (see ecc_compute for 4D images;
- *     ecc_compute_streamed returns ECC_ERR_UNSUPPORTED for a 4D image); every
- *     dim is >= 1.
+ *     alignment is accepted.  ndim is 2 to ECC_MAX_NDIM (see ecc_compute for
+ *     images of 4 or more dimensions); entry points that do not take a
+ *     dimension return ECC_ERR_UNSUPPORTED for it: ecc_compute_streamed takes 2
+ *     and 3, the batch calls, plans and ecc_compute_noalloc 2 to 4.  Every dim
+ *     is >= 1.
  *   - `out` is a DEVICE pointer to nbins int64 values, overwritten (not
  *     accumulated) with the ECC.  1 <= nbins <= 65535.
  *   - Every call validates all of its arguments on the host before anything is
@@ -75,6 +77,10 @@ typedef enum {
 
 typedef enum { ECC_U8 = 0, ECC_U16 = 1, ECC_F32 = 2 } ecc_dtype;
 
+/* Most dimensions of an image (the cubical complex of Sec. 2.1 is defined in
+ * every dimension). */
+#define ECC_MAX_NDIM 8
+
 typedef enum { ECC_VERTEX = 0, ECC_TOP = 1 } ecc_construction;
 
 typedef enum {
@@ -86,9 +92,9 @@ typedef enum {
 /* One image of a call.  Enum-valued fields are int32_t for a fixed layout. */
 typedef struct {
     const void* data;    /* device pointer to the voxels */
-    int32_t ndim;        /* 2 or 3; 4 where the entry point takes 4D images */
+    int32_t ndim;        /* 2 .. ECC_MAX_NDIM, as the entry point takes them */
     int32_t dtype;       /* ecc_dtype */
-    int64_t dims[4];     /* dims[0] slowest; entries beyond ndim are ignored */
+    int64_t dims[ECC_MAX_NDIM]; /* dims[0] slowest; entries beyond ndim are ignored */
     int32_t range_mode;  /* ecc_range_mode */
     int32_t reserved;    /* must be 0 */
     double lo, hi;       /* used with ECC_RANGE_EXPLICIT only */
@@ -129,11 +135,16 @@ ecc_status ecc_reserve(ecc_ctx* ctx, size_t scratch_bytes, size_t table_bytes);
 const char* ecc_last_error(const ecc_ctx* ctx);
 
 /* ECC of one image with the default range (Eq. (1), Sec. 2.3).
- * image: device pointer; ndim 2|3|4; dims: HOST pointer to ndim int64;
- * dtype: ecc_dtype; out: device pointer to nbins int64 (overwritten).
+ * image: device pointer; ndim 2 .. ECC_MAX_NDIM; dims: HOST pointer to ndim
+ * int64; dtype: ecc_dtype; out: device pointer to nbins int64 (overwritten).
  * A 4D image (the cubical complex of Sec. 2.1 in four dimensions) is computed as
  * signed 3D passes over its hyperplanes dims[0] and over the elementwise max
- * (vertex) or min (top) of adjacent hyperplanes.
+ * (vertex) or min (top) of adjacent hyperplanes.  An image of five or more
+ * dimensions is reduced the same way one axis at a time down to 4D: each
+ * hyperplane of axis 0 and the elementwise max (min) of each adjacent pair,
+ * the latter written into the context's scratch (one hyperplane per reduced
+ * axis), is a (d-1)-dimensional image counted with its sign; the 3D passes
+ * number prod over the first d-3 axes of (2 dims[i] - 1).
  * Errors: ECC_ERR_INVALID_ARG for any bad argument (nothing enqueued),
  * ECC_ERR_OUT_OF_MEMORY, ECC_ERR_DEVICE. */
 ecc_status ecc_compute(ecc_ctx* ctx, const void* image, int32_t ndim, const int64_t* dims,
@@ -141,14 +152,14 @@ ecc_status ecc_compute(ecc_ctx* ctx, const void* image, int32_t ndim, const int6
 
 /* ECC of one image described by `img` (HOST pointer to the descriptor; its data
  * and out fields are device pointers).  Same semantics and errors as ecc_compute
- * (ndim 2|3|4), plus the range selection of the descriptor; an AUTO range of a
- * 4D image is the min/max of all its hyperplanes. */
+ * (ndim 2 .. ECC_MAX_NDIM), plus the range selection of the descriptor; an AUTO
+ * range of an image of 4 or more dimensions is the min/max of all its voxels. */
 ecc_status ecc_compute_ex(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, void* hip_stream);
 
 /* ecc_compute_ex for callers that cannot allocate device memory: code being
  * captured into a HIP graph, tight serving loops, harnesses that forbid
  * hipMalloc.  Same arguments, semantics, results and errors as ecc_compute_ex
- * (ndim 2|3|4), but the call allocates nothing (no hipMalloc/hipFree, no
+ * (ndim 2 to 4; ECC_ERR_UNSUPPORTED for more), but the call allocates nothing (no hipMalloc/hipFree, no
  * allocating library routine): its scratch is a fixed array of 24 MiB
  * (kNoAllocBytes) that the library keeps on each device it runs on, set up by
  * the first ecc_create on that device and held until the process ends.  The
@@ -167,7 +178,8 @@ ecc_status ecc_compute_noalloc(ecc_ctx* ctx, const ecc_image* img, int32_t nbins
  * enters as its signed 3D passes (hyperplanes and adjacent max/min pairs, as in
  * ecc_compute), each counted like a 3D image of the batch into rows of its own
  * image.  The result of every image is identical to what ecc_compute_ex returns
- * for it alone.
+ * for it alone.  Images of more than 4 dimensions are refused
+ * (ECC_ERR_UNSUPPORTED).
  * count == 0 is a no-op.  Errors as above; the index of the first bad descriptor
  * is named in ecc_last_error. */
 ecc_status ecc_compute_batch(ecc_ctx* ctx, const ecc_image* imgs, int32_t count, int32_t nbins,
@@ -220,10 +232,11 @@ typedef struct {
 
 /* Times a set of launch shapes for the image `img` on hip_stream (`reps` calls
  * each, after one warm-up; the calls overwrite img->out) and makes `ctx` use the
- * fastest for every later call on an image with the same ndim, dims, dtype and
- * filtration and nbins on the same side of 4096.  Every shape gives the same
- * ECC; only the time differs.  A 4D image is tuned for the shape of its 3D
- * passes (the launches of ecc_compute on it).  Blocks until the timing runs have
+ * fastest for every later call on an image with the same ndim, dims (for 4 or
+ * more dimensions: the last three), dtype and filtration and nbins on the same
+ * side of 4096.  Every shape gives the same
+ * ECC; only the time differs.  An image of 4 or more dimensions is tuned for
+ * the shape of its 3D passes (the launches of ecc_compute on it).  Blocks until the timing runs have
  * finished.
  * chosen (HOST pointer, may be null) receives the chosen shape.  Not for use
  * during graph capture.
@@ -238,7 +251,7 @@ ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32
  * tuned in another process, e.g. in a run under a profiler, whose timings the
  * profiler distorts.  A field <= 0 keeps the default for that field; `ms` is
  * ignored.  The result of a call does not depend on the shape.  Enqueues
- * nothing.  img->data and img->out are not read; img->ndim is 2, 3 or 4.
+ * nothing.  img->data and img->out are not read; img->ndim is 2 .. ECC_MAX_NDIM.
  * Errors: ECC_ERR_INVALID_ARG (null pointer, an invalid descriptor as for
  * ecc_compute_ex, waves above 9, wgs_per_cu above 16, depth above 4096, window
  * above 4096, copies other than 0, 2, 4 or 8). */

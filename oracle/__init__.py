@@ -88,7 +88,7 @@ def _as_image(image):
     a = np.ascontiguousarray(image)
     if a.dtype not in DTYPES:
         raise TypeError(f"unsupported dtype {a.dtype}")
-    if a.ndim < 1 or a.ndim > 4 or a.size == 0:
+    if a.ndim < 1 or a.ndim > 8 or a.size == 0:
         raise ValueError(f"unsupported shape {a.shape}")
     return a
 
@@ -136,7 +136,7 @@ def prefix(vcec):
 
 
 def ecc(image, nbins: int, construction: str = "vertex", value_range=None, threads: int = 1):
-    """ECC (int64[nbins]) of a u8/u16/f32 image of 1 to 3 dimensions."""
+    """ECC (int64[nbins]) of a u8/u16/f32 image of 1 to 8 dimensions."""
     lib = _load()
     a = _as_image(image)
     mode, lo, hi = _range_args(value_range)

@@ -1,7 +1,7 @@
 /*
  * ecc_oracle.c -- reference ("oracle") computation of the Euler characteristic
- * curve of a 1D/2D/3D/4D grayscale image (the definitions are the same in every
- * dimension, Sec. 2.1).
+ * curve of a grayscale image of 1 to 8 dimensions (the definitions are the same
+ * in every dimension, Sec. 2.1).
  *
  * TEST INFRASTRUCTURE ONLY.  This file is a plain, slow, obviously correct CPU
  * implementation used to check the GPU library bit for bit.  It shares no code,
@@ -52,7 +52,7 @@ enum { ORACLE_U8 = 0, ORACLE_U16 = 1, ORACLE_F32 = 2 };
 enum { ORACLE_VERTEX = 0, ORACLE_TOP = 1 };
 enum { ORACLE_RANGE_DEFAULT = 0, ORACLE_RANGE_EXPLICIT = 1, ORACLE_RANGE_AUTO = 2 };
 
-#define ORACLE_MAX_NDIM 4
+#define ORACLE_MAX_NDIM 8
 
 /* ---------------------------------------------------------------- binning */
 

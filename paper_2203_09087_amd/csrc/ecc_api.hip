@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstddef>
 #include <cmath>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -160,37 +161,42 @@ ecc_status ensure_ws(ecc_ctx* ctx, size_t bytes)
     return ECC_OK;
 }
 
-// Validated form of one image.
 // the descriptor layout the bindings mirror
-static_assert(sizeof(ecc_image) == 80 && offsetof(ecc_image, dims) == 16 && offsetof(ecc_image, range_mode) == 48 &&
-                  offsetof(ecc_image, lo) == 56 && offsetof(ecc_image, out) == 72,
+static_assert(sizeof(ecc_image) == 112 && offsetof(ecc_image, dims) == 16 && offsetof(ecc_image, range_mode) == 80 &&
+                  offsetof(ecc_image, lo) == 88 && offsetof(ecc_image, out) == 104,
               "ecc_image layout");
+
+// Validated form of one image.
 
 struct Job {
     const void* data;
     const void* data2;    // 4D pair passes: count the max (min) of data and data2
     int ndim, dtype, range_mode;
-    ecc::Geom g;          // 2D/3D: the image; 4D: one hyperplane (dims[1..3])
-    int64_t nw;           // 4D: hyperplanes (dims[0]); else 1
+    ecc::Geom g;          // 2D/3D: the image; 4D and up: the last three axes
+    int64_t nw;           // 4D and up: dims[ndim-4] (hyperplanes of a 4D part); else 1
+    int64_t dims[ECC_MAX_NDIM];
     int64_t nvox;
     double lo, hi;
     int64_t* out;
 };
 
-// max_ndim: 4 for every call but streaming (3).
+// max_ndim: the most dimensions the entry point takes (ECC_MAX_NDIM for the
+// single-image calls, 4 for batches and the fixed-scratch call, 3 for
+// streaming); a valid ndim above it is ECC_ERR_UNSUPPORTED.
 ecc_status validate(ecc_ctx* ctx, const ecc_image& im, int32_t nbins, const char* where, Job* job,
-                    int max_ndim = 3)
+                    int max_ndim)
 {
     char buf[256];
     if (!im.data) { snprintf(buf, sizeof buf, "%s: null image pointer", where); return fail(ctx, ECC_ERR_INVALID_ARG, buf); }
     if (!im.out) { snprintf(buf, sizeof buf, "%s: null output pointer", where); return fail(ctx, ECC_ERR_INVALID_ARG, buf); }
-    if (im.ndim == 4 && max_ndim < 4) {
-        snprintf(buf, sizeof buf, "%s: 4D images are not taken by streaming", where);
-        return fail(ctx, ECC_ERR_UNSUPPORTED, buf);
-    }
-    if (im.ndim < 2 || im.ndim > 4) {
-        snprintf(buf, sizeof buf, "%s: ndim must be 2, 3 or 4 (got %d)", where, im.ndim);
+    if (im.ndim < 2 || im.ndim > ECC_MAX_NDIM) {
+        snprintf(buf, sizeof buf, "%s: ndim must be in [2, %d] (got %d)", where, ECC_MAX_NDIM, im.ndim);
         return fail(ctx, ECC_ERR_INVALID_ARG, buf);
+    }
+    if (im.ndim > max_ndim) {
+        snprintf(buf, sizeof buf, "%s: images of more than %d dimensions are not taken here (got %d)", where,
+                 max_ndim, im.ndim);
+        return fail(ctx, ECC_ERR_UNSUPPORTED, buf);
     }
     if (im.dtype != ECC_U8 && im.dtype != ECC_U16 && im.dtype != ECC_F32) {
         snprintf(buf, sizeof buf, "%s: unknown dtype %d", where, im.dtype);
@@ -252,11 +258,12 @@ ecc_status validate(ecc_ctx* ctx, const ecc_image& im, int32_t nbins, const char
     job->lo = im.range_mode == ECC_RANGE_DEFAULT ? 0.0 : im.lo;
     job->hi = im.range_mode == ECC_RANGE_DEFAULT ? 255.0 : im.hi;
     job->nw = 1;
-    if (im.ndim == 2) job->g = {1, im.dims[0], im.dims[1]};
-    else if (im.ndim == 3) job->g = {im.dims[0], im.dims[1], im.dims[2]};
+    for (int i = 0; i < ECC_MAX_NDIM; ++i) job->dims[i] = i < im.ndim ? im.dims[i] : 1;
+    const int d = im.ndim;
+    if (d == 2) job->g = {1, im.dims[0], im.dims[1]};
     else {
-        job->g = {im.dims[1], im.dims[2], im.dims[3]};
-        job->nw = im.dims[0];
+        job->g = {im.dims[d - 3], im.dims[d - 2], im.dims[d - 1]};
+        if (d >= 4) job->nw = im.dims[d - 4];
     }
     job->nvox = nvox;
     job->out = im.out;
@@ -545,52 +552,36 @@ ecc_status enqueue_one(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t st
     return enqueue_hist(ctx, base, j, nbins, stream, sz, pdev, j.g.n0, 0, j.g.n0, false, true);
 }
 
-// A 4D image as signed 3D passes (the cells of a 4D complex are 3D cells times
-// a vertex or an edge of the first axis, Sec. 2.1).  With H_w the hyperplanes:
-//   vertex: VCEC = sum_w V3(H_w) - sum_{w<n-1} V3(max(H_w, H_{w+1}))
-//   top:    VCEC = sum_w c_w T3(H_w) + sum_{w<n-1} T3(min(H_w, H_{w+1})),
+// An image of four or more dimensions as signed 3D passes.  The cells of a
+// d-dimensional complex are (d-1)-dimensional cells times a vertex or an edge
+// of the first axis (Sec. 2.1), so with H_w the hyperplanes of that axis:
+//   vertex: VCEC = sum_w V(H_w) - sum_{w<n-1} V(max(H_w, H_{w+1}))
+//   top:    VCEC = sum_w c_w T(H_w) + sum_{w<n-1} T(min(H_w, H_{w+1})),
 //           c_w = -1 + [w == 0] + [w == n-1]
-// A pair pass reads both hyperplanes and counts the max (min) of their keys.
-// Every pass adds into (or subtracts from) the caller's output, the last one
-// scans it.  The binning parameters are the whole image's.
-ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t stream, bool no_alloc = false,
-                      const ecc_launch_shape* force = nullptr)
+// (elementwise max and min).  Applied once, this takes a 4D image to 3D passes;
+// a pair pass reads both hyperplanes and counts the max (min) of their keys.
+// Above four dimensions it is applied one axis at a time, and the max (min) of
+// two hyperplanes of a reduced axis is written into a buffer of that axis in
+// the scratch, whose hyperplanes the next axis then reads.  Every pass adds
+// into (or subtracts from) the caller's output, the last one scans it.  The
+// binning parameters are the whole image's.
+
+// The 3D passes of one 4D image or 4D part (at img4, nw hyperplanes of the
+// shape of h), each times `outer`; the first part writes out, the others add
+// to it, and the last one scans it.
+ecc_status enqueue_4d_part(ecc_ctx* ctx, char* base, const Sizes& sz, Job h, const char* img4, int64_t nw,
+                           const ecc::BinParams* pdev, int32_t nbins, hipStream_t stream, int outer, bool first,
+                           bool last)
 {
-    const int64_t nw = j4.nw;
-    const int64_t hv = j4.g.n0 * j4.g.n1 * j4.g.n2;
-    const size_t esize = j4.dtype == ECC_U8 ? 1 : (j4.dtype == ECC_U16 ? 2 : 4);
-    Job h = j4;   // one hyperplane as a 3D image
-    h.ndim = 3;
-    h.nw = 1;
-    h.nvox = hv;
-    // the passes' launch shape: forced, tuned for this 4D shape, or the default
-    if (!force) {
-        auto it = ctx->tuned.find(tune_key(ctx, j4, nbins));
-        if (it != ctx->tuned.end()) force = &it->second;
-    }
-    Sizes sz = plan_sizes(ctx, h, nbins, force);
-    char* base = nullptr;
-    ecc_status st = call_scratch(ctx, h, no_alloc, sz, &base);
-    if (st != ECC_OK) return st;
-    ecc::BinParams* pdev = nullptr;
-    hipError_t e;
-    if (j4.range_mode == ECC_RANGE_AUTO) {
-        uint32_t* mm = (uint32_t*)(base + sz.off_mm);
-        pdev = (ecc::BinParams*)(base + sz.off_params);
-        const int blocks = (int)std::min<int64_t>(kMinmaxBlocks, (j4.nvox + 4095) / 4096);
-        if ((e = ecc::launch_minmax(j4.data, j4.dtype, j4.nvox, mm, blocks, stream)) != hipSuccess)
-            return hip_fail(ctx, e, "minmax launch");
-        if ((e = ecc::launch_params_from_minmax(mm, blocks, j4.dtype, nbins, pdev, stream)) != hipSuccess)
-            return hip_fail(ctx, e, "params launch");
-    }
-    const char* img = (const char*)j4.data;
+    const int64_t hv = h.nvox;
+    const size_t esize = h.dtype == ECC_U8 ? 1 : (h.dtype == ECC_U16 ? 2 : 4);
     const bool vertex = ctx->construction == ECC_VERTEX;
     // the passes in order: hyperplane w (sign c_w, skipped when 0), then the
     // pair (w, w+1); counted first, then enqueued (no host allocation)
     auto single_sign = [&](int64_t w) { return vertex ? 1 : -1 + (w == 0) + (w == nw - 1); };
     int64_t npasses = 0;
     for (int64_t w = 0; w < nw; ++w) npasses += (single_sign(w) != 0) + (w + 1 < nw);
-    auto plane = [&](int64_t w) { return (const void*)(img + (size_t)w * (size_t)hv * esize); };
+    auto plane = [&](int64_t w) { return (const void*)(img4 + (size_t)w * (size_t)hv * esize); };
     // With one LDS window the passes add into the same workgroup rows and one
     // merge follows, when the int32 rows cannot overflow: a workgroup sees at
     // most ceil(bricks / grid) bricks of chunk x rows x depth voxels per pass, and
@@ -598,6 +589,7 @@ ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t st
     const int64_t bricks = ecc::wg_bricks(3, ctx->construction, h.g, sz.waves, sz.depth);
     const int64_t per_wg = (bricks + sz.grid - 1) / sz.grid * ecc::kLaneCols * sz.waves * ecc::kRows3 * sz.depth;
     const bool one_merge = sz.window >= nbins && npasses * per_wg < (int64_t(1) << 28);
+    ecc_status st;
     int64_t k = 0;
     for (int64_t w = 0; w < nw; ++w) {
         for (int pair = 0; pair < 2; ++pair) {
@@ -605,20 +597,97 @@ ecc_status enqueue_4d(ecc_ctx* ctx, const Job& j4, int32_t nbins, hipStream_t st
             if (sign == 0 || (pair && w + 1 >= nw)) continue;
             h.data = plane(w);
             h.data2 = pair ? plane(w + 1) : nullptr;
-            if ((st = enqueue_hist(ctx, base, h, nbins, stream, sz, pdev, h.g.n0, 0, h.g.n0, k > 0,
-                                   k + 1 == npasses, sign, one_merge, k > 0)) != ECC_OK)
+            if ((st = enqueue_hist(ctx, base, h, nbins, stream, sz, pdev, h.g.n0, 0, h.g.n0, !first || k > 0,
+                                   last && k + 1 == npasses, sign * outer, one_merge, k > 0)) != ECC_OK)
                 return st;
             ++k;
         }
     }
     if (one_merge) {
         uint32_t* counters = (uint32_t*)(base + sz.off_counters);
-        if ((e = ecc::launch_merge((int32_t*)(base + sz.off_partials), sz.grid, nbins, 0,
-                                   (int64_t*)(base + sz.off_level2), j4.out, nbins, counters, false, true, 1,
-                                   stream)) != hipSuccess)
-            return hip_fail(ctx, e, "merge launch");
+        const hipError_t e = ecc::launch_merge((int32_t*)(base + sz.off_partials), sz.grid, nbins, 0,
+                                               (int64_t*)(base + sz.off_level2), h.out, nbins, counters, !first,
+                                               last, 1, stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "merge launch");
     }
     return ECC_OK;
+}
+
+ecc_status enqueue_nd(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t stream, bool no_alloc = false,
+                      const ecc_launch_shape* force = nullptr)
+{
+    const int d = j.ndim;
+    const size_t esize = j.dtype == ECC_U8 ? 1 : (j.dtype == ECC_U16 ? 2 : 4);
+    Job h = j;   // one hyperplane of the last three axes, as a 3D image
+    h.ndim = 3;
+    h.nw = 1;
+    h.nvox = j.g.n0 * j.g.n1 * j.g.n2;
+    h.data2 = nullptr;
+    // the passes' launch shape: forced, tuned for this image's shape, or the default
+    if (!force) {
+        auto it = ctx->tuned.find(tune_key(ctx, j, nbins));
+        if (it != ctx->tuned.end()) force = &it->second;
+    }
+    Sizes sz = plan_sizes(ctx, h, nbins, force);
+    // one buffer per reduced axis a < d-4, a hyperplane of it, after the rest
+    size_t mat_off[ECC_MAX_NDIM] = {};
+    int64_t plane_vox[ECC_MAX_NDIM] = {};
+    int64_t left = j.nvox;
+    for (int a = 0; a + 4 < d; ++a) {
+        left /= j.dims[a];
+        plane_vox[a] = left;
+        mat_off[a] = sz.total;
+        sz.total += align_up((size_t)left * esize);
+    }
+    if (d > 4 && no_alloc) return fail(ctx, ECC_ERR_UNSUPPORTED, "images of more than 4 dimensions need scratch");
+    char* base = nullptr;
+    ecc_status st = call_scratch(ctx, h, no_alloc, sz, &base);
+    if (st != ECC_OK) return st;
+    ecc::BinParams* pdev = nullptr;
+    hipError_t e;
+    if (j.range_mode == ECC_RANGE_AUTO) {
+        uint32_t* mm = (uint32_t*)(base + sz.off_mm);
+        pdev = (ecc::BinParams*)(base + sz.off_params);
+        const int blocks = (int)std::min<int64_t>(kMinmaxBlocks, (j.nvox + 4095) / 4096);
+        if ((e = ecc::launch_minmax(j.data, j.dtype, j.nvox, mm, blocks, stream)) != hipSuccess)
+            return hip_fail(ctx, e, "minmax launch");
+        if ((e = ecc::launch_params_from_minmax(mm, blocks, j.dtype, nbins, pdev, stream)) != hipSuccess)
+            return hip_fail(ctx, e, "params launch");
+    }
+    const bool vertex = ctx->construction == ECC_VERTEX;
+    auto single_sign = [&](int64_t w, int64_t n) { return vertex ? 1 : -1 + (w == 0) + (w == n - 1); };
+    // 4D parts in all: per reduced axis, its hyperplanes of nonzero sign and its pairs
+    int64_t parts = 1;
+    for (int a = 0; a + 4 < d; ++a) {
+        int64_t c = j.dims[a] - 1;
+        for (int64_t w = 0; w < j.dims[a]; ++w) c += single_sign(w, j.dims[a]) != 0;
+        parts *= c;
+    }
+    int64_t done = 0;
+    // axis a of the (d-a)-dimensional volume at vol, counted with sign
+    std::function<ecc_status(int, const char*, int)> visit = [&](int a, const char* vol, int sign) -> ecc_status {
+        if (a + 4 == d) {
+            const bool first = done == 0, last = done + 1 == parts;
+            ++done;
+            return enqueue_4d_part(ctx, base, sz, h, vol, j.dims[a], pdev, nbins, stream, sign, first, last);
+        }
+        const int64_t n = j.dims[a];
+        const size_t pb = (size_t)plane_vox[a] * esize;
+        char* m = base + mat_off[a];
+        for (int64_t w = 0; w < n; ++w) {
+            ecc_status r;
+            const int c = single_sign(w, n);
+            if (c != 0 && (r = visit(a + 1, vol + (size_t)w * pb, sign * c)) != ECC_OK) return r;
+            if (w + 1 < n) {
+                hipError_t ce = ecc::launch_combine(vol + (size_t)w * pb, vol + (size_t)(w + 1) * pb, m,
+                                                    plane_vox[a], j.dtype, vertex, stream);
+                if (ce != hipSuccess) return hip_fail(ctx, ce, "combine launch");
+                if ((r = visit(a + 1, m, vertex ? -sign : sign)) != ECC_OK) return r;
+            }
+        }
+        return ECC_OK;
+    };
+    return visit(0, (const char*)j.data, 1);
 }
 
 // ------------------------------------------------------------------ batches
@@ -701,7 +770,7 @@ void build_batch_tables(int cu_count, int construction, const std::vector<Job>& 
     T.window = std::min<int32_t>(nbins, ecc::kMaxLdsBins);
     T.images.assign((size_t)count, ecc::BatchImage{});
     // the volumes that are counted, in image order: a 2D or 3D image itself; a
-    // 4D image's signed 3D passes (as in enqueue_4d), appended after the images
+    // 4D image's signed 3D passes (as in enqueue_nd), appended after the images
     std::vector<int> vols;
     for (int i = 0; i < count; ++i) {
         const Job& j = jobs[(size_t)i];
@@ -1158,11 +1227,11 @@ ecc_status ecc_compute_ex(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, voi
     ctx->err.clear();
     if (!img) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_compute_ex: null descriptor");
     Job j;
-    ecc_status st = validate(ctx, *img, nbins, "ecc_compute_ex", &j, 4);
+    ecc_status st = validate(ctx, *img, nbins, "ecc_compute_ex", &j, ECC_MAX_NDIM);
     if (st != ECC_OK) return st;
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed");
-    if (j.ndim == 4) return enqueue_4d(ctx, j, nbins, (hipStream_t)hip_stream);
+    if (j.ndim >= 4) return enqueue_nd(ctx, j, nbins, (hipStream_t)hip_stream);
     return enqueue_one(ctx, j, nbins, (hipStream_t)hip_stream);
 }
 
@@ -1179,7 +1248,7 @@ ecc_status ecc_compute_noalloc(ecc_ctx* ctx, const ecc_image* img, int32_t nbins
     if (ctx->device < 0 || ctx->device >= kMaxDevices || !g_noalloc_ptr[ctx->device]) {
         if ((st = noalloc_setup(ctx->device, ctx->err)) != ECC_OK) return st;
     }
-    if (j.ndim == 4) return enqueue_4d(ctx, j, nbins, (hipStream_t)hip_stream, true);
+    if (j.ndim >= 4) return enqueue_nd(ctx, j, nbins, (hipStream_t)hip_stream, true);
     return enqueue_one(ctx, j, nbins, (hipStream_t)hip_stream, nullptr, true);
 }
 
@@ -1189,7 +1258,7 @@ ecc_status ecc_compute(ecc_ctx* ctx, const void* image, int32_t ndim, const int6
     if (!ctx) return ECC_ERR_INVALID_ARG;
     ctx->err.clear();
     if (!dims) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_compute: null dims");
-    if (ndim < 2 || ndim > 4) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_compute: ndim must be 2, 3 or 4");
+    if (ndim < 2 || ndim > ECC_MAX_NDIM) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_compute: ndim must be in [2, 8]");
     ecc_image im;
     memset(&im, 0, sizeof im);
     im.data = image;
@@ -1199,11 +1268,11 @@ ecc_status ecc_compute(ecc_ctx* ctx, const void* image, int32_t ndim, const int6
     im.range_mode = ECC_RANGE_DEFAULT;
     im.out = out;
     Job j;
-    ecc_status st = validate(ctx, im, nbins, "ecc_compute", &j, 4);
+    ecc_status st = validate(ctx, im, nbins, "ecc_compute", &j, ECC_MAX_NDIM);
     if (st != ECC_OK) return st;
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed");
-    if (j.ndim == 4) return enqueue_4d(ctx, j, nbins, (hipStream_t)hip_stream);
+    if (j.ndim >= 4) return enqueue_nd(ctx, j, nbins, (hipStream_t)hip_stream);
     return enqueue_one(ctx, j, nbins, (hipStream_t)hip_stream);
 }
 
@@ -1442,7 +1511,7 @@ ecc_status ecc_set_launch_shape(ecc_ctx* ctx, const ecc_image* img, int32_t nbin
                     "ecc_set_launch_shape: waves must be at most 9, wgs_per_cu at most 16, depth at most 4096, "
                     "window at most 4096, copies 0, 2, 4 or 8");
     Job j;
-    ecc_status st = validate(ctx, *img, nbins, "ecc_set_launch_shape", &j, 4);
+    ecc_status st = validate(ctx, *img, nbins, "ecc_set_launch_shape", &j, ECC_MAX_NDIM);
     if (st != ECC_OK) return st;
     ecc_launch_shape c = *shape;
     c.ms = 0.0;
@@ -1458,7 +1527,7 @@ ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32
     if (!img) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_autotune: null descriptor");
     if (reps < 1 || reps > 1000) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_autotune: reps must be in [1, 1000]");
     Job j;
-    ecc_status st = validate(ctx, *img, nbins, "ecc_autotune", &j, 4);
+    ecc_status st = validate(ctx, *img, nbins, "ecc_autotune", &j, ECC_MAX_NDIM);
     if (st != ECC_OK) return st;
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed");
@@ -1466,17 +1535,18 @@ ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32
     const TuneKey key = tune_key(ctx, j, nbins);
     ctx->tuned.erase(key);
     // candidates: the default shape, then waves, depth and workgroups per CU
-    // around it (every shape gives the same result; only the time differs); a
-    // 4D image is tuned for its 3D passes (one hyperplane's shape)
+    // around it (every shape gives the same result; only the time differs); an
+    // image of 4 or more dimensions is tuned for its 3D passes (the shape of
+    // its last three axes)
     Job shape_job = j;
-    if (j.ndim == 4) {
+    if (j.ndim >= 4) {
         shape_job.ndim = 3;
         shape_job.nw = 1;
         shape_job.nvox = j.g.n0 * j.g.n1 * j.g.n2;
     }
     const Sizes def = plan_sizes(ctx, shape_job, nbins);
     auto run = [&](const ecc_launch_shape* c) {
-        return j.ndim == 4 ? enqueue_4d(ctx, j, nbins, stream, false, c) : enqueue_one(ctx, j, nbins, stream, c);
+        return j.ndim >= 4 ? enqueue_nd(ctx, j, nbins, stream, false, c) : enqueue_one(ctx, j, nbins, stream, c);
     };
     const int64_t cols = (ecc::axis_positions(j.g.n2, ctx->construction) + ecc::kLaneCols - 1) / ecc::kLaneCols;
     std::vector<ecc_launch_shape> cand;
@@ -1546,7 +1616,7 @@ ecc_status ecc_compute_streamed(ecc_ctx* ctx, const ecc_image* img, int32_t nbin
     if (!img) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_compute_streamed: null descriptor");
     if (slab_planes < 0) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_compute_streamed: negative slab_planes");
     Job j;
-    ecc_status st = validate(ctx, *img, nbins, "ecc_compute_streamed", &j);
+    ecc_status st = validate(ctx, *img, nbins, "ecc_compute_streamed", &j, 3);
     if (st != ECC_OK) return st;
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed");

@@ -239,6 +239,10 @@ hipError_t launch_smooth13(const float* in, float* out, float* tmp, int64_t n1, 
                            hipStream_t s);
 hipError_t launch_minmax(const void* data, int dtype, int64_t nvox, uint32_t* mm_out, int blocks,
                          hipStream_t s);
+// Elementwise max (take_max) or min of the n values at a and b into out, NaN
+// taken as the largest float (the reduction of images of 5+ dimensions).
+hipError_t launch_combine(const void* a, const void* b, void* out, int64_t n, int dtype, bool take_max,
+                          hipStream_t s);
 hipError_t launch_params_from_minmax(const uint32_t* mm, int blocks, int dtype, int32_t nbins,
                                      BinParams* out, hipStream_t s);
 hipError_t launch_ecc(const EccLaunch& L, hipStream_t s);

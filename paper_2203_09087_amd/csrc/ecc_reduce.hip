@@ -44,6 +44,31 @@ __global__ __launch_bounds__(kThreads) void k_minmax(const void* data, int64_t n
     }
 }
 
+// Elementwise max (take_max) or min of two hyperplanes of an image, for the
+// reduction of an image of five or more dimensions one axis at a time (a cell
+// that spans two adjacent hyperplanes takes the max of its vertices' values in
+// the vertex filtration and the min of its voxels' in the top one, Sec. 2.1).
+// The combined value must bin to the max (min) of the two bins, and binning is
+// monotone with NaN in the last bin: NaN is taken as the largest float here.
+template <int DT, bool MAX>
+__global__ __launch_bounds__(kThreads) void k_combine(const void* a, const void* b, void* out, int64_t n)
+{
+    using T = typename ValT<DT>::T;
+    const T* __restrict__ x = (const T*)a;
+    const T* __restrict__ y = (const T*)b;
+    T* __restrict__ z = (T*)out;
+    const int64_t nthreads = (int64_t)gridDim.x * kThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += nthreads) {
+        const T u = x[i], v = y[i];
+        if constexpr (DT == DT_F32) {
+            if constexpr (MAX) z[i] = (u != u || u > v) ? u : v;    // v NaN: u > v fails, v wins
+            else z[i] = (v != v || u < v) ? u : v;                  // u NaN: u < v fails, v wins
+        } else {
+            z[i] = MAX ? (u > v ? u : v) : (u < v ? u : v);
+        }
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_params(const uint32_t* mm, int blocks, int dtype,
                                                      int32_t nbins, BinParams* out)
 {
@@ -231,6 +256,22 @@ hipError_t launch_minmax(const void* data, int dtype, int64_t nvox, uint32_t* mm
     case DT_U8: hipLaunchKernelGGL(k_minmax<DT_U8>, dim3(blocks), dim3(kThreads), 0, s, data, nvox, mm); break;
     case DT_U16: hipLaunchKernelGGL(k_minmax<DT_U16>, dim3(blocks), dim3(kThreads), 0, s, data, nvox, mm); break;
     default: hipLaunchKernelGGL(k_minmax<DT_F32>, dim3(blocks), dim3(kThreads), 0, s, data, nvox, mm); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const void* a, const void* b, void* out, int64_t n, int dtype, bool take_max,
+                          hipStream_t s)
+{
+    const unsigned blocks = (unsigned)std::min<int64_t>(4096, (n + kThreads - 1) / kThreads);
+    const dim3 g(blocks > 0 ? blocks : 1), t(kThreads);
+    switch (dtype * 2 + (take_max ? 1 : 0)) {
+    case DT_U8 * 2: hipLaunchKernelGGL((k_combine<DT_U8, false>), g, t, 0, s, a, b, out, n); break;
+    case DT_U8 * 2 + 1: hipLaunchKernelGGL((k_combine<DT_U8, true>), g, t, 0, s, a, b, out, n); break;
+    case DT_U16 * 2: hipLaunchKernelGGL((k_combine<DT_U16, false>), g, t, 0, s, a, b, out, n); break;
+    case DT_U16 * 2 + 1: hipLaunchKernelGGL((k_combine<DT_U16, true>), g, t, 0, s, a, b, out, n); break;
+    case DT_F32 * 2: hipLaunchKernelGGL((k_combine<DT_F32, false>), g, t, 0, s, a, b, out, n); break;
+    default: hipLaunchKernelGGL((k_combine<DT_F32, true>), g, t, 0, s, a, b, out, n); break;
     }
     return hipGetLastError();
 }

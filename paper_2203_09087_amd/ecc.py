@@ -24,6 +24,7 @@ ECC_OK, ECC_ERR_INVALID_ARG, ECC_ERR_UNSUPPORTED, ECC_ERR_OUT_OF_MEMORY, ECC_ERR
 ECC_U8, ECC_U16, ECC_F32 = 0, 1, 2
 ECC_VERTEX, ECC_TOP = 0, 1
 ECC_RANGE_DEFAULT, ECC_RANGE_EXPLICIT, ECC_RANGE_AUTO = 0, 1, 2
+ECC_MAX_NDIM = 8   # most dimensions of an image
 
 STATUS_NAMES = {0: "ECC_OK", 1: "ECC_ERR_INVALID_ARG", 2: "ECC_ERR_UNSUPPORTED",
                 3: "ECC_ERR_OUT_OF_MEMORY", 4: "ECC_ERR_DEVICE"}
@@ -43,7 +44,7 @@ class ecc_image(ctypes.Structure):
         ("data", ctypes.c_void_p),
         ("ndim", ctypes.c_int32),
         ("dtype", ctypes.c_int32),
-        ("dims", ctypes.c_int64 * 4),
+        ("dims", ctypes.c_int64 * ECC_MAX_NDIM),
         ("range_mode", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
         ("lo", ctypes.c_double),
@@ -279,7 +280,7 @@ def make_image(t, out, value_range=None) -> ecc_image:
     im.data = t.data_ptr()
     im.ndim = t.dim()
     im.dtype = _dtype_code(t)
-    for i, s in enumerate(t.shape[:4]):
+    for i, s in enumerate(t.shape[:ECC_MAX_NDIM]):
         im.dims[i] = int(s)
     im.range_mode, im.lo, im.hi = _range_fields(value_range)
     im.out = out.data_ptr()
@@ -306,7 +307,7 @@ def _image_record():
     import numpy as np
     f = {n: getattr(ecc_image, n) for n, _ in ecc_image._fields_}
     _RECORD.append(np.dtype({"names": [n for n, _ in ecc_image._fields_],
-                     "formats": [np.uint64, np.int32, np.int32, (np.int64, 4), np.int32, np.int32, np.float64,
+                     "formats": [np.uint64, np.int32, np.int32, (np.int64, ECC_MAX_NDIM), np.int32, np.int32, np.float64,
                                  np.float64, np.uint64],
                      "offsets": [f[n].offset for n, _ in ecc_image._fields_],
                      "itemsize": ctypes.sizeof(ecc_image)}))
@@ -329,9 +330,10 @@ def make_images(tensors, outs, value_ranges=None):
         code = codes.get(t.dtype)
         if code is None:
             raise TypeError(f"unsupported dtype {t.dtype}")
-        sh = tuple(t.shape)[:4]
+        sh = tuple(t.shape)[:ECC_MAX_NDIM]
         mode, lo, hi = (ECC_RANGE_DEFAULT, 0.0, 0.0) if r is None else _range_fields(r)
-        rows.append((t.data_ptr(), len(t.shape), code, sh + (0,) * (4 - len(sh)), mode, 0, lo, hi, o.data_ptr()))
+        rows.append((t.data_ptr(), len(t.shape), code, sh + (0,) * (ECC_MAX_NDIM - len(sh)), mode, 0, lo, hi,
+                     o.data_ptr()))
     return np.array(rows, dtype=_image_record())
 
 

@@ -46,10 +46,12 @@ def test_library_exports_every_declared_symbol():
 def test_descriptor_layout():
     from paper_2203_09087_amd import ecc
     im = ecc.ecc_image
-    assert ctypes.sizeof(im) == 80
+    assert ctypes.sizeof(im) == 112 and ecc.ECC_MAX_NDIM == 8
     assert im.data.offset == 0 and im.ndim.offset == 8 and im.dtype.offset == 12
-    assert im.dims.offset == 16 and im.range_mode.offset == 48 and im.reserved.offset == 52
-    assert im.lo.offset == 56 and im.hi.offset == 64 and im.out.offset == 72
+    assert im.dims.offset == 16 and im.range_mode.offset == 80 and im.reserved.offset == 84
+    assert im.lo.offset == 88 and im.hi.offset == 96 and im.out.offset == 104
+    with open(HEADER) as fh:
+        assert re.search(r"#define ECC_MAX_NDIM (\d+)", fh.read()).group(1) == str(ecc.ECC_MAX_NDIM)
 
 
 def test_create_without_device_reports_error():

@@ -89,10 +89,13 @@ def test_schedule_rejects_bad_descriptors():
     bad = _img((0, 5))
     st = ecc.ecc_batch_schedule([bad], 256)[0]
     assert st == ecc.ECC_ERR_INVALID_ARG and "dims" in ecc.ecc_last_error(None)
-    five = _img((2, 3, 4, 5))
-    five.ndim = 5
-    st = ecc.ecc_batch_schedule([five], 256)[0]
+    nine = _img((2, 3, 4, 5))
+    nine.ndim = 9
+    st = ecc.ecc_batch_schedule([nine], 256)[0]
     assert st == ecc.ECC_ERR_INVALID_ARG
+    # five dimensions are valid, but not taken by batches
+    st = ecc.ecc_batch_schedule([_img((2, 3, 4, 5, 6))], 256)[0]
+    assert st == ecc.ECC_ERR_UNSUPPORTED and "more than 4 dimensions" in ecc.ecc_last_error(None)
 
 
 @pytest.mark.parametrize("nw", [1, 2, 5])

@@ -307,7 +307,7 @@ def test_invalid_arguments_enqueue_nothing(ctxs):
                 setattr(im, k, v)
         return im
 
-    bad = [variant(data=None), variant(out=None), variant(ndim=1), variant(ndim=5),
+    bad = [variant(data=None), variant(out=None), variant(ndim=1), variant(ndim=9),
            variant(dtype=7), variant(range_mode=9), variant(reserved=1), variant(dims=(0, 8)),
            variant(dims=(8, -1)), variant(range_mode=ecc.ECC_RANGE_EXPLICIT, lo=3.0, hi=2.0),
            variant(range_mode=ecc.ECC_RANGE_EXPLICIT, lo=0.5, hi=2.0),
@@ -318,12 +318,12 @@ def test_invalid_arguments_enqueue_nothing(ctxs):
     for nb in (0, -1, 65536):
         assert ecc.ecc_compute_ex(h, good, nb) == ecc.ECC_ERR_INVALID_ARG
     assert ecc.ecc_compute(h, img.data_ptr(), 2, (8, 8), 0, 16, 0) == ecc.ECC_ERR_INVALID_ARG
-    assert ecc.ecc_compute(h, img.data_ptr(), 5, (8, 8), 0, 16, out.data_ptr()) == ecc.ECC_ERR_INVALID_ARG
+    assert ecc.ecc_compute(h, img.data_ptr(), 9, (8, 8), 0, 16, out.data_ptr()) == ecc.ECC_ERR_INVALID_ARG
     f = torch.zeros((4, 4), dtype=torch.float32, device="cuda")
     fim = ecc.make_image(f, out, (0.0, float("inf")))
     assert ecc.ecc_compute_ex(h, fim, 16) == ecc.ECC_ERR_INVALID_ARG
     # batch: the bad descriptor is named and nothing runs for the good ones either
-    st = ecc.ecc_compute_batch(h, [good, variant(ndim=5)], 16)
+    st = ecc.ecc_compute_batch(h, [good, variant(ndim=9)], 16)
     assert st == ecc.ECC_ERR_INVALID_ARG and "image 1" in ecc.ecc_last_error(h)
     torch.cuda.synchronize()
     assert (out.cpu() == -7).all()
