@@ -32,10 +32,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def timed_calls(fn, stream, steps, warmup):
-    """Runs fn() warmup+steps times on `stream`; returns per-call ms (HIP events)."""
+def timed_calls(fn, stream, steps, warmup, spin=True):
+    """Runs fn() warmup+steps times on `stream` (after spin_up, unless the caller
+    has just done it); returns per-call ms (HIP events)."""
     import torch
-    spin_up(fn)
+    if spin:
+        spin_up(fn)
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -309,9 +311,9 @@ MAIN_KERNEL = "k_ecc_3d<2, 0, false, false>"
 def write_trace_summary(db_path, bench_json):
     """Summarizes a `rocprofv3 --kernel-trace` database of `bench.py --no-side
     --no-serve --no-cpu` into the profiles folder: every kernel's statistics, and
-    the histogram kernel's mean over the timed launches (the last 2 * steps
-    dispatches: the timed pass and the pass with kernel events) beside the
-    kernel time the benchmark measured itself."""
+    the histogram kernel's mean over the launches the benchmark timed with
+    kernel events (the last `roofline.launches` dispatches: that pass's steps)
+    beside the kernel time the benchmark measured itself."""
     import sqlite3
     res = json.loads([l for l in open(bench_json) if l.startswith("{")][-1])
     steps = int(res["steps"])
@@ -321,19 +323,20 @@ def write_trace_summary(db_path, bench_json):
     for name, a, b in rows:
         stats.setdefault(name, []).append((b - a) / 1000.0)
     main = [(b - a) / 1000.0 for name, a, b in rows if MAIN_KERNEL in name]
-    timed = main[-2 * steps:]
+    timed = main[-int(res["roofline"]["launches"]):]
     total = sum(sum(v) for v in stats.values())
     out = ["# Kernel trace: 512^3 float32 GRF step (bench.py defaults without side runs)", "",
            "Commands (on one MI355X, from /tmp, $REPO the repository root):", "",
            f"    rocprofv3 --kernel-trace --stats -d $REPO/gpurun_out/prof -o run -- python3 $REPO/bench.py "
            f"--steps {steps} --warmup {res['warmup']} --no-cpu --no-side --no-serve > $REPO/gpurun_out/prof.json",
            "    python3 $REPO/bench.py --trace-summary $REPO/gpurun_out/prof/run_results.db $REPO/gpurun_out/prof.json", "",
-           f"Histogram kernel `{MAIN_KERNEL}` over the {len(timed)} timed launches "
+           f"Histogram kernel `{MAIN_KERNEL}` over the {len(timed)} launches timed with kernel events "
            f"(launch shape {res.get('launch_shape')}): mean {np.mean(timed):.2f} us, "
            f"min {np.min(timed):.2f} us, max {np.max(timed):.2f} us.  The benchmark's own HIP-event "
            f"measurement in the same run: {res['roofline']['kernel_ms'] * 1000:.2f} us per launch "
            f"(roofline.kernel_ms); step {res['ms_per_step'] * 1000:.1f} us.  Earlier dispatches of the "
-           "kernel are the launch-shape tuner's candidates.", "",
+           "kernel are the launch-shape tuner's candidates and the passes timed without kernel events "
+           "(each spun up to steady clocks first).", "",
            "| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---:|---:|---:|---:|---:|"]
     for name, v in sorted(stats.items(), key=lambda kv: -sum(kv[1])):
         short = name.replace("ecc::(anonymous namespace)::", "")
@@ -757,10 +760,11 @@ def main():
     # The dominant kernel alone: the same steps again with HIP events recorded
     # around every launch of the histogram kernel on the call's stream (kept out
     # of the run above, whose step time they would lengthen).
+    # Only the timed steps' launches carry the events (the spin-up calls run
+    # without them, one synchronisation every 8 calls).
+    spin_up(step)
     ctx.set_kernel_timing(True)
-    step()
-    ctx.kernel_time()
-    ms_k, _ = timed_calls(step, stream, args.steps, 0)
+    ms_k, _ = timed_calls(step, stream, args.steps, 0, spin=False)
     k_ms, k_launches = ctx.kernel_time()
     ctx.set_kernel_timing(False)
     k_avg = k_ms / max(1, k_launches)

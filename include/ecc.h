@@ -323,9 +323,10 @@ ecc_status ecc_batch_schedule(const ecc_image* imgs, int32_t count, int32_t nbin
                               int64_t* image_bricks, int64_t* covered_bricks);
 
 /* Kernel timing, for measurement tools (the method itself does not need it).
- * With enable != 0, every later call on `ctx` records a pair of HIP events on its
- * stream around each launch of the histogram kernel (the voxel pass of Sec. 2.3
- * that reads the image; AUTO min/max, merge and scan launches are not counted).
+ * With enable != 0, every later call on `ctx` gives each launch of the
+ * histogram kernel (the voxel pass of Sec. 2.3 that reads the image; AUTO
+ * min/max, merge and scan launches are not counted) a pair of HIP events that
+ * take that kernel's own start and end (hipExtLaunchKernel).
  * enable == 0 stops recording and drops unread records.  Timing changes no result.
  * Errors: ECC_ERR_INVALID_ARG (ctx null), ECC_ERR_DEVICE. */
 ecc_status ecc_set_kernel_timing(ecc_ctx* ctx, int32_t enable);

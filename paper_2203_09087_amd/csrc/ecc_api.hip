@@ -118,19 +118,20 @@ ecc_status fold_timing(ecc_ctx* ctx)
     return ECC_OK;
 }
 
-// Runs `launch` (returning hipError_t) between a pair of timing events when the
-// context records kernel timing.
+// Runs `launch(start, stop)` (returning hipError_t), with a pair of timing
+// events when the context records kernel timing, else with null events.  The
+// events go to the launch itself (hipExtLaunchKernel), which gives them the
+// kernel's own start and end: events recorded on the stream around it would
+// also count the wait between the start marker and the dispatch (about 6 us on
+// a 150 us kernel).
 template <class F>
-hipError_t timed_launch(ecc_ctx* ctx, hipStream_t s, F&& launch)
+hipError_t timed_launch(ecc_ctx* ctx, F&& launch)
 {
-    if (!ctx->timing) return launch();
+    if (!ctx->timing) return launch(nullptr, nullptr);
     if (ctx->tused == kTimingPairs && fold_timing(ctx) != ECC_OK) return hipErrorUnknown;
-    hipError_t e = hipEventRecord(ctx->tev[2 * ctx->tused], s);
-    if (e != hipSuccess) return e;
-    if ((e = launch()) != hipSuccess) return e;
-    if ((e = hipEventRecord(ctx->tev[2 * ctx->tused + 1], s)) != hipSuccess) return e;
-    ctx->tused += 1;
-    return hipSuccess;
+    const hipError_t e = launch(ctx->tev[2 * ctx->tused], ctx->tev[2 * ctx->tused + 1]);
+    if (e == hipSuccess) ctx->tused += 1;
+    return e;
 }
 
 ecc_status ensure_ws(ecc_ctx* ctx, size_t bytes)
@@ -498,12 +499,13 @@ ecc_status enqueue_hist(ecc_ctx* ctx, char* base, const Job& j, int32_t nbins, h
     L.hist_copies = sz.hist_copies;
     L.sentinel = sz.sentinel;
     L.lds_bytes = sz.lds_bytes;
+    auto launch_l = [&](hipEvent_t t0, hipEvent_t t1) { return ecc::launch_ecc(L, stream, t0, t1); };
     hipError_t e;
     if (pass_only) {
         // one window, histogram kernel only: its rows are merged by a later call
         L.bin_lo = 0;
         L.width = sz.window;
-        if ((e = timed_launch(ctx, stream, [&] { return ecc::launch_ecc(L, stream); })) != hipSuccess)
+        if ((e = timed_launch(ctx, launch_l)) != hipSuccess)
             return hip_fail(ctx, e, "ecc launch");
         return ECC_OK;
     }
@@ -514,7 +516,7 @@ ecc_status enqueue_hist(ecc_ctx* ctx, char* base, const Job& j, int32_t nbins, h
         L.bin_lo = 0;
         L.width = nbins;
         L.fused = 1;
-        if ((e = timed_launch(ctx, stream, [&] { return ecc::launch_ecc(L, stream); })) != hipSuccess)
+        if ((e = timed_launch(ctx, launch_l)) != hipSuccess)
             return hip_fail(ctx, e, "ecc launch");
         return ECC_OK;
     }
@@ -522,7 +524,7 @@ ecc_status enqueue_hist(ecc_ctx* ctx, char* base, const Job& j, int32_t nbins, h
         L.bin_lo = b0;
         L.width = std::min<int32_t>(sz.window, nbins - b0);
         const bool last = b0 + L.width >= nbins;
-        if ((e = timed_launch(ctx, stream, [&] { return ecc::launch_ecc(L, stream); })) != hipSuccess)
+        if ((e = timed_launch(ctx, launch_l)) != hipSuccess)
             return hip_fail(ctx, e, "ecc launch");
         if ((e = ecc::launch_merge(L.partials, L.grid, L.width, L.bin_lo, (int64_t*)(base + sz.off_level2),
                                    j.out, nbins, counters, accumulate, scan && last, sign, stream)) != hipSuccess)
@@ -948,9 +950,10 @@ ecc_status launch_batch_kernels(ecc_ctx* ctx, const BatchTables& T, char* d, boo
             B.grid = gr.grid;
             B.wg_seg = (const int32_t*)(d + lay.wg_seg) + gr.wg_seg_first;
             B.pairs = gr.pairs ? 1 : 0;
-            if ((e = timed_launch(ctx, stream, [&] { return ecc::launch_ecc_batch(B, ctx->construction, stream); })) !=
-                hipSuccess)
-                return hip_fail(ctx, e, "batch launch");
+            auto launch_b = [&](hipEvent_t t0, hipEvent_t t1) {
+                return ecc::launch_ecc_batch(B, ctx->construction, stream, t0, t1);
+            };
+            if ((e = timed_launch(ctx, launch_b)) != hipSuccess) return hip_fail(ctx, e, "batch launch");
         }
         if ((e = ecc::launch_merge_batch(B, b0 + B.width >= T.nbins, stream)) != hipSuccess)
             return hip_fail(ctx, e, "batch merge launch");

@@ -10,6 +10,8 @@
 // does not depend on the batch it is in.
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "ecc_device.h"
 
 namespace ecc {
@@ -141,30 +143,36 @@ __global__ __launch_bounds__(kThreads) void k_scan_batch(BatchLaunch B)
     block_scan_inplace(B.images[blockIdx.x].out, B.nbins);
 }
 
-template <int DT, int CONS, bool PAIRS>
-hipError_t launch_batch_p(const BatchLaunch& B, hipStream_t s)
+template <class K>
+hipError_t launch_batch_k(K kernel, const BatchLaunch& B, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
 {
-    if (B.windowed)
-        hipLaunchKernelGGL((k_ecc_batch<DT, CONS, true, PAIRS>), dim3(B.grid), dim3(B.waves * 64), B.lds_bytes, s, B);
+    if (t0 || t1)
+        hipExtLaunchKernelGGL(kernel, dim3(B.grid), dim3(B.waves * 64), B.lds_bytes, s, t0, t1, 0, B);
     else
-        hipLaunchKernelGGL((k_ecc_batch<DT, CONS, false, PAIRS>), dim3(B.grid), dim3(B.waves * 64), B.lds_bytes, s,
-                           B);
+        hipLaunchKernelGGL(kernel, dim3(B.grid), dim3(B.waves * 64), B.lds_bytes, s, B);
     return hipGetLastError();
 }
 
-template <int DT, int CONS>
-hipError_t launch_batch_w(const BatchLaunch& B, hipStream_t s)
+template <int DT, int CONS, bool PAIRS>
+hipError_t launch_batch_p(const BatchLaunch& B, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
 {
-    return B.pairs ? launch_batch_p<DT, CONS, true>(B, s) : launch_batch_p<DT, CONS, false>(B, s);
+    return B.windowed ? launch_batch_k(k_ecc_batch<DT, CONS, true, PAIRS>, B, s, t0, t1)
+                      : launch_batch_k(k_ecc_batch<DT, CONS, false, PAIRS>, B, s, t0, t1);
+}
+
+template <int DT, int CONS>
+hipError_t launch_batch_w(const BatchLaunch& B, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
+{
+    return B.pairs ? launch_batch_p<DT, CONS, true>(B, s, t0, t1) : launch_batch_p<DT, CONS, false>(B, s, t0, t1);
 }
 
 template <int CONS>
-hipError_t launch_batch_d(const BatchLaunch& B, hipStream_t s)
+hipError_t launch_batch_d(const BatchLaunch& B, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
 {
     switch (B.dtype) {
-    case DT_U8: return launch_batch_w<DT_U8, CONS>(B, s);
-    case DT_U16: return launch_batch_w<DT_U16, CONS>(B, s);
-    default: return launch_batch_w<DT_F32, CONS>(B, s);
+    case DT_U8: return launch_batch_w<DT_U8, CONS>(B, s, t0, t1);
+    case DT_U16: return launch_batch_w<DT_U16, CONS>(B, s, t0, t1);
+    default: return launch_batch_w<DT_F32, CONS>(B, s, t0, t1);
     }
 }
 
@@ -223,9 +231,9 @@ hipError_t launch_mm_init(uint32_t* mm, int count, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_ecc_batch(const BatchLaunch& B, int construction, hipStream_t s)
+hipError_t launch_ecc_batch(const BatchLaunch& B, int construction, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
 {
-    return construction == CONS_TOP ? launch_batch_d<CONS_TOP>(B, s) : launch_batch_d<CONS_VERTEX>(B, s);
+    return construction == CONS_TOP ? launch_batch_d<CONS_TOP>(B, s, t0, t1) : launch_batch_d<CONS_VERTEX>(B, s, t0, t1);
 }
 
 hipError_t launch_merge_batch(const BatchLaunch& B, bool scan, hipStream_t s)

@@ -209,7 +209,8 @@ struct BatchLaunch {
 // Launchers (ecc_batch.hip).
 hipError_t launch_minmax_batch(const BatchImage* images, const BatchPiece* pieces, int npieces, uint32_t* mm,
                                hipStream_t s);
-hipError_t launch_ecc_batch(const BatchLaunch& B, int construction, hipStream_t s);
+hipError_t launch_ecc_batch(const BatchLaunch& B, int construction, hipStream_t s, hipEvent_t t0 = nullptr,
+                            hipEvent_t t1 = nullptr);
 // Sets mm[2i] = ~0, mm[2i+1] = 0 for the `count` images (a kernel, so that the
 // enqueue stays valid inside a captured graph).
 hipError_t launch_mm_init(uint32_t* mm, int count, hipStream_t s);
@@ -245,7 +246,7 @@ hipError_t launch_combine(const void* a, const void* b, void* out, int64_t n, in
                           hipStream_t s);
 hipError_t launch_params_from_minmax(const uint32_t* mm, int blocks, int dtype, int32_t nbins,
                                      BinParams* out, hipStream_t s);
-hipError_t launch_ecc(const EccLaunch& L, hipStream_t s);
+hipError_t launch_ecc(const EccLaunch& L, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 // Sums the `rows` partial histograms into out[bin_lo..bin_lo+width) (through
 // `level2`, kLevel2Words int64 of scratch) and, with `scan`, prefix-sums
 // out[0..nbins).  counters[0] is the merge's last-block counter, which the merge

@@ -6,6 +6,8 @@
 #include <mutex>
 #include <tuple>
 
+#include <hip/hip_ext.h>
+
 #include "ecc_device.h"
 
 namespace ecc {
@@ -68,44 +70,50 @@ int64_t wg_bricks(int ndim, int construction, const Geom& g, int waves, int64_t 
     return nxc * ((axis_positions(g.n1, construction) + kRows3 - 1) / kRows3) * ((g.n0 + depth - 1) / depth);
 }
 
-template <int NDIM, int DT, int CONS, bool WIN>
-static hipError_t launch_t(const EccLaunch& L, hipStream_t s)
+template <class K>
+static hipError_t launch_k(K kernel, const EccLaunch& L, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
 {
-    if constexpr (NDIM == 2)
-        hipLaunchKernelGGL((k_ecc_2d<DT, CONS, WIN>), dim3(L.grid), dim3(L.waves * 64), L.lds_bytes, s, L);
-    else if (L.data2)
-        hipLaunchKernelGGL((k_ecc_3d<DT, CONS, WIN, true>), dim3(L.grid), dim3(L.waves * 64), L.lds_bytes, s, L);
+    if (t0 || t1)
+        hipExtLaunchKernelGGL(kernel, dim3(L.grid), dim3(L.waves * 64), L.lds_bytes, s, t0, t1, 0, L);
     else
-        hipLaunchKernelGGL((k_ecc_3d<DT, CONS, WIN, false>), dim3(L.grid), dim3(L.waves * 64), L.lds_bytes, s, L);
+        hipLaunchKernelGGL(kernel, dim3(L.grid), dim3(L.waves * 64), L.lds_bytes, s, L);
     return hipGetLastError();
 }
 
-template <int NDIM, int DT, int CONS>
-static hipError_t launch_w(const EccLaunch& L, hipStream_t s)
+template <int NDIM, int DT, int CONS, bool WIN>
+static hipError_t launch_t(const EccLaunch& L, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
 {
-    return L.windowed ? launch_t<NDIM, DT, CONS, true>(L, s) : launch_t<NDIM, DT, CONS, false>(L, s);
+    if constexpr (NDIM == 2) return launch_k(k_ecc_2d<DT, CONS, WIN>, L, s, t0, t1);
+    else if (L.data2) return launch_k(k_ecc_3d<DT, CONS, WIN, true>, L, s, t0, t1);
+    else return launch_k(k_ecc_3d<DT, CONS, WIN, false>, L, s, t0, t1);
+}
+
+template <int NDIM, int DT, int CONS>
+static hipError_t launch_w(const EccLaunch& L, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
+{
+    return L.windowed ? launch_t<NDIM, DT, CONS, true>(L, s, t0, t1) : launch_t<NDIM, DT, CONS, false>(L, s, t0, t1);
 }
 
 template <int NDIM, int DT>
-static hipError_t launch_c(const EccLaunch& L, hipStream_t s)
+static hipError_t launch_c(const EccLaunch& L, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
 {
-    return L.construction == CONS_TOP ? launch_w<NDIM, DT, CONS_TOP>(L, s)
-                                      : launch_w<NDIM, DT, CONS_VERTEX>(L, s);
+    return L.construction == CONS_TOP ? launch_w<NDIM, DT, CONS_TOP>(L, s, t0, t1)
+                                      : launch_w<NDIM, DT, CONS_VERTEX>(L, s, t0, t1);
 }
 
 template <int NDIM>
-static hipError_t launch_d(const EccLaunch& L, hipStream_t s)
+static hipError_t launch_d(const EccLaunch& L, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
 {
     switch (L.dtype) {
-    case DT_U8: return launch_c<NDIM, DT_U8>(L, s);
-    case DT_U16: return launch_c<NDIM, DT_U16>(L, s);
-    default: return launch_c<NDIM, DT_F32>(L, s);
+    case DT_U8: return launch_c<NDIM, DT_U8>(L, s, t0, t1);
+    case DT_U16: return launch_c<NDIM, DT_U16>(L, s, t0, t1);
+    default: return launch_c<NDIM, DT_F32>(L, s, t0, t1);
     }
 }
 
-hipError_t launch_ecc(const EccLaunch& L, hipStream_t s)
+hipError_t launch_ecc(const EccLaunch& L, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
 {
-    return L.ndim == 2 ? launch_d<2>(L, s) : launch_d<3>(L, s);
+    return L.ndim == 2 ? launch_d<2>(L, s, t0, t1) : launch_d<3>(L, s, t0, t1);
 }
 
 template <int NDIM, int DT, int CONS, bool WIN>
