@@ -335,13 +335,16 @@ Sizes plan_sizes(const ecc_ctx* ctx, const Job& j, int32_t nbins, const ecc_laun
     const int64_t cols = (xpos + ecc::kLaneCols - 1) / ecc::kLaneCols;
     const int64_t max_waves = j.ndim == 3 ? ECC_MAX_WAVES_3D : ecc::kMaxWaves;
     s.waves = (int)(cols <= max_waves ? cols : std::min<int64_t>(8, max_waves));
+    // 3D: when the last wave of a row would own only a few columns, one wave
+    // fewer and a packed tail (ecc::layout_3d) keep more lanes busy
+    if (j.ndim == 3 && cols > 1 && cols <= max_waves && ecc::layout_3d(j.g, cons, (int)cols - 1).spw > 0)
+        s.waves = (int)cols - 1;
     if (tuned && tuned->waves > 0) s.waves = (int)std::min<int64_t>(std::min<int64_t>(tuned->waves, ecc::kMaxWaves), cols);
     const int64_t chunk = ecc::kLaneCols * (int64_t)s.waves;
     const int64_t nxc = (xpos + chunk - 1) / chunk;
     const int64_t target = 2 * (int64_t)ctx->cu_count;
     if (j.ndim == 3) {
-        const int64_t nyb = (ecc::axis_positions(j.g.n1, cons) + ecc::kRows3 - 1) / ecc::kRows3;
-        int64_t d = (j.g.n0 * nxc * nyb + target - 1) / target;
+        int64_t d = (j.g.n0 * ecc::layout_3d(j.g, cons, s.waves).per_z + target - 1) / target;
         s.depth = std::min<int64_t>(std::max<int64_t>(d, 4), 32);
         if (tuned && tuned->depth > 0) s.depth = std::min<int64_t>(tuned->depth, 256);
     } else {

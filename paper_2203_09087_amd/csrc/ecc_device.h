@@ -450,6 +450,28 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v)
     const uint32_t lo = uniform_u32((uint32_t)v), hi = uniform_u32((uint32_t)((uint64_t)v >> 32));
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
+__device__ __forceinline__ double uniform_f64(double v)
+{
+    return __longlong_as_double((long long)uniform_i64((int64_t)__double_as_longlong(v)));
+}
+// The binning parameters that key_of reads, read back from the first lane.
+// Loaded through a pointer they arrive in vector registers (the kernels also
+// write global memory, so the compiler does not load them through the scalar
+// cache); as uniform values they stay in scalar registers, which the binning's
+// fp64 operations read directly, and leave the vector registers to the brick
+// loop.
+// (Float data only: the integer kernels have fewer vector registers in use and
+// are short of scalar ones.)
+template <int DT>
+__device__ __forceinline__ BinParams uniform_params(BinParams p)
+{
+    if constexpr (DT == DT_F32) {
+        p.nbins = (int32_t)uniform_u32((uint32_t)p.nbins);
+        p.base = uniform_f64(p.base);
+        p.scale = uniform_f64(p.scale);
+    }
+    return p;
+}
 __device__ __forceinline__ const void* uniform_ptr(const void* p) { return (const void*)uniform_i64((int64_t)p); }
 
 // Raw buffer loads: one 32-bit per-lane byte offset (the column) plus one scalar
@@ -824,12 +846,32 @@ __device__ __forceinline__ WaveCols wave_cols(int64_t x0, int wave, int64_t n2, 
     return w;
 }
 
-// One 3D workgroup brick (x-chunk xc, row block yb, plane block zb) for this wave.
-// `xw`: this wave's place among the waves of the brick.  Position columns and
-// rows start at -1 for the top filtration (the lattice point before voxel 0).
-template <int DT, int CONS, bool WIN, bool PAIR = false>
-__device__ __forceinline__ void run_brick_3d(const EccLaunch& L, const BinParams& P, const HistRef& H,
-                                             int64_t chunk, uint32_t xc, uint32_t yb, uint32_t zb, int xw)
+// Where one wave works in a 3D brick: its first row ys (row r of the brick is
+// image row ys + r), planes [z0, zend), the lane's byte offset in a row (xob)
+// and out-of-image mask (oob), the lanes that add (own), and the rows [r_lo,
+// r_hi) of the brick that lie in the image.
+struct Brick3 {
+    bool active;
+    int64_t ys;
+    uint32_t z0, zend, xob, oob;
+    uint64_t own;
+    int r_lo, r_hi;
+};
+
+// The planes of plane block zb.
+__device__ __forceinline__ void brick_planes(const EccLaunch& L, uint32_t zb, Brick3& B)
+{
+    B.z0 = zb * (uint32_t)L.depth;
+    const int64_t z_own = L.z_own;   // planes counted (the image's, or a slab's)
+    B.zend = ((int64_t)B.z0 + L.depth < z_own) ? B.z0 + (uint32_t)L.depth : (uint32_t)z_own;
+}
+
+// An ordinary 3D workgroup brick (x-chunk xc, strip yb, plane block zb) for
+// wave xw.  Position columns and rows start at -1 for the top filtration (the
+// lattice point before voxel 0).
+template <int DT, int CONS, bool WIN>
+__device__ __forceinline__ Brick3 chunk_brick_3d(const EccLaunch& L, const HistRef& H, int64_t chunk, uint32_t xc,
+                                                 uint32_t yb, uint32_t zb, int xw)
 {
     xc = uniform_u32(xc);
     yb = uniform_u32(yb);
@@ -839,23 +881,84 @@ __device__ __forceinline__ void run_brick_3d(const EccLaunch& L, const BinParams
     using T = typename ValT<DT>::T;
     const int64_t n1 = L.g.n1, n2 = L.g.n2;
     const WaveCols w = wave_cols<WIN>(org + (int64_t)xc * chunk, xw, n2, H.sm);
-    if (!w.active) return;
-    const uint32_t xob = w.xo * (uint32_t)sizeof(T);
-    const int64_t ys = org + (int64_t)yb * NR;
-    const uint32_t z0 = zb * (uint32_t)L.depth;
-    const int64_t z_own = L.z_own;   // planes counted (the image's, or a slab's)
-    const uint32_t zend = ((int64_t)z0 + L.depth < z_own) ? z0 + (uint32_t)L.depth : (uint32_t)z_own;
-    // rows r in [r_lo, r_hi) of the brick (row r is ys + r) lie inside the image
-    const int r_lo = ys < 0 ? (int)(-ys) : 0;
-    const int r_hi = (int)((n1 - ys) < NR + 1 ? (n1 - ys) : NR + 1);
-    const bool full = r_lo == 0 && r_hi == NR + 1;
+    Brick3 B;
+    B.active = w.active;
+    B.xob = w.xo * (uint32_t)sizeof(T);
+    B.oob = w.oob;
+    B.own = w.own;
+    B.ys = org + (int64_t)yb * NR;
+    brick_planes(L, zb, B);
+    // rows r in [r_lo, r_hi) of the brick lie inside the image
+    B.r_lo = B.ys < 0 ? (int)(-B.ys) : 0;
+    B.r_hi = (int)((n1 - B.ys) < NR + 1 ? (n1 - B.ys) : NR + 1);
+    return B;
+}
+
+// A packed tail brick (packed brick pk of plane block zb, Layout3) for wave xw:
+// tail strips s0 .. s0 + spw - 1, lane l on strip s0 + l / (t + 1) and position
+// column tail_start + l % (t + 1); the lanes at l % (t + 1) == t only supply
+// their left neighbours' right ones.  Every strip's rows lie in the image, so the
+// brick is a full one, each lane's row offset folded into its column offset.
+template <int DT, int CONS, bool WIN>
+__device__ __forceinline__ Brick3 tail_brick_3d(const EccLaunch& L, const HistRef& H, const Layout3& Y, int waves,
+                                                uint32_t pk, uint32_t zb, int xw)
+{
+    pk = uniform_u32(pk);
+    zb = uniform_u32(zb);
+    constexpr int NR = kRows3;
+    constexpr int64_t org = CONS == CONS_TOP ? -1 : 0;
+    using T = typename ValT<DT>::T;
+    const int64_t n2 = L.g.n2;
+    const int64_t s0 = Y.sa + ((int64_t)pk * waves + xw) * Y.spw;   // the wave's first strip
+    Brick3 B;
+    B.active = s0 < Y.sb;
+    const uint32_t group = (uint32_t)Y.t + 1u;
+    // the lane's place, computed here for each brick: the empty asm keeps the
+    // compiler from hoisting these per-lane values out of the brick loop, where
+    // they would hold registers through every brick's body
+    uint32_t lane = lane_id();
+    asm volatile("" : "+v"(lane));
+    uint32_t q = lane / group;
+    const uint32_t j = lane - q * group;
+    const bool strip_ok = q < (uint32_t)Y.spw && s0 + (int64_t)q < Y.sb;
+    if (!strip_ok) q = 0;   // reads the wave's first strip, adds nothing
+    const int64_t x = org + Y.nxc * kLaneCols * waves + (int64_t)j;
+    const bool x_ok = x >= 0 && x < n2;
+    B.oob = x_ok ? 0u : sentinel_key<WIN>(H.sm);
+    B.own = ballot(strip_ok && j < (uint32_t)Y.t);
+    const uint32_t xo = (uint32_t)(x < 0 ? 0 : (x >= n2 ? n2 - 1 : x));
+    const uint32_t row_bytes = (uint32_t)(n2 * (int64_t)sizeof(T));
+    B.xob = xo * (uint32_t)sizeof(T) + q * (uint32_t)NR * row_bytes;
+    B.ys = org + s0 * NR;
+    brick_planes(L, zb, B);
+    B.r_lo = 0;
+    B.r_hi = NR + 1;
+    return B;
+}
+
+// Runs a 3D brick (the body is inlined once for every kind of brick).
+template <int DT, int CONS, bool WIN, bool PAIR = false>
+__device__ __forceinline__ void run_brick3(const EccLaunch& L, const BinParams& P, const HistRef& H, const Brick3& B)
+{
+    constexpr int NR = kRows3;
+    if (!B.active) return;
+    const bool full = B.r_lo == 0 && B.r_hi == NR + 1;
     if (DT != DT_F32 && uniform_flag(P.ident)) {
-        if (full) brick_3d<DT, CONS, WIN, true, true, PAIR>(L, P, H, ys, z0, zend, xob, w.oob, w.own, r_lo, r_hi);
-        else brick_3d<DT, CONS, WIN, false, true, PAIR>(L, P, H, ys, z0, zend, xob, w.oob, w.own, r_lo, r_hi);
+        if (full) brick_3d<DT, CONS, WIN, true, true, PAIR>(L, P, H, B.ys, B.z0, B.zend, B.xob, B.oob, B.own, B.r_lo, B.r_hi);
+        else brick_3d<DT, CONS, WIN, false, true, PAIR>(L, P, H, B.ys, B.z0, B.zend, B.xob, B.oob, B.own, B.r_lo, B.r_hi);
     } else {
-        if (full) brick_3d<DT, CONS, WIN, true, false, PAIR>(L, P, H, ys, z0, zend, xob, w.oob, w.own, r_lo, r_hi);
-        else brick_3d<DT, CONS, WIN, false, false, PAIR>(L, P, H, ys, z0, zend, xob, w.oob, w.own, r_lo, r_hi);
+        if (full) brick_3d<DT, CONS, WIN, true, false, PAIR>(L, P, H, B.ys, B.z0, B.zend, B.xob, B.oob, B.own, B.r_lo, B.r_hi);
+        else brick_3d<DT, CONS, WIN, false, false, PAIR>(L, P, H, B.ys, B.z0, B.zend, B.xob, B.oob, B.own, B.r_lo, B.r_hi);
     }
+}
+
+// One ordinary 3D workgroup brick (x-chunk xc, strip yb, plane block zb) for
+// this wave (`xw`: its place among the waves of the brick).
+template <int DT, int CONS, bool WIN, bool PAIR = false>
+__device__ __forceinline__ void run_brick_3d(const EccLaunch& L, const BinParams& P, const HistRef& H,
+                                             int64_t chunk, uint32_t xc, uint32_t yb, uint32_t zb, int xw)
+{
+    run_brick3<DT, CONS, WIN, PAIR>(L, P, H, chunk_brick_3d<DT, CONS, WIN>(L, H, chunk, xc, yb, zb, xw));
 }
 
 // One 2D workgroup brick (x-chunk xc, row block yb) for this wave.

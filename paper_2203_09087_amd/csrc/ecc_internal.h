@@ -118,6 +118,57 @@ constexpr int kChunk2 = ECC_CHUNK2;    // rows loaded together in the 2D kernel
 // Waves per workgroup of the main kernels (x-chunk = waves * 63 position columns).
 constexpr int kMaxWaves = 9;
 
+// Workgroup bricks of a single 3D image (k_ecc_3d).  Ordinary bricks are an
+// x-chunk of 63 * waves position columns x kRows3 rows (a strip) x `depth`
+// planes, each wave on 63 columns of the chunk.  When the positions of a row
+// leave a narrow tail after the full chunks (t < 32 columns), a wave on the
+// tail would own t of its 63 lanes; instead the tail is packed: t + 1 lanes per
+// strip (t owning, one supplying the right neighbour), floor(64 / (t + 1))
+// strips per wave, for the strips whose rows (and the row after them) all lie
+// in the image; the few other strips' tails run as ordinary bricks.  A 512-wide
+// row then takes 8 waves of 63 columns and a packed tail of 8 instead of a
+// ninth wave with 8 columns.
+struct Layout3 {
+    int64_t nxc;        // x-chunks of the ordinary bricks of each strip (full ones)
+    int64_t nyb;        // strips
+    int64_t t;          // positions of the tail (0: none)
+    int64_t spw;        // tail strips per wave (0: the tail is not packed)
+    int64_t sa, sb;     // strips [sa, sb) have packed tails
+    int64_t npk;        // packed bricks per plane block
+    int64_t per_z;      // bricks per plane block
+};
+inline __host__ __device__ Layout3 layout_3d(const Geom& g, int construction, int waves)
+{
+    Layout3 y = {};
+    const int64_t cw = (int64_t)kLaneCols * waves;
+    const int64_t xpos = axis_positions(g.n2, construction);
+    const int64_t org = construction == CONS_TOP ? -1 : 0;
+    y.nyb = (axis_positions(g.n1, construction) + kRows3 - 1) / kRows3;
+    y.nxc = xpos / cw;
+    y.t = xpos - y.nxc * cw;
+    // strip s reads rows org + 3s .. org + 3s + 3 (the last one completes pairs)
+    y.sa = org < 0 ? 1 : 0;
+    y.sb = g.n1 - kRows3 - 1 - org >= 0 ? (g.n1 - kRows3 - 1 - org) / kRows3 + 1 : 0;
+    if (y.sb > y.nyb) y.sb = y.nyb;
+    const int64_t group = y.t + 1;
+    // a lane's rows are up to (3 spw + 1) rows past the wave's first: 32-bit offsets
+    const int64_t row_bytes = g.n2 * 4;
+    const bool pack = y.t > 0 && group <= 32 && y.sb > y.sa &&
+                      (kRows3 * (64 / group) + 1) * row_bytes < (int64_t(1) << 31);
+    if (pack) {
+        y.spw = 64 / group;
+        const int64_t per_brick = y.spw * waves;
+        y.npk = (y.sb - y.sa + per_brick - 1) / per_brick;
+        y.per_z = y.nxc * y.nyb + y.npk + (y.nyb - (y.sb - y.sa));
+    } else {
+        if (y.t > 0) y.nxc += 1;
+        y.t = 0;
+        y.sa = y.sb = 0;
+        y.per_z = y.nxc * y.nyb;
+    }
+    return y;
+}
+
 struct EccLaunch {
     const void* data;
     const void* data2;             // non-null (3D): count the elementwise max (min) of data and data2

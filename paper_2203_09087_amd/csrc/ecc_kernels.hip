@@ -24,17 +24,31 @@ template <int DT, int CONS, bool WIN, bool PAIR>
 __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU_3D))) void k_ecc_3d(EccLaunch L)
 {
     extern __shared__ __align__(16) int32_t hist[];
-    const BinParams P = L.params_dev ? *L.params_dev : L.params;
+    const BinParams P = uniform_params<DT>(L.params_dev ? *L.params_dev : L.params);
     const HistRef H = hist_ref(hist, L.bin_lo, L.width, L.hist_stride, L.sentinel, L.hist_copies);
     zero_hist(H, L.width);
-    const int64_t chunk = (int64_t)(blockDim.x >> 6) * kLaneCols;
-    const uint32_t nxc = (uint32_t)((axis_positions(L.g.n2, CONS) + chunk - 1) / chunk);
-    const uint32_t nyb = (uint32_t)((axis_positions(L.g.n1, CONS) + kRows3 - 1) / kRows3);
+    const int waves = (int)(blockDim.x >> 6);
+    const int64_t chunk = (int64_t)waves * kLaneCols;
+    // per plane block: the ordinary bricks (x-chunk fastest), then the packed
+    // tail bricks, then the tails of the strips not packed (Layout3)
+    const Layout3 Y = layout_3d(L.g, CONS, waves);
+    const uint32_t nxc = (uint32_t)Y.nxc, nyb = (uint32_t)Y.nyb, per_z = (uint32_t)Y.per_z;
+    const uint32_t main = nxc * nyb, npk = (uint32_t)Y.npk, sa = (uint32_t)Y.sa, sb = (uint32_t)Y.sb;
     const uint32_t nzb = (uint32_t)((L.z_own + L.depth - 1) / L.depth);
-    const uint32_t nbricks = nxc * nyb * nzb;
-    for (uint32_t brick = blockIdx.x; brick < nbricks; brick += gridDim.x)
-        run_brick_3d<DT, CONS, WIN, PAIR>(L, P, H, chunk, brick % nxc, (brick / nxc) % nyb, brick / (nxc * nyb),
-                                          wave_id());
+    const uint32_t nbricks = per_z * nzb;
+    for (uint32_t brick = blockIdx.x; brick < nbricks; brick += gridDim.x) {
+        const uint32_t zb = brick / per_z, r = brick - zb * per_z;
+        Brick3 B;
+        if (r < main) {
+            B = chunk_brick_3d<DT, CONS, WIN>(L, H, chunk, r % nxc, r / nxc, zb, wave_id());
+        } else if (r - main < npk) {
+            B = tail_brick_3d<DT, CONS, WIN>(L, H, Y, waves, r - main, zb, wave_id());
+        } else {
+            const uint32_t e = r - main - npk;   // the strips before sa, then those from sb on
+            B = chunk_brick_3d<DT, CONS, WIN>(L, H, chunk, nxc, e < sa ? e : sb + (e - sa), zb, wave_id());
+        }
+        run_brick3<DT, CONS, WIN, PAIR>(L, P, H, B);
+    }
     flush_hist(H, L.partials + (size_t)blockIdx.x * (size_t)L.width, L.width, L.flush_add != 0, L.flush_sign);
     if (L.fused) fused_merge_scan(hist, L.partials, L.width, L.out, L.counter + 1);
 }
@@ -44,7 +58,7 @@ template <int DT, int CONS, bool WIN>
 __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU_2D))) void k_ecc_2d(EccLaunch L)
 {
     extern __shared__ __align__(16) int32_t hist[];
-    const BinParams P = L.params_dev ? *L.params_dev : L.params;
+    const BinParams P = uniform_params<DT>(L.params_dev ? *L.params_dev : L.params);
     const HistRef H = hist_ref(hist, L.bin_lo, L.width, L.hist_stride, L.sentinel, L.hist_copies);
     zero_hist(H, L.width);
     const int64_t chunk = (int64_t)(blockDim.x >> 6) * kLaneCols;
@@ -67,7 +81,7 @@ int64_t wg_bricks(int ndim, int construction, const Geom& g, int waves, int64_t 
     const int64_t chunk = (int64_t)waves * kLaneCols;
     const int64_t nxc = (axis_positions(g.n2, construction) + chunk - 1) / chunk;
     if (ndim == 2) return nxc * ((g.n1 + depth - 1) / depth);
-    return nxc * ((axis_positions(g.n1, construction) + kRows3 - 1) / kRows3) * ((g.n0 + depth - 1) / depth);
+    return layout_3d(g, construction, waves).per_z * ((g.n0 + depth - 1) / depth);
 }
 
 template <class K>

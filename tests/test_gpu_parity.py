@@ -140,6 +140,49 @@ def test_workload_smoothed_3d(ctxs, oracle_mod, cons):
     check(ctxs[cons], oracle_mod, img, 256, cons, threads=16)
 
 
+def _tail(xpos, waves):
+    """Positions left after the full x-chunks of 63 * waves positions."""
+    return xpos - (xpos // (63 * waves)) * 63 * waves
+
+
+@pytest.mark.parametrize("cons", CONS)
+def test_packed_row_tails(oracle_mod, cons):
+    """Rows whose positions leave a narrow tail (1 to 31 positions) after the
+    full x-chunks of a 3D launch: the tail of every strip inside the image runs
+    packed (t + 1 lanes per strip, several strips per wave), the strips at the
+    image's first and last rows as ordinary bricks.  Widths, heights (one to a few
+    strips, partial ones at either end) and forced wave counts cover tails of 1,
+    2, 7, 8, 15, 16 and 31 positions, after one full chunk or in an image
+    narrower than a chunk; every case gives the oracle's ECC."""
+    from paper_2203_09087_amd import ecc
+    rng = np.random.default_rng(78)
+    extra = 1 if cons == "top" else 0   # the top filtration has n + 1 positions
+    ctx = ecc.Context(0, cons)
+    try:
+        # one full chunk and a tail, or (chunks = 0) an image narrower than a chunk
+        for waves, chunks in ((1, 1), (2, 1), (4, 1), (8, 1), (1, 0), (3, 0)):
+            for t in (1, 2, 7, 8, 15, 16, 31):
+                n2 = 63 * waves * chunks + t - extra
+                if n2 < 1:
+                    continue
+                assert _tail(n2 + extra, waves) == t
+                for n1 in (1, 3, 4, 5, 8, 26):
+                    shape = (3, n1, n2)
+                    img = (rng.standard_normal(size=shape).astype(np.float32) if (t + n1) % 2
+                           else rng.integers(0, 9, size=shape).astype(np.uint8))
+                    nbins = 300 if img.dtype == np.float32 else 9
+                    rngv = "auto" if img.dtype == np.float32 else (0, 8)
+                    dev = to_dev(img)
+                    ctx.set_launch_shape(dev, nbins, waves=waves, depth=2, wgs_per_cu=1)
+                    say(f"case: packed tail {cons} waves={waves} t={t} shape={shape} {img.dtype}")
+                    got = ctx.compute(dev, nbins, value_range=rngv)
+                    torch.cuda.synchronize()
+                    want = oracle_mod.ecc(img, nbins, cons, value_range=rngv, threads=8)
+                    assert np.array_equal(got.cpu().numpy(), want), (cons, waves, t, shape)
+    finally:
+        ctx.close()
+
+
 @pytest.fixture(scope="module")
 def grf3d():
     from paper_2203_09087_amd import synth
