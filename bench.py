@@ -61,7 +61,7 @@ COPY_BYTES = 512 << 20
 PROFILES = {
     "3d": {"kernel": "k_ecc_3d", "file": "k_ecc_3d_f32_512cubed", "per_call": 1,
            "what": "512^3 float32 GRF (seed 3), vertex filtration, 4096 bins over [min, max]",
-           "shape": {"waves": 9, "wgs_per_cu": 3, "depth": 32}},
+           "shape": {"waves": 8, "wgs_per_cu": 3, "depth": 32}},
     "2d": {"kernel": "k_ecc_2d", "file": "k_ecc_2d_u16_16384sq", "per_call": 1,
            "what": "16384^2 uint16 GRF (seed 4, 4096 levels), vertex filtration, 4096 bins over [min, max]",
            "shape": {"waves": 4, "wgs_per_cu": 4, "depth": 256}},
@@ -70,10 +70,10 @@ PROFILES = {
               "shape": None},
     "c2": {"kernel": "k_ecc_3d<0, 0, false, false>", "file": "k_ecc_3d_u8_256cubed", "per_call": 1,
            "what": "256^3 uint8 smoothed noise (sigma 2, seed 2), vertex filtration, 256 bins over [0, 255]",
-           "shape": {"waves": 5, "wgs_per_cu": 4, "depth": 16}},
+           "shape": {"waves": 4, "wgs_per_cu": 4, "depth": 16}},
     "minmax": {"kernel": "k_minmax", "file": "k_minmax_f32_512cubed", "per_call": 1,
                "what": "the AUTO-range min/max pass over the 512^3 float32 GRF (seed 3), 4096 bins",
-               "shape": {"waves": 9, "wgs_per_cu": 3, "depth": 32}},
+               "shape": {"waves": 8, "wgs_per_cu": 3, "depth": 32}},
     "smooth": {"kernel": "k_smooth", "file": "k_smooth13_f32_8192sq", "per_call": 2,
                "what": "one 13-tap smoothing pass (rows, then columns) of an 8192^2 float32 GRF (seed 8)",
                "shape": None},

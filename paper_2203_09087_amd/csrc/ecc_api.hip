@@ -1576,6 +1576,11 @@ ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32
             add(def.waves, def.depth * dm / 2, wgs);
             if (def.waves > 4) add((def.waves + 1) / 2, def.depth * dm / 2, wgs);
         }
+    // a 3D row whose default packs its narrow tail (one wave fewer than the
+    // row's chunks, ecc::layout_3d): also one chunk with the tail in its last wave
+    if (shape_job.ndim == 3 && def.waves + 1 == cols && cols <= ECC_MAX_WAVES_3D)
+        for (int wgs : {2, 3, 4})
+            for (int64_t dm : {1, 2}) add((int)cols, def.depth * dm, wgs);
     // the bins-per-pass split: half the window (two passes, half the LDS each)
     // at the default shape and with more workgroups per CU, which the smaller
     // LDS allows
