@@ -461,16 +461,19 @@ __device__ __forceinline__ double uniform_f64(double v)
 // fp64 operations read directly, and leave the vector registers to the brick
 // loop.
 // (Float data only: the integer kernels have fewer vector registers in use and
-// are short of scalar ones.)
+// are short of scalar ones, and take the parameters as they are.)
 template <int DT>
-__device__ __forceinline__ BinParams uniform_params(BinParams p)
+__device__ __forceinline__ BinParams load_params(const EccLaunch& L)
 {
     if constexpr (DT == DT_F32) {
+        BinParams p = L.params_dev ? *L.params_dev : L.params;
         p.nbins = (int32_t)uniform_u32((uint32_t)p.nbins);
         p.base = uniform_f64(p.base);
         p.scale = uniform_f64(p.scale);
+        return p;
+    } else {
+        return L.params_dev ? *L.params_dev : L.params;
     }
-    return p;
 }
 __device__ __forceinline__ const void* uniform_ptr(const void* p) { return (const void*)uniform_i64((int64_t)p); }
 

@@ -24,7 +24,7 @@ template <int DT, int CONS, bool WIN, bool PAIR>
 __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU_3D))) void k_ecc_3d(EccLaunch L)
 {
     extern __shared__ __align__(16) int32_t hist[];
-    const BinParams P = uniform_params<DT>(L.params_dev ? *L.params_dev : L.params);
+    const BinParams P = load_params<DT>(L);
     const HistRef H = hist_ref(hist, L.bin_lo, L.width, L.hist_stride, L.sentinel, L.hist_copies);
     zero_hist(H, L.width);
     const int waves = (int)(blockDim.x >> 6);
@@ -58,7 +58,7 @@ template <int DT, int CONS, bool WIN>
 __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU_2D))) void k_ecc_2d(EccLaunch L)
 {
     extern __shared__ __align__(16) int32_t hist[];
-    const BinParams P = uniform_params<DT>(L.params_dev ? *L.params_dev : L.params);
+    const BinParams P = L.params_dev ? *L.params_dev : L.params;
     const HistRef H = hist_ref(hist, L.bin_lo, L.width, L.hist_stride, L.sentinel, L.hist_copies);
     zero_hist(H, L.width);
     const int64_t chunk = (int64_t)(blockDim.x >> 6) * kLaneCols;
