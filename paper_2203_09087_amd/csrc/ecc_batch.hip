@@ -60,7 +60,7 @@ __global__ __launch_bounds__(kThreads) void k_minmax_batch(const BatchImage* ima
 
 // PAIRS: the launch holds pair volumes (their bricks load two hyperplanes).
 template <int DT, int CONS, bool WIN, bool PAIRS>
-__global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU_3D)))
+__global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(ECC_WAVES_PER_EU_BATCH)))
 void k_ecc_batch(BatchLaunch B)
 {
     extern __shared__ __align__(16) int32_t hist[];
@@ -93,20 +93,34 @@ void k_ecc_batch(BatchLaunch B)
         const int wpb = uniform_u32((uint32_t)I.wpb);
         const int teams = W / wpb, team = wave / wpb, xw = wave - team * wpb;
         const int64_t chunk = kLaneCols * (int64_t)wpb;
-        const uint32_t nxc = uniform_u32((uint32_t)I.nxc), nyb = uniform_u32((uint32_t)I.nyb);
+        const uint32_t nxc = uniform_u32((uint32_t)I.nxc);
         const int64_t b0 = uniform_i64(S.b0), b1 = uniform_i64(S.b1);
-        if (team < teams) {
+        if (team < teams && ndim == 3) {
+            // per plane block: ordinary bricks (x-chunk fastest), packed tail
+            // bricks, the tails of the strips not packed (layout_3d, as k_ecc_3d)
+            const Layout3 Y = layout_3d(L.g, CONS, wpb);
+            const int64_t per_z = Y.per_z, main = Y.nxc * Y.nyb;
             for (int64_t b = b0 + team; b < b1; b += teams) {
                 // brick coordinates from the 64-bit index; each fits 32 bits
+                const int64_t zb = b / per_z, r = b - zb * per_z;
+                Brick3 K;
+                if (r < main) {
+                    K = chunk_brick_3d<DT, CONS, WIN>(L, H, chunk, (uint32_t)(r % nxc), (uint32_t)(r / nxc),
+                                                      (uint32_t)zb, xw);
+                } else if (r - main < Y.npk) {
+                    K = tail_brick_3d<DT, CONS, WIN>(L, H, Y, wpb, (uint32_t)(r - main), (uint32_t)zb, xw);
+                } else {
+                    const int64_t e = r - main - Y.npk;   // the strips before sa, then those from sb on
+                    K = chunk_brick_3d<DT, CONS, WIN>(L, H, chunk, nxc, (uint32_t)(e < Y.sa ? e : Y.sb + (e - Y.sa)),
+                                                      (uint32_t)zb, xw);
+                }
+                if (PAIRS && L.data2) run_brick3<DT, CONS, WIN, true>(L, P, H, K);
+                else run_brick3<DT, CONS, WIN>(L, P, H, K);
+            }
+        } else if (team < teams) {
+            for (int64_t b = b0 + team; b < b1; b += teams) {
                 const int64_t row = b / nxc;
-                const uint32_t xc = (uint32_t)(b - row * nxc);
-                if (PAIRS && L.data2)
-                    run_brick_3d<DT, CONS, WIN, true>(L, P, H, chunk, xc, (uint32_t)(row % nyb), (uint32_t)(row / nyb),
-                                                      xw);
-                else if (ndim == 3)
-                    run_brick_3d<DT, CONS, WIN>(L, P, H, chunk, xc, (uint32_t)(row % nyb), (uint32_t)(row / nyb), xw);
-                else
-                    run_brick_2d<DT, CONS, WIN>(L, P, H, chunk, xc, (uint32_t)row, xw);
+                run_brick_2d<DT, CONS, WIN>(L, P, H, chunk, (uint32_t)(b - row * nxc), (uint32_t)row, xw);
             }
         }
         flush_hist(H, B.partials + (size_t)uniform_u32((uint32_t)S.slot) * (size_t)B.width, B.width, false,
@@ -200,9 +214,13 @@ int64_t batch_bricks(BatchImage& im, int construction, int waves, int depth3, in
     const int64_t chunk = kLaneCols * (int64_t)im.wpb;
     im.nxc = (int32_t)((xpos + chunk - 1) / chunk);
     if (im.ndim == 3) {
+        // the bricks of k_ecc_3d's layout for a workgroup of wpb waves (a narrow
+        // row tail packed several strips per team, layout_3d)
+        const Layout3 Y = layout_3d(im.g, construction, im.wpb);
         im.depth = depth3;
-        im.nyb = (int32_t)((axis_positions(im.g.n1, construction) + kRows3 - 1) / kRows3);
-        return (int64_t)im.nxc * im.nyb * ((im.g.n0 + im.depth - 1) / im.depth);
+        im.nxc = (int32_t)Y.nxc;
+        im.nyb = (int32_t)Y.nyb;
+        return Y.per_z * ((im.g.n0 + im.depth - 1) / im.depth);
     }
     // whole chunks of rows per brick (the 2D brick body steps a chunk at a time)
     im.depth = ((int64_t)(depth2 < 1 ? 1 : depth2) + kChunk2 - 1) / kChunk2 * kChunk2;

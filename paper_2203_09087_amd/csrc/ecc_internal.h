@@ -52,6 +52,9 @@ constexpr int kMaxLdsBins = 4096;
 #ifndef ECC_WAVES_PER_EU_3D
 #define ECC_WAVES_PER_EU_3D 5   // resident waves per SIMD the 3D kernels are compiled for
 #endif
+#ifndef ECC_WAVES_PER_EU_BATCH
+#define ECC_WAVES_PER_EU_BATCH 6   // the batched kernel: at most 80 vector registers, so two 9-wave workgroups fit a CU
+#endif
 #ifndef ECC_WAVES_PER_EU_2D
 #define ECC_WAVES_PER_EU_2D 5   // resident waves per SIMD the 2D kernels are compiled for
 #endif
