@@ -258,10 +258,11 @@ def write_traffic(which, fetch_csv, write_csv):
     lines = [
         f"# HBM traffic per call of the histogram kernel ({spec['kernel']}, {n} dispatch(es) per call):",
         f"# {spec['what']}; counters in KiB per dispatch.",
+        "# $REPO is the repository root, $OUT an output folder.",
         f"command_fetch: cd /tmp && timeout -s KILL 120 rocprofv3 --pmc FETCH_SIZE --output-format csv "
-        f"-d $REPO/gpurun_out/pmc_fetch_{which} -o run -- python3 $REPO/bench.py --traffic {which}",
+        f"-d $OUT/pmc_fetch_{which} -o run -- python3 $REPO/bench.py --traffic {which}",
         f"command_write: cd /tmp && timeout -s KILL 120 rocprofv3 --pmc WRITE_SIZE --output-format csv "
-        f"-d $REPO/gpurun_out/pmc_write_{which} -o run -- python3 $REPO/bench.py --traffic {which}",
+        f"-d $OUT/pmc_write_{which} -o run -- python3 $REPO/bench.py --traffic {which}",
         f"command_summary: python3 bench.py --write-traffic {which} FETCH_CSV WRITE_CSV",
         f"launch_shape: {spec['shape'] or 'default'}",
         f"calibration_kernel: {copy[0]} (the three largest copy dispatches)",
@@ -326,10 +327,10 @@ def write_trace_summary(db_path, bench_json):
     timed = main[-int(res["roofline"]["launches"]):]
     total = sum(sum(v) for v in stats.values())
     out = ["# Kernel trace: 512^3 float32 GRF step (bench.py defaults without side runs)", "",
-           "Commands (on one MI355X, from /tmp, $REPO the repository root):", "",
-           f"    rocprofv3 --kernel-trace --stats -d $REPO/gpurun_out/prof -o run -- python3 $REPO/bench.py "
-           f"--steps {steps} --warmup {res['warmup']} --no-cpu --no-side --no-serve > $REPO/gpurun_out/prof.json",
-           "    python3 $REPO/bench.py --trace-summary $REPO/gpurun_out/prof/run_results.db $REPO/gpurun_out/prof.json", "",
+           "Commands (on one MI355X, from /tmp, $REPO the repository root, $OUT an output folder):", "",
+           f"    rocprofv3 --kernel-trace --stats -d $OUT/prof -o run -- python3 $REPO/bench.py "
+           f"--steps {steps} --warmup {res['warmup']} --no-cpu --no-side --no-serve > $OUT/prof.json",
+           "    python3 $REPO/bench.py --trace-summary $OUT/prof/run_results.db $OUT/prof.json", "",
            f"Histogram kernel `{MAIN_KERNEL}` over the {len(timed)} launches timed with kernel events "
            f"(launch shape {res.get('launch_shape')}): mean {np.mean(timed):.2f} us, "
            f"min {np.min(timed):.2f} us, max {np.max(timed):.2f} us.  The benchmark's own HIP-event "
@@ -389,13 +390,13 @@ def write_sq_summary(which, csv_a, csv_b):
     esize = {"3d": 4, "2d": 2, "4d": 4, "batch": 1, "c2": 1, "minmax": 4, "smooth": 16}[which]
     kvox = alg / esize / 1000.0
     out = [f"# SQ counters: `{spec['kernel']}`, {spec['what']}", "",
-           "Commands (one pass each, from /tmp, $REPO the repository root):", "",
-           f"    timeout -s KILL 120 rocprofv3 --pmc {SQ_A} --output-format csv -d $REPO/gpurun_out/sqa_{which} "
+           "Commands (one pass each, from /tmp, $REPO the repository root, $OUT an output folder):", "",
+           f"    timeout -s KILL 120 rocprofv3 --pmc {SQ_A} --output-format csv -d $OUT/sqa_{which} "
            f"-o run -- python3 $REPO/bench.py --traffic {which}",
-           f"    timeout -s KILL 120 rocprofv3 --pmc {SQ_B} --output-format csv -d $REPO/gpurun_out/sqb_{which} "
+           f"    timeout -s KILL 120 rocprofv3 --pmc {SQ_B} --output-format csv -d $OUT/sqb_{which} "
            f"-o run -- python3 $REPO/bench.py --traffic {which}",
-           f"    python3 $REPO/bench.py --sq-summary {which} $REPO/gpurun_out/sqa_{which}/run_counter_collection.csv "
-           f"$REPO/gpurun_out/sqb_{which}/run_counter_collection.csv", "",
+           f"    python3 $REPO/bench.py --sq-summary {which} $OUT/sqa_{which}/run_counter_collection.csv "
+           f"$OUT/sqb_{which}/run_counter_collection.csv", "",
            f"Dispatch: grid {meta.get('Grid_Size')} work-items, workgroup {meta.get('Workgroup_Size')}, "
            f"LDS {meta.get('LDS_Block_Size')} B, scratch {meta.get('Scratch_Size')} B; launch shape "
            f"{spec['shape'] or 'default'}.  Values per call ({n} dispatch(es)), means over the last three calls.", "",

@@ -70,7 +70,7 @@ typedef struct ecc_ctx ecc_ctx;
 typedef enum {
     ECC_OK = 0,
     ECC_ERR_INVALID_ARG = 1,   /* a null pointer, a bad size, range or enum value */
-    ECC_ERR_UNSUPPORTED = 2,   /* a valid request this build cannot serve */
+    ECC_ERR_UNSUPPORTED = 2,   /* a valid request the library does not serve */
     ECC_ERR_OUT_OF_MEMORY = 3, /* device scratch memory could not be allocated */
     ECC_ERR_DEVICE = 4         /* a HIP runtime call failed */
 } ecc_status;
