@@ -230,8 +230,10 @@ typedef struct {
     int32_t copies;
 } ecc_launch_shape;
 
-/* Times a set of launch shapes for the image `img` on hip_stream (`reps` calls
- * each, after one warm-up; the calls overwrite img->out) and makes `ctx` use the
+/* Times a set of launch shapes for the image `img` on hip_stream (after about
+ * 40 ms of calls at the default shape, which bring the device's clocks up: two
+ * rounds over the shapes, `reps` calls per shape and round, the faster round
+ * counting; the calls overwrite img->out) and makes `ctx` use the
  * fastest for every later call on an image with the same ndim, dims (for 4 or
  * more dimensions: the last three), dtype and filtration and nbins on the same
  * side of 4096.  Every shape gives the same

@@ -1581,6 +1581,29 @@ ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32
     if (shape_job.ndim == 3 && def.waves + 1 == cols && cols <= ECC_MAX_WAVES_3D)
         for (int wgs : {2, 3, 4})
             for (int64_t dm : {1, 2}) add((int)cols, def.depth * dm, wgs);
+    // 3D: for each workgroup count, the plane depth (between half and twice the
+    // default) whose bricks split most evenly over the workgroups: the slowest
+    // workgroup walks ceil(bricks / grid) bricks of depth planes plus about one
+    // and a half planes of start-up each
+    if (shape_job.ndim == 3) {
+        const int64_t per_z = ecc::layout_3d(shape_job.g, ctx->construction, def.waves).per_z;
+        const int resident = ecc::resident_wgs_per_cu(3, j.dtype, ctx->construction, def.window < nbins, def.waves,
+                                                      def.lds_bytes);
+        for (int wgs : {2, 3, 4}) {
+            const int64_t grid = (int64_t)ctx->cu_count * std::min(wgs, resident);
+            int64_t best_d = def.depth;
+            double best_cost = HUGE_VAL;
+            for (int64_t d = std::max<int64_t>(4, def.depth / 2); d <= 2 * def.depth; ++d) {
+                const int64_t bricks = per_z * ((shape_job.g.n0 + d - 1) / d);
+                const double cost = (double)((bricks + grid - 1) / grid) * ((double)d + 1.5);
+                if (cost < best_cost) {
+                    best_cost = cost;
+                    best_d = d;
+                }
+            }
+            add(def.waves, best_d, wgs);
+        }
+    }
     // the bins-per-pass split: half the window (two passes, half the LDS each)
     // at the default shape and with more workgroups per CU, which the smaller
     // LDS allows
@@ -1595,22 +1618,43 @@ ecc_status ecc_autotune(ecc_ctx* ctx, const ecc_image* img, int32_t nbins, int32
         if (e0) (void)hipEventDestroy(e0);
         return hip_fail(ctx, e, "hipEventCreate(autotune)");
     }
-    ecc_launch_shape best = cand[0];
-    best.ms = HUGE_VAL;
-    for (auto& c : cand) {
-        if ((st = run(&c)) != ECC_OK) break;   // warm-up, sizes the scratch
-        if ((e = hipEventRecord(e0, stream)) != hipSuccess) { st = hip_fail(ctx, e, "hipEventRecord"); break; }
-        for (int r = 0; r < reps && st == ECC_OK; ++r) st = run(&c);
-        if (st != ECC_OK) break;
-        if ((e = hipEventRecord(e1, stream)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) {
-            st = hip_fail(ctx, e, "hipEventSynchronize(autotune)");
-            break;
-        }
+    // Times `n` calls of shape c on the stream, in milliseconds per call.
+    auto timed = [&](const ecc_launch_shape& c, int n, double* ms_per_call) -> ecc_status {
+        ecc_status r = ECC_OK;
+        if ((e = hipEventRecord(e0, stream)) != hipSuccess) return hip_fail(ctx, e, "hipEventRecord");
+        for (int k = 0; k < n && r == ECC_OK; ++k) r = run(&c);
+        if (r != ECC_OK) return r;
+        if ((e = hipEventRecord(e1, stream)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess)
+            return hip_fail(ctx, e, "hipEventSynchronize(autotune)");
         float ms = 0.f;
-        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { st = hip_fail(ctx, e, "hipEventElapsedTime"); break; }
-        c.ms = ms / reps;
-        if (c.ms < best.ms) best = c;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return hip_fail(ctx, e, "hipEventElapsedTime");
+        *ms_per_call = ms / n;
+        return ECC_OK;
+    };
+    // The device's clocks rise over the first tenths of a second of load, which
+    // would favour the candidates timed last: the default shape runs first
+    // until 40 ms of calls (at most 400) have passed; then every candidate is
+    // timed in two rounds (one warm-up call each the first time) and keeps the
+    // faster of its two times.
+    {
+        double ms = 0.0, total = 0.0;
+        for (int k = 0; k < 100 && total < 40.0 && st == ECC_OK; ++k) {
+            st = timed(cand[0], 4, &ms);
+            total += 4.0 * ms;
+        }
     }
+    for (auto& c : cand) c.ms = HUGE_VAL;
+    for (int round = 0; round < 2 && st == ECC_OK; ++round) {
+        for (auto& c : cand) {
+            if (round == 0 && (st = run(&c)) != ECC_OK) break;   // warm-up, sizes the scratch
+            double ms = 0.0;
+            if ((st = timed(c, reps, &ms)) != ECC_OK) break;
+            c.ms = std::min(c.ms, ms);
+        }
+    }
+    ecc_launch_shape best = cand[0];
+    for (const auto& c : cand)
+        if (c.ms < best.ms) best = c;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != ECC_OK) return st;
