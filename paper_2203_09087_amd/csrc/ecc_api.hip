@@ -176,6 +176,10 @@ struct Job {
     ecc::Geom g;          // 2D/3D: the image; 4D and up: the last three axes
     int64_t nw;           // 4D and up: dims[ndim-4] (hyperplanes of a 4D part); else 1
     int64_t dims[ECC_MAX_NDIM];
+    // 3D passes of a 4D part: npass volumes of this shape, pass_stride bytes
+    // apart, counted by one launch (EccLaunch::npass)
+    int32_t npass = 1;
+    int64_t pass_stride = 0;
     int64_t nvox;
     double lo, hi;
     int64_t* out;
@@ -492,6 +496,8 @@ ecc_status enqueue_hist(ecc_ctx* ctx, char* base, const Job& j, int32_t nbins, h
     L.z_own = z_own;
     L.z_base = z_base;
     L.n0_global = n0_global;
+    L.npass = j.npass;
+    L.pass_stride = j.pass_stride;
     L.partials = (int32_t*)(base + sz.off_partials);
     L.flush_add = pass_add ? 1 : 0;
     L.flush_sign = sign;
@@ -514,7 +520,8 @@ ecc_status enqueue_hist(ecc_ctx* ctx, char* base, const Job& j, int32_t nbins, h
     }
     L.flush_add = 0;
     L.flush_sign = 1;
-    if (!accumulate && scan && sign > 0 && sz.window >= nbins && (int64_t)L.grid * nbins <= ecc::kFusedMergeWords) {
+    if (!accumulate && scan && sign > 0 && L.npass == 1 && sz.window >= nbins &&
+        (int64_t)L.grid * nbins <= ecc::kFusedMergeWords) {
         // few rows: the histogram kernel's last workgroup merges and scans them
         L.bin_lo = 0;
         L.width = nbins;
@@ -529,7 +536,7 @@ ecc_status enqueue_hist(ecc_ctx* ctx, char* base, const Job& j, int32_t nbins, h
         const bool last = b0 + L.width >= nbins;
         if ((e = timed_launch(ctx, launch_l)) != hipSuccess)
             return hip_fail(ctx, e, "ecc launch");
-        if ((e = ecc::launch_merge(L.partials, L.grid, L.width, L.bin_lo, (int64_t*)(base + sz.off_level2),
+        if ((e = ecc::launch_merge(L.partials, L.grid * L.npass, L.width, L.bin_lo, (int64_t*)(base + sz.off_level2),
                                    j.out, nbins, counters, accumulate, scan && last, sign, stream)) != hipSuccess)
             return hip_fail(ctx, e, "merge launch");
     }
@@ -581,36 +588,80 @@ ecc_status enqueue_4d_part(ecc_ctx* ctx, char* base, const Sizes& sz, Job h, con
     const int64_t hv = h.nvox;
     const size_t esize = h.dtype == ECC_U8 ? 1 : (h.dtype == ECC_U16 ? 2 : 4);
     const bool vertex = ctx->construction == ECC_VERTEX;
-    // the passes in order: hyperplane w (sign c_w, skipped when 0), then the
-    // pair (w, w+1); counted first, then enqueued (no host allocation)
-    auto single_sign = [&](int64_t w) { return vertex ? 1 : -1 + (w == 0) + (w == nw - 1); };
-    int64_t npasses = 0;
-    for (int64_t w = 0; w < nw; ++w) npasses += (single_sign(w) != 0) + (w + 1 < nw);
     auto plane = [&](int64_t w) { return (const void*)(img4 + (size_t)w * (size_t)hv * esize); };
-    // With one LDS window the passes add into the same workgroup rows and one
-    // merge follows, when the int32 rows cannot overflow: a workgroup sees at
-    // most ceil(bricks / grid) bricks of chunk x rows x depth voxels per pass, and
-    // a voxel adds at most 8 in absolute value.
-    const int64_t bricks = ecc::wg_bricks(3, ctx->construction, h.g, sz.waves, sz.depth);
-    const int64_t per_wg = (bricks + sz.grid - 1) / sz.grid * ecc::kLaneCols * sz.waves * ecc::kRows3 * sz.depth;
-    const bool one_merge = sz.window >= nbins && npasses * per_wg < (int64_t(1) << 28);
-    ecc_status st;
-    int64_t k = 0;
-    for (int64_t w = 0; w < nw; ++w) {
-        for (int pair = 0; pair < 2; ++pair) {
-            const int sign = pair ? (vertex ? -1 : 1) : single_sign(w);
-            if (sign == 0 || (pair && w + 1 >= nw)) continue;
-            h.data = plane(w);
-            h.data2 = pair ? plane(w + 1) : nullptr;
-            if ((st = enqueue_hist(ctx, base, h, nbins, stream, sz, pdev, h.g.n0, 0, h.g.n0, !first || k > 0,
-                                   last && k + 1 == npasses, sign * outer, one_merge, k > 0)) != ECC_OK)
-                return st;
-            ++k;
-        }
+    // The passes in groups of one sign and kind, each a run of hyperplanes (or
+    // of pairs (w, w+1)) one hyperplane apart, the largest group first:
+    //   vertex: hyperplanes 0 .. nw-1 (+), pairs 0 .. nw-2 (-);
+    //   top:    pairs 0 .. nw-2 (+), interior hyperplanes 1 .. nw-2 (-) (the
+    //           end ones have c_w = 0), or the one hyperplane of nw = 1 (+).
+    struct Group {
+        int64_t w0, count;
+        int sign;
+        bool pair;
+    } groups[2];
+    int ng = 0;
+    if (vertex) {
+        groups[ng++] = {0, nw, 1, false};
+        if (nw > 1) groups[ng++] = {0, nw - 1, -1, true};
+    } else if (nw == 1) {
+        groups[ng++] = {0, 1, 1, false};
+    } else {
+        groups[ng++] = {0, nw - 1, 1, true};
+        if (nw > 2) groups[ng++] = {1, nw - 2, -1, false};
     }
+    // A group runs as launches of c passes each (EccLaunch::npass), gx
+    // workgroups per pass: the first launch's gx * c rows (at most the buffer's
+    // sz.grid) cover the rows of every later launch, which add into them.
+    int64_t rows = sz.grid;
+    auto for_launches = [&](auto&& fn) -> ecc_status {
+        int64_t cap = sz.grid;
+        bool first_launch = true;
+        for (int g = 0; g < ng; ++g) {
+            for (int64_t done = 0; done < groups[g].count;) {
+                const int64_t c = std::min<int64_t>(groups[g].count - done, cap);
+                const int64_t gx = std::max<int64_t>(1, cap / c);
+                if (first_launch) {
+                    cap = rows = gx * c;
+                    first_launch = false;
+                }
+                const ecc_status r = fn(groups[g].w0 + done, c, groups[g].sign, groups[g].pair, gx);
+                if (r != ECC_OK) return r;
+                done += c;
+            }
+        }
+        return ECC_OK;
+    };
+    // With one LDS window every launch adds into the same workgroup rows and one
+    // merge follows, when the int32 rows cannot overflow: a row's workgroup sees
+    // at most ceil(bricks / gx) bricks of chunk x rows x depth voxels per
+    // launch, and a voxel adds at most 8 in absolute value.
+    const int64_t bricks = ecc::wg_bricks(3, ctx->construction, h.g, sz.waves, sz.depth);
+    const int64_t brick_vox = ecc::kLaneCols * sz.waves * ecc::kRows3 * sz.depth;
+    int64_t nlaunch = 0, per_row = 0;
+    for_launches([&](int64_t, int64_t, int, bool, int64_t gx) {
+        ++nlaunch;
+        per_row += (bricks + gx - 1) / gx * brick_vox;
+        return ECC_OK;
+    });
+    const bool one_merge = sz.window >= nbins && per_row < (int64_t(1) << 28);
+    int64_t k = 0;
+    ecc_status st = for_launches([&](int64_t w0, int64_t c, int sign, bool pair, int64_t gx) {
+        Job p = h;
+        p.data = plane(w0);
+        p.data2 = pair ? plane(w0 + 1) : nullptr;
+        p.npass = (int32_t)c;
+        p.pass_stride = (int64_t)hv * (int64_t)esize;
+        Sizes s = sz;
+        s.grid = (int)gx;
+        const ecc_status r = enqueue_hist(ctx, base, p, nbins, stream, s, pdev, h.g.n0, 0, h.g.n0, !first || k > 0,
+                                          last && k + 1 == nlaunch, sign * outer, one_merge, k > 0);
+        ++k;
+        return r;
+    });
+    if (st != ECC_OK) return st;
     if (one_merge) {
         uint32_t* counters = (uint32_t*)(base + sz.off_counters);
-        const hipError_t e = ecc::launch_merge((int32_t*)(base + sz.off_partials), sz.grid, nbins, 0,
+        const hipError_t e = ecc::launch_merge((int32_t*)(base + sz.off_partials), (int)rows, nbins, 0,
                                                (int64_t*)(base + sz.off_level2), h.out, nbins, counters, !first,
                                                last, 1, stream);
         if (e != hipSuccess) return hip_fail(ctx, e, "merge launch");

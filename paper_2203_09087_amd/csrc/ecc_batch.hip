@@ -85,6 +85,7 @@ void k_ecc_batch(BatchLaunch B)
         L.depth = uniform_i64(I.depth);
         L.z_own = L.g.n0;
         L.z_base = 0;
+        L.pass_stride = 0;
         L.n0_global = L.g.n0;
         const int ndim = (int)uniform_u32((uint32_t)I.ndim);
         zero_hist(H, B.width);

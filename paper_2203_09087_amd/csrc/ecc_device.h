@@ -344,7 +344,8 @@ __device__ __forceinline__ int64_t wave_scan(int64_t v)
 __device__ __forceinline__ void fused_merge_scan(int32_t* hist, const int32_t* partials, int width, int64_t* out,
                                                  uint32_t* counter)
 {
-    if (!last_to_arrive(counter, gridDim.x)) return;
+    const uint32_t rows = gridDim.x * gridDim.y;
+    if (!last_to_arrive(counter, rows)) return;
     __shared__ int64_t wave_tot[kMaxWaves];
     const int bd = (int)blockDim.x, t = (int)threadIdx.x;
     uint64_t* acc = reinterpret_cast<uint64_t*>(hist);
@@ -353,7 +354,7 @@ __device__ __forceinline__ void fused_merge_scan(int32_t* hist, const int32_t* p
     // the rows as one flat array, 16 loads in flight per thread; element i adds
     // to bin i mod width (tracked incrementally)
     constexpr int U = 16;
-    const int64_t total = (int64_t)gridDim.x * width;
+    const int64_t total = (int64_t)rows * width;
     const int step = bd % width;
     int j = t % width;
     for (int64_t i0 = t; i0 < total; i0 += (int64_t)bd * U) {
@@ -541,8 +542,10 @@ __device__ __forceinline__ void brick_3d(const EccLaunch& L, const BinParams& P,
     const uint32_t n0 = (uint32_t)L.g.n0;
     const int64_t n1 = L.g.n1, n2 = L.g.n2;
     const uint32_t row_bytes = (uint32_t)(n2 * (int64_t)sizeof(T));
-    const char* img = (const char*)L.data;
-    const char* img2 = (const char*)L.data2;
+    // the launch's pass (one volume of several of the same shape, pass_stride apart)
+    const int64_t pass_off = (int64_t)blockIdx.y * L.pass_stride;
+    const char* img = (const char*)L.data + pass_off;
+    const char* img2 = PAIR ? (const char*)L.data2 + pass_off : nullptr;
     // first row read: ys, or the first row inside the image
     const int64_t ybase = ys + (FULL ? 0 : r_lo);
     constexpr int NR2 = PAIR ? NR + 1 : 1;

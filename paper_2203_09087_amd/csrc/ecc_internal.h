@@ -189,7 +189,12 @@ struct EccLaunch {
     // plane 0 is plane z_base of a volume of n0_global planes.  A whole image
     // has z_own = g.n0, z_base = 0, n0_global = g.n0.
     int64_t z_own, z_base, n0_global;
-    int32_t* partials;             // [grid][width] workgroup histograms
+    // Several passes of the same shape in one launch (3D): workgroup row y of
+    // the grid (grid x npass workgroups) counts the volume at data (and data2)
+    // plus y * pass_stride bytes; its histograms go to partial rows y * grid ..
+    int32_t npass;
+    int64_t pass_stride;
+    int32_t* partials;             // [grid * npass][width] workgroup histograms
     int32_t flush_add;             // add the workgroup histogram to its partial row (else write it)
     int32_t flush_sign;            // +1, or -1: the histogram enters its row negated
     int64_t* out;                  // the caller's output

@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kMaxWaves * 64) __attribute__((amdgpu_waves_per_eu(
         }
         run_brick3<DT, CONS, WIN, PAIR>(L, P, H, B);
     }
-    flush_hist(H, L.partials + (size_t)blockIdx.x * (size_t)L.width, L.width, L.flush_add != 0, L.flush_sign);
+    flush_hist(H, L.partials + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * (size_t)L.width, L.width, L.flush_add != 0, L.flush_sign);
     if (L.fused) fused_merge_scan(hist, L.partials, L.width, L.out, L.counter + 1);
 }
 
@@ -87,10 +87,11 @@ int64_t wg_bricks(int ndim, int construction, const Geom& g, int waves, int64_t 
 template <class K>
 static hipError_t launch_k(K kernel, const EccLaunch& L, hipStream_t s, hipEvent_t t0, hipEvent_t t1)
 {
+    const dim3 grid((unsigned)L.grid, (unsigned)(L.npass > 1 ? L.npass : 1));
     if (t0 || t1)
-        hipExtLaunchKernelGGL(kernel, dim3(L.grid), dim3(L.waves * 64), L.lds_bytes, s, t0, t1, 0, L);
+        hipExtLaunchKernelGGL(kernel, grid, dim3(L.waves * 64), L.lds_bytes, s, t0, t1, 0, L);
     else
-        hipLaunchKernelGGL(kernel, dim3(L.grid), dim3(L.waves * 64), L.lds_bytes, s, L);
+        hipLaunchKernelGGL(kernel, grid, dim3(L.waves * 64), L.lds_bytes, s, L);
     return hipGetLastError();
 }
 
