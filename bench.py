@@ -77,9 +77,10 @@ PROFILES = {
     "smooth": {"kernel": "k_smooth", "file": "k_smooth13_f32_8192sq", "per_call": 2,
                "what": "one 13-tap smoothing pass (rows, then columns) of an 8192^2 float32 GRF (seed 8)",
                "shape": None},
-    "4d": {"kernel": "k_ecc_3d<2, 0, false, true>", "file": "k_ecc_3d_pair_f32_8x256cubed", "per_call": 7,
-           "what": "the 7 pair passes (elementwise max of two neighbouring 256^3 hyperplanes) of one call on the "
-                   "8 x 256^3 float32 GRF (seed 9), vertex filtration, 4096 bins over [min, max]",
+    "4d": {"kernel": "k_ecc_3d<2, 0, false, true>", "file": "k_ecc_3d_pair_f32_8x256cubed", "per_call": 1,
+           "what": "the launch of the 7 pair terms (elementwise max of two neighbouring 256^3 hyperplanes, one "
+                   "term per workgroup row of the grid) of one call on the 8 x 256^3 float32 GRF (seed 9), "
+                   "vertex filtration, 4096 bins over [min, max]",
            "shape": None},
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", PROFILES["3d"]["file"] + "_traffic.txt")
@@ -300,7 +301,7 @@ def _alg_bytes(which):
     if which == "c2":
         return 256 ** 3
     if which == "4d":
-        return 7 * 2 * 256 ** 3 * 4   # each pair pass reads two hyperplanes
+        return 7 * 2 * 256 ** 3 * 4   # each of the 7 pair terms reads two hyperplanes
     from paper_2203_09087_amd import synth
     return int(sum(int(np.prod(s)) for s in synth.batch_shapes(count=512, seed=5)))
 
