@@ -183,6 +183,48 @@ def test_packed_row_tails(oracle_mod, cons):
         ctx.close()
 
 
+def test_random_shapes_and_launch_shapes(oracle_mod):
+    """Seeded random 3D and 4D images (widths around every tail length, few to
+    many rows and planes, every dtype, both filtrations, narrow and windowed
+    histograms) at random forced launch shapes (waves, workgroups per CU,
+    depth, histogram copies) against the oracle."""
+    from paper_2203_09087_amd import ecc
+    rng = np.random.default_rng(2024)
+    ctxs_ = {c: ecc.Context(0, c) for c in CONS}
+    try:
+        for case in range(48):
+            cons = CONS[case % 2]
+            ndim = 4 if case % 6 == 5 else 3
+            n2 = int(rng.integers(1, 600))
+            n1 = int(rng.integers(1, 40))
+            n0 = int(rng.integers(1, 7))
+            shape = ((int(rng.integers(1, 4)),) if ndim == 4 else ()) + (n0, n1, n2)
+            kind = int(rng.integers(0, 3))
+            if kind == 0:
+                img = rng.integers(0, 256, size=shape).astype(np.uint8)
+            elif kind == 1:
+                img = rng.integers(0, 5000, size=shape).astype(np.uint16)
+            else:
+                img = rng.standard_normal(size=shape).astype(np.float32)
+            nbins = int(rng.choice([1, 7, 256, 4096, 5000]))
+            rngv = None if kind == 0 else "auto"
+            waves = int(rng.integers(1, 10))
+            wgs = int(rng.integers(1, 5))
+            depth = int(rng.choice([1, 2, 5, 16]))
+            copies = int(rng.choice([0, 2, 4, 8])) if nbins <= 1024 else 0
+            ctx = ctxs_[cons]
+            dev = to_dev(img)
+            ctx.set_launch_shape(dev, nbins, waves=waves, wgs_per_cu=wgs, depth=depth, copies=copies)
+            say(f"case {case}: {cons} shape={shape} {img.dtype} nbins={nbins} shape=({waves},{wgs},{depth},{copies})")
+            got = ctx.compute(dev, nbins, value_range=rngv)
+            torch.cuda.synchronize()
+            want = oracle_mod.ecc(img, nbins, cons, value_range=rngv, threads=8)
+            assert np.array_equal(got.cpu().numpy(), want), (case, cons, shape, img.dtype, nbins, waves, wgs, depth)
+    finally:
+        for c in ctxs_.values():
+            c.close()
+
+
 @pytest.fixture(scope="module")
 def grf3d():
     from paper_2203_09087_amd import synth
