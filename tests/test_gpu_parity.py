@@ -192,7 +192,7 @@ def test_random_shapes_and_launch_shapes(oracle_mod):
     rng = np.random.default_rng(2024)
     ctxs_ = {c: ecc.Context(0, c) for c in CONS}
     try:
-        for case in range(48):
+        for case in range(144):
             cons = CONS[case % 2]
             ndim = 4 if case % 6 == 5 else 3
             n2 = int(rng.integers(1, 600))
