@@ -949,22 +949,16 @@ __device__ __forceinline__ void run_brick3(const EccLaunch& L, const BinParams& 
     constexpr int NR = kRows3;
     if (!B.active) return;
     const bool full = B.r_lo == 0 && B.r_hi == NR + 1;
+    const int64_t ys = B.ys;
+    const uint32_t z0 = B.z0, ze = B.zend, xob = B.xob, oob = B.oob;
+    const uint64_t own = B.own;
     if (DT != DT_F32 && uniform_flag(P.ident)) {
-        if (full) brick_3d<DT, CONS, WIN, true, true, PAIR>(L, P, H, B.ys, B.z0, B.zend, B.xob, B.oob, B.own, B.r_lo, B.r_hi);
-        else brick_3d<DT, CONS, WIN, false, true, PAIR>(L, P, H, B.ys, B.z0, B.zend, B.xob, B.oob, B.own, B.r_lo, B.r_hi);
+        if (full) brick_3d<DT, CONS, WIN, true, true, PAIR>(L, P, H, ys, z0, ze, xob, oob, own, B.r_lo, B.r_hi);
+        else brick_3d<DT, CONS, WIN, false, true, PAIR>(L, P, H, ys, z0, ze, xob, oob, own, B.r_lo, B.r_hi);
     } else {
-        if (full) brick_3d<DT, CONS, WIN, true, false, PAIR>(L, P, H, B.ys, B.z0, B.zend, B.xob, B.oob, B.own, B.r_lo, B.r_hi);
-        else brick_3d<DT, CONS, WIN, false, false, PAIR>(L, P, H, B.ys, B.z0, B.zend, B.xob, B.oob, B.own, B.r_lo, B.r_hi);
+        if (full) brick_3d<DT, CONS, WIN, true, false, PAIR>(L, P, H, ys, z0, ze, xob, oob, own, B.r_lo, B.r_hi);
+        else brick_3d<DT, CONS, WIN, false, false, PAIR>(L, P, H, ys, z0, ze, xob, oob, own, B.r_lo, B.r_hi);
     }
-}
-
-// One ordinary 3D workgroup brick (x-chunk xc, strip yb, plane block zb) for
-// this wave (`xw`: its place among the waves of the brick).
-template <int DT, int CONS, bool WIN, bool PAIR = false>
-__device__ __forceinline__ void run_brick_3d(const EccLaunch& L, const BinParams& P, const HistRef& H,
-                                             int64_t chunk, uint32_t xc, uint32_t yb, uint32_t zb, int xw)
-{
-    run_brick3<DT, CONS, WIN, PAIR>(L, P, H, chunk_brick_3d<DT, CONS, WIN>(L, H, chunk, xc, yb, zb, xw));
 }
 
 // One 2D workgroup brick (x-chunk xc, row block yb) for this wave.
