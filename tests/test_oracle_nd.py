@@ -1,4 +1,4 @@
-"""Pins for the oracle in five and six dimensions (the definitions of Sec. 2.1
+"""Pins for the oracle in five to eight dimensions (the definitions of Sec. 2.1
 and the VCEC of Sec. 2.3 are the same in every dimension).
 
 Each check reaches its expected value without the oracle's code: the naive
@@ -96,6 +96,14 @@ def test_closed_forms_nd(oracle_mod, cons, d):
     b = np.full((3, 2) + (2,) * (d - 2), 4, dtype=np.int32)
     b[(2, 1) + (0,) * (d - 2)] = 1
     assert np.array_equal(_ecc(oracle_mod, b, 6, cons), np.array([0, 1, 1, 1, 1, 1]))
+
+
+@pytest.mark.parametrize("cons", CONS)
+def test_naive_recount_7d(oracle_mod, cons):
+    """Seven dimensions, five of them two voxels long."""
+    rng = np.random.default_rng(96 + (cons == "top"))
+    b = rng.integers(0, 2, size=(2, 2, 1, 2, 1, 2, 2)).astype(np.int32)
+    assert np.array_equal(_ecc(oracle_mod, b, 2, cons), pins.brute_ecc(b, 2, cons))
 
 
 def test_largest_dimension_and_beyond(oracle_mod):
