@@ -108,6 +108,11 @@ class Server:
         """Queues a request that has arrived (its ``t_arrival`` is already set).  Its
         source may still be being written by work on the current stream."""
         src = req.source
+        # what a batch takes (a bad request would fail the whole batch it joins)
+        if not 2 <= src.dim() <= 4:
+            raise ValueError(f"requests are 2D to 4D images (got {src.dim()} dimensions)")
+        if not 1 <= req.nbins <= 65535:
+            raise ValueError(f"nbins must be in [1, 65535] (got {req.nbins})")
         req.nbytes = src.numel() * src.element_size() + 8 * req.nbins
         if req.nbytes > self.budget:
             raise ValueError(f"request of {req.nbytes} bytes exceeds the budget of {self.budget}")

@@ -157,3 +157,34 @@ def test_sources_written_on_another_stream(oracle_mod):
             assert np.array_equal(r.out.cpu().numpy(), want), i
     finally:
         srv.close()
+
+
+def test_bad_requests_are_refused_at_submit(oracle_mod):
+    """A request the batch call would refuse (a 5D image, nbins out of range) is
+    refused when submitted, so it cannot fail the batch it would have joined;
+    a 4D request is served like the others."""
+    from paper_2203_09087_amd import serve
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import time
+    say("case: serving refuses bad requests, serves a 4D one")
+    srv = serve.Server(budget_bytes=1 << 28, max_batch=4, lanes=1)
+    try:
+        five = torch.zeros((2, 2, 3, 4, 5), dtype=torch.uint8, device="cuda")
+        with pytest.raises(ValueError):
+            srv.submit(serve.Request(source=five, nbins=16))
+        one = torch.zeros((7,), dtype=torch.uint8, device="cuda")
+        with pytest.raises(ValueError):
+            srv.submit(serve.Request(source=one, nbins=16))
+        with pytest.raises(ValueError):
+            srv.submit(serve.Request(source=torch.zeros((4, 4), dtype=torch.uint8, device="cuda"), nbins=0))
+        rng = np.random.default_rng(9)
+        img = rng.integers(0, 256, size=(3, 5, 6, 70)).astype(np.uint8)
+        r = serve.Request(source=torch.from_numpy(img).cuda(), nbins=256)
+        r.t_arrival = time.perf_counter()
+        srv.submit(r)
+        srv.drain()
+        torch.cuda.synchronize()
+        assert np.array_equal(r.out.cpu().numpy(), oracle_mod.ecc(img, 256, "vertex"))
+    finally:
+        srv.close()
