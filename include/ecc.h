@@ -37,9 +37,9 @@
  *   - Images are DEVICE pointers, contiguous, row-major, dims[0] slowest.  Any
  *     alignment is accepted.  ndim is 2 to ECC_MAX_NDIM (see ecc_compute for
  *     images of 4 or more dimensions); entry points that do not take a
- *     dimension return ECC_ERR_UNSUPPORTED for it: ecc_compute_streamed takes 2
- *     and 3, the batch calls, plans and ecc_compute_noalloc 2 to 4.  Every dim
- *     is >= 1.
+ *     dimension return ECC_ERR_UNSUPPORTED for it: the batch calls, plans,
+ *     ecc_compute_noalloc and ecc_compute_streamed take 2 to 4.  Every dim is
+ *     >= 1.
  *   - `out` is a DEVICE pointer to nbins int64 values, overwritten (not
  *     accumulated) with the ECC.  1 <= nbins <= 65535.
  *   - Every call validates all of its arguments on the host before anything is
@@ -192,8 +192,10 @@ ecc_status ecc_compute_batch(ecc_ctx* ctx, const ecc_image* imgs, int32_t count,
  * counted on hip_stream; the slab VCECs add up exactly, since every cell is
  * counted by the slab that owns its first-axis start.  img->data is a HOST
  * pointer (pinned memory copies fastest, pageable memory works), img->out a
- * device pointer.  A 2D image travels as one slab.  An AUTO range reads the
- * volume twice (min/max first).  Asynchronous: the host image must stay
+ * device pointer.  A 2D image travels as one slab.  A 4D image streams in
+ * slabs of hyperplanes (its first axis), each with the hyperplane after it,
+ * a slab counting the signed 3D terms of its own hyperplanes (as ecc_compute).
+ * An AUTO range reads the volume twice (min/max first).  Asynchronous: the host image must stay
  * unchanged until hip_stream has completed the call.  Two device slab buffers
  * are kept by the context.  Results are identical to ecc_compute_ex.
  * Errors: as ecc_compute_ex, plus ECC_ERR_INVALID_ARG for slab_planes < 0. */

@@ -583,32 +583,41 @@ ecc_status enqueue_one(ecc_ctx* ctx, const Job& j, int32_t nbins, hipStream_t st
 // to it, and the last one scans it.
 ecc_status enqueue_4d_part(ecc_ctx* ctx, char* base, const Sizes& sz, Job h, const char* img4, int64_t nw,
                            const ecc::BinParams* pdev, int32_t nbins, hipStream_t stream, int outer, bool first,
-                           bool last)
+                           bool last, int64_t w_first = 0, int64_t nw_all = -1, int64_t n_own = -1)
 {
+    // img4 holds hyperplanes w_first .. of a 4D image of nw_all hyperplanes (all
+    // nw of them unless a streamed slab); the terms of its own n_own hyperplanes
+    // are counted (a pair term (w, w+1) belongs to w; the hyperplane after the
+    // own ones, when held, completes the last pair).
+    if (nw_all < 0) nw_all = nw;
+    if (n_own < 0) n_own = nw;
     const int64_t hv = h.nvox;
     const size_t esize = h.dtype == ECC_U8 ? 1 : (h.dtype == ECC_U16 ? 2 : 4);
     const bool vertex = ctx->construction == ECC_VERTEX;
     auto plane = [&](int64_t w) { return (const void*)(img4 + (size_t)w * (size_t)hv * esize); };
-    // The passes in groups of one sign and kind, each a run of hyperplanes (or
+    // The terms in groups of one sign and kind, each a run of hyperplanes (or
     // of pairs (w, w+1)) one hyperplane apart, the largest group first:
-    //   vertex: hyperplanes 0 .. nw-1 (+), pairs 0 .. nw-2 (-);
-    //   top:    pairs 0 .. nw-2 (+), interior hyperplanes 1 .. nw-2 (-) (the
-    //           end ones have c_w = 0), or the one hyperplane of nw = 1 (+).
+    //   vertex: hyperplanes (+), pairs (-);
+    //   top:    pairs (+), interior hyperplanes (-) (the end ones have
+    //           c_w = 0), or the one hyperplane of a single-hyperplane image (+).
     struct Group {
-        int64_t w0, count;
+        int64_t w0, count;   // w0: index in img4
         int sign;
         bool pair;
     } groups[2];
     int ng = 0;
+    const int64_t npairs = std::max<int64_t>(0, std::min<int64_t>(n_own, nw_all - 1 - w_first));
     if (vertex) {
-        groups[ng++] = {0, nw, 1, false};
-        if (nw > 1) groups[ng++] = {0, nw - 1, -1, true};
-    } else if (nw == 1) {
+        groups[ng++] = {0, n_own, 1, false};
+        if (npairs > 0) groups[ng++] = {0, npairs, -1, true};
+    } else if (nw_all == 1) {
         groups[ng++] = {0, 1, 1, false};
     } else {
-        groups[ng++] = {0, nw - 1, 1, true};
-        if (nw > 2) groups[ng++] = {1, nw - 2, -1, false};
+        if (npairs > 0) groups[ng++] = {0, npairs, 1, true};
+        const int64_t a = std::max<int64_t>(w_first, 1), b = std::min<int64_t>(w_first + n_own, nw_all - 1);
+        if (b > a) groups[ng++] = {a - w_first, b - a, -1, false};
     }
+    if (ng == 2 && groups[1].count > groups[0].count) std::swap(groups[0], groups[1]);
     // A group runs as launches of c passes each (EccLaunch::npass), gx
     // workgroups per pass: the first launch's gx * c rows (at most the buffer's
     // sz.grid) cover the rows of every later launch, which add into them.
@@ -1088,20 +1097,33 @@ ecc_status stream_copy(ecc_ctx* ctx, const char* host, size_t plane_bytes, int64
 
 ecc_status enqueue_streamed(ecc_ctx* ctx, const Job& vol, int32_t nbins, int64_t slab_planes, hipStream_t stream)
 {
-    const int64_t N = vol.g.n0;
+    // A 4D image streams in slabs of hyperplanes (its first axis) the same way
+    // a 3D one streams in slabs of planes; each slab counts the 3D terms of its
+    // own hyperplanes (enqueue_4d_part), the hyperplane after them completing
+    // the last pair.
+    const bool four = vol.ndim == 4;
+    const int64_t N = four ? vol.nw : vol.g.n0;
     const size_t esize = vol.dtype == ECC_U8 ? 1 : (vol.dtype == ECC_U16 ? 2 : 4);
-    const size_t plane_bytes = (size_t)(vol.g.n1 * vol.g.n2) * esize;
+    const int64_t plane_vox = four ? vol.g.n0 * vol.g.n1 * vol.g.n2 : vol.g.n1 * vol.g.n2;
+    const size_t plane_bytes = (size_t)plane_vox * esize;
     int64_t S = slab_planes;
     if (S <= 0) S = std::max<int64_t>(1, (int64_t)((size_t)256 << 20) / (int64_t)plane_bytes);
     S = std::min<int64_t>(S, N);
     const int64_t nslabs = (N + S - 1) / S;
     ecc_status st = ensure_streaming(ctx, (size_t)(std::min<int64_t>(S + 1, N)) * plane_bytes);
     if (st != ECC_OK) return st;
-    // one scratch size for every slab (the first is the largest), fixed before
-    // anything is enqueued so that no slab reallocates it
+    // one scratch size for every slab (the first is the largest; for a 4D
+    // image, that of its hyperplanes' 3D terms), fixed before anything is
+    // enqueued so that no slab reallocates it
     Job first = vol;
-    first.g.n0 = std::min<int64_t>(S + 1, N);
-    first.nvox = first.g.n0 * vol.g.n1 * vol.g.n2;
+    if (four) {
+        first.ndim = 3;
+        first.nw = 1;
+        first.nvox = plane_vox;
+    } else {
+        first.g.n0 = std::min<int64_t>(S + 1, N);
+        first.nvox = first.g.n0 * vol.g.n1 * vol.g.n2;
+    }
     const Sizes sz = plan_sizes(ctx, first, nbins);
     if ((st = ensure_ws(ctx, sz.total)) != ECC_OK) return st;
     hipError_t e;
@@ -1123,7 +1145,7 @@ ecc_status enqueue_streamed(ecc_ctx* ctx, const Job& vol, int32_t nbins, int64_t
             if ((st = stream_copy(ctx, host, plane_bytes, z0, n, b)) != ECC_OK) return st;
             if ((e = hipStreamWaitEvent(stream, ctx->copied[b], 0)) != hipSuccess)
                 return hip_fail(ctx, e, "hipStreamWaitEvent(compute)");
-            const int64_t nv = n * vol.g.n1 * vol.g.n2;
+            const int64_t nv = n * plane_vox;
             const int blocks = (int)std::min<int64_t>(kMinmaxBlocks, (nv + 4095) / 4096);
             if ((e = ecc::launch_minmax(ctx->slab_buf[b], vol.dtype, nv, mm, blocks, stream)) != hipSuccess ||
                 (e = ecc::launch_mm_fold(mm, blocks, acc, k == 0, stream)) != hipSuccess)
@@ -1135,14 +1157,39 @@ ecc_status enqueue_streamed(ecc_ctx* ctx, const Job& vol, int32_t nbins, int64_t
             return hip_fail(ctx, e, "params launch");
     }
     // pass 2: slab k counts its own planes [k*S, k*S + n) and reads one collar
-    // plane beyond them (the plane its last plane pairs with)
+    // plane beyond them (the plane its last plane pairs with).  A 4D slab may
+    // own no term (the top filtration's last hyperplane has c_w = 0 and no
+    // pair): it is skipped, and the first and last slabs with terms write and
+    // scan the output.
+    auto has_terms = [&](int64_t z0, int64_t n) {
+        if (!four || ctx->construction == ECC_VERTEX || N == 1) return true;
+        const int64_t pairs = std::min<int64_t>(n, N - 1 - z0);
+        return pairs > 0 || std::min<int64_t>(z0 + n, N - 1) > std::max<int64_t>(z0, 1);
+    };
+    int64_t k_first = -1, k_last = -1;
+    for (int64_t k = 0; k < nslabs; ++k)
+        if (has_terms(k * S, std::min<int64_t>(S, N - k * S))) {
+            if (k_first < 0) k_first = k;
+            k_last = k;
+        }
     for (int64_t k = 0; k < nslabs; ++k) {
         const int b = (int)(k & 1);
         const int64_t z0 = k * S, n = std::min<int64_t>(S, N - z0);
         const int64_t loaded = std::min<int64_t>(n + 1, N - z0);
+        if (four && !has_terms(z0, n)) continue;
         if ((st = stream_copy(ctx, host, plane_bytes, z0, loaded, b)) != ECC_OK) return st;
         if ((e = hipStreamWaitEvent(stream, ctx->copied[b], 0)) != hipSuccess)
             return hip_fail(ctx, e, "hipStreamWaitEvent(compute)");
+        if (four) {
+            Job h = first;
+            h.data = nullptr;
+            if ((st = enqueue_4d_part(ctx, base, sz, h, (const char*)ctx->slab_buf[b], loaded, pdev, nbins, stream,
+                                      1, k == k_first, k == k_last, z0, N, n)) != ECC_OK)
+                return st;
+            if ((e = hipEventRecord(ctx->consumed[b], stream)) != hipSuccess)
+                return hip_fail(ctx, e, "hipEventRecord(consumed)");
+            continue;
+        }
         Job slab = vol;
         slab.data = ctx->slab_buf[b];
         slab.g.n0 = loaded;
@@ -1722,7 +1769,7 @@ ecc_status ecc_compute_streamed(ecc_ctx* ctx, const ecc_image* img, int32_t nbin
     if (!img) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_compute_streamed: null descriptor");
     if (slab_planes < 0) return fail(ctx, ECC_ERR_INVALID_ARG, "ecc_compute_streamed: negative slab_planes");
     Job j;
-    ecc_status st = validate(ctx, *img, nbins, "ecc_compute_streamed", &j, 3);
+    ecc_status st = validate(ctx, *img, nbins, "ecc_compute_streamed", &j, 4);
     if (st != ECC_OK) return st;
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, ECC_ERR_DEVICE, "hipSetDevice failed");

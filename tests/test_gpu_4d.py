@@ -177,9 +177,32 @@ def test_4d_benchmark_field_in_batch(ctxs, oracle_mod, cons):
     assert np.array_equal(out.cpu().numpy(), want)
 
 
-def test_4d_is_rejected_where_unsupported(ctxs):
+@pytest.mark.parametrize("cons", CONS)
+def test_4d_streamed_from_host(ctxs, oracle_mod, cons):
+    """A 4D image in host memory streamed in slabs of 1, 2 and 3 hyperplanes (and
+    the default): each slab counts the terms of its own hyperplanes, the one
+    after them completing the last pair; every dtype, AUTO and explicit ranges,
+    single-hyperplane and two-hyperplane images (the top filtration's last slab
+    then owns no term)."""
+    rng = np.random.default_rng(123 + CONS.index(cons))
+    cases = [((5, 6, 9, 70), np.float32, "auto", 300), ((4, 3, 5, 130), np.uint16, "auto", 5000),
+             ((2, 4, 6, 40), np.uint8, None, 256), ((1, 5, 5, 66), np.float32, (-1.0, 1.0), 64),
+             ((7, 2, 3, 20), np.uint8, (3, 200), 17)]
+    for shape, dt, rngv, nbins in cases:
+        img = (rng.standard_normal(size=shape).astype(np.float32) if dt == np.float32
+               else rng.integers(0, 6000 if dt == np.uint16 else 256, size=shape).astype(dt))
+        host = torch.from_numpy(img.view(np.int16) if dt == np.uint16 else img).pin_memory()
+        want = oracle_mod.ecc(img, nbins, cons, value_range=rngv, threads=8)
+        for slab in (1, 2, 3, 0):
+            say(f"case: 4d streamed {cons} shape={shape} {img.dtype} nbins={nbins} slab={slab}")
+            got = ctxs[cons].compute_streamed(host, nbins, value_range=rngv, slab_planes=slab)
+            torch.cuda.synchronize()
+            assert np.array_equal(got.cpu().numpy(), want), (cons, shape, slab)
+
+
+def test_5d_streaming_is_refused(ctxs):
     from paper_2203_09087_amd import ecc
-    img = torch.zeros((2, 3, 4, 5), dtype=torch.uint8)
+    img = torch.zeros((2, 2, 3, 4, 5), dtype=torch.uint8)
     with pytest.raises(ecc.EccError) as e:
         ctxs["vertex"].compute_streamed(img, 16)
     assert e.value.status == ecc.ECC_ERR_UNSUPPORTED
