@@ -550,8 +550,11 @@ __device__ __forceinline__ void brick_3d(const EccLaunch& L, const BinParams& P,
     const int64_t ybase = ys + (FULL ? 0 : r_lo);
     constexpr int NR2 = PAIR ? NR + 1 : 1;
 
+    // the brick's first row in plane 0, and the bytes from plane to plane
+    const int64_t first_row = ybase * (int64_t)row_bytes;
+    const int64_t plane_bytes = n1 * (int64_t)row_bytes;
     auto load_plane = [&](uint32_t z, T (&raw)[NR + 1], T (&raw2)[NR2]) {
-        const int64_t off = ((int64_t)z * n1 + ybase) * (int64_t)row_bytes;
+        const int64_t off = first_row + (int64_t)z * plane_bytes;
         const __amdgpu_buffer_rsrc_t rs = rsrc_at(img + off);
         __amdgpu_buffer_rsrc_t rs2 = rs;
         if constexpr (PAIR) rs2 = rsrc_at(img2 + off);
